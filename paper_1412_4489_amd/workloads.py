@@ -1,0 +1,427 @@
+"""Seeded synthetic workloads (initial data) shaped like the paper's tests.
+
+This module only builds inputs: problem descriptions, initial cell averages
+and initial interface point values, plus the exact solutions the paper uses
+for its accuracy tables.  It contains none of the scheme's arithmetic and is
+shared by the HIP path's tests, the oracle's tests and the benchmark.
+
+Workloads (Sec. 4 of Pan & Xu, arXiv:1412.4489):
+  * advection_1d     -- density advection, Sec. 4.1 (Table 1)
+  * vortex_2d        -- isentropic vortex, Sec. 4.1 (Table 2), on [0,10]^2
+  * sod_1d / blast_1d -- Sec. 4.2
+  * riemann_2d       -- 2D Riemann problems, Sec. 4.3 (cases 1, 2)
+  * dmr              -- double Mach reflection, Sec. 4.5
+  * cavity           -- lid-driven cavity, Sec. 4.8
+  * batch            -- many independent vortex / Riemann grids of uneven size
+
+Initial point values are the exact initial data at the interface Gauss points
+(2D: tangential offsets -+ sqrt(3)/6 of the cell width; 1D: the interface);
+where a discontinuity lies on an interface the mean of the two adjacent states
+is used.  Cell averages use tensor Gauss-Legendre quadrature (smooth data) or
+sub-cell sampling (discontinuous data).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+import math
+
+import numpy as np
+
+BC_KINDS = ("periodic", "outflow", "reflect", "noslip_iso", "noslip_adia",
+            "inflow", "dmr_bottom", "dmr_top")
+
+
+@dataclass
+class BC:
+    kind: str = "periodic"
+    state: tuple = (0.0, 0.0, 0.0, 0.0)   # primitive (rho, u, v, p)
+    alt: tuple = (0.0, 0.0, 0.0, 0.0)     # second primitive state (DMR pre-shock)
+    wall: tuple = (0.0, 0.0, 0.0)         # wall (u, v, T)
+
+
+@dataclass
+class Problem:
+    dim: int
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    gamma: float = 1.4
+    viscous: bool = False
+    mu: float = 0.0
+    prandtl: float = 1.0
+    tau_eps: float = 0.05
+    tau_c: float = 1.0
+    cfl: float = 0.2
+    weno_eps: float = 1e-6
+    weno_c: float = 1.0
+    recon_vars: int = 0
+    bc: list = field(default_factory=lambda: [BC(), BC(), BC(), BC()])
+    t_end: float = 0.0
+    name: str = ""
+
+    @property
+    def nvar(self) -> int:
+        return self.dim + 2
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y1 - self.y0) / self.ny if self.dim == 2 else 1.0
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny
+
+
+@dataclass
+class State:
+    """Host arrays (float64, no ghosts):
+    cell[nvar][ny][nx]; fx[ng][nvar][ny][nx+1]; fy[2][nvar][ny+1][nx] (2D)."""
+    cell: np.ndarray
+    fx: np.ndarray
+    fy: np.ndarray
+
+    def copy(self) -> "State":
+        return State(self.cell.copy(), self.fx.copy(), self.fy.copy())
+
+
+GAUSS_OFFSET = math.sqrt(3.0) / 6.0
+
+
+def cons(gamma, rho, u, v, p, dim=2):
+    """Conservative variables from primitive ones (stacked on axis 0)."""
+    rho, u, v, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, u, v, p)))
+    if dim == 2:
+        return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def _gl(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return x, w / 2.0
+
+
+def _cell_average_2d(fun, prob: Problem, nq=4):
+    """Tensor Gauss-Legendre average of fun(x, y) -> (nvar, ...) over each cell."""
+    xq, wq = _gl(nq)
+    h, k = prob.dx, prob.dy
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * h
+    yc = prob.y0 + (np.arange(prob.ny) + 0.5) * k
+    acc = np.zeros((prob.nvar, prob.ny, prob.nx))
+    for a in range(nq):
+        for b in range(nq):
+            X = xc[None, :] + 0.5 * h * xq[a]
+            Y = yc[:, None] + 0.5 * k * xq[b]
+            X, Y = np.broadcast_arrays(X, Y)
+            acc += wq[a] * wq[b] * fun(X, Y)
+    return acc
+
+
+def _face_values_2d(fun, prob: Problem):
+    h, k = prob.dx, prob.dy
+    xf = prob.x0 + np.arange(prob.nx + 1) * h
+    yc = prob.y0 + (np.arange(prob.ny) + 0.5) * k
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * h
+    yf = prob.y0 + np.arange(prob.ny + 1) * k
+    fx = np.zeros((2, prob.nvar, prob.ny, prob.nx + 1))
+    fy = np.zeros((2, prob.nvar, prob.ny + 1, prob.nx))
+    for g, s in enumerate((-GAUSS_OFFSET, GAUSS_OFFSET)):
+        X, Y = np.broadcast_arrays(xf[None, :], (yc + s * k)[:, None])
+        fx[g] = fun(X, Y)
+        X, Y = np.broadcast_arrays((xc + s * h)[None, :], yf[:, None])
+        fy[g] = fun(X, Y)
+    return fx, fy
+
+
+# --------------------------------------------------------------------------
+# 1D
+# --------------------------------------------------------------------------
+
+def advection_1d(n=100, cfl=0.5, t_end=2.0, tau_eps=0.0):
+    """Sec. 4.1: rho = 1 + 0.2 sin(pi x), u = 1, p = 1, periodic [0, 2].
+
+    Reading for the smooth accuracy tests: tau = tau_eps dt + |jump| dt with
+    tau_eps = 0 (the printed 0.05 dt adds a heat conduction far above the
+    errors of Table 1)."""
+    g = 1.4
+    prob = Problem(dim=1, nx=n, ny=1, x0=0.0, x1=2.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=tau_eps, tau_c=1.0, cfl=cfl, t_end=t_end,
+                   name=f"advection1d_{n}")
+    h = prob.dx
+    xl = np.arange(n) * h
+    xr = xl + h
+    rho_avg = 1.0 + 0.2 * (np.cos(math.pi * xl) - np.cos(math.pi * xr)) / (math.pi * h)
+    cell = cons(g, rho_avg, 1.0, 0.0, 1.0, dim=1)
+    # rho u and rho E are linear in rho here, so their averages are exact too
+    xf = np.arange(n + 1) * h
+    fx = cons(g, 1.0 + 0.2 * np.sin(math.pi * xf), 1.0, 0.0, 1.0, dim=1)
+    st = State(cell.reshape(3, 1, n), fx.reshape(1, 3, 1, n + 1), np.zeros((2, 3, 2, n)))
+    return prob, st
+
+
+def advection_1d_exact_average(n, t):
+    h = 2.0 / n
+    xl = np.arange(n) * h - t
+    xr = xl + h
+    return 1.0 + 0.2 * (np.cos(math.pi * xl) - np.cos(math.pi * xr)) / (math.pi * h)
+
+
+def _piecewise_1d(n, x0, x1, breaks, states, g, nsub=64):
+    """states: list of primitive (rho, u, p) on the intervals split by breaks."""
+    h = (x1 - x0) / n
+    W = [cons(g, s[0], s[1], 0.0, s[2], dim=1) for s in states]
+
+    def at(x):
+        idx = np.searchsorted(np.asarray(breaks), x, side="right")
+        return np.stack([W[i] for i in np.atleast_1d(idx)], axis=-1)
+
+    cell = np.zeros((3, n))
+    sub = (np.arange(nsub) + 0.5) / nsub
+    for i in range(n):
+        xs = x0 + (i + sub) * h
+        cell[:, i] = at(xs).mean(axis=1)
+    xf = x0 + np.arange(n + 1) * h
+    fx = at(xf)
+    for b in breaks:  # a discontinuity on an interface: mean of both states
+        on = np.isclose(xf, b, rtol=0, atol=1e-12 * max(1.0, abs(b)))
+        for fi in np.nonzero(on)[0]:
+            lo = at(np.array([b - 1e-9 * h]))[:, 0]
+            hi = at(np.array([b + 1e-9 * h]))[:, 0]
+            fx[:, fi] = 0.5 * (lo + hi)
+    return cell, fx
+
+
+def sod_1d(n=100, t_end=0.2, recon_vars=1):
+    """Sec. 4.2 Sod problem on [0, 1]."""
+    g = 1.4
+    prob = Problem(dim=1, nx=n, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars,
+                   bc=[BC("outflow"), BC("outflow"), BC(), BC()], name=f"sod1d_{n}")
+    cell, fx = _piecewise_1d(n, 0.0, 1.0, [0.5], [(1.0, 0.0, 1.0), (0.125, 0.0, 0.1)], g)
+    return prob, State(cell.reshape(3, 1, n), fx.reshape(1, 3, 1, n + 1), np.zeros((2, 3, 2, n)))
+
+
+def blast_1d(n=400, t_end=3.8, recon_vars=1):
+    """Sec. 4.2 Woodward-Colella blast wave on [0, 100], reflecting ends."""
+    g = 1.4
+    prob = Problem(dim=1, nx=n, ny=1, x0=0.0, x1=100.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars,
+                   bc=[BC("reflect"), BC("reflect"), BC(), BC()], name=f"blast1d_{n}")
+    cell, fx = _piecewise_1d(n, 0.0, 100.0, [10.0, 90.0],
+                             [(1.0, 0.0, 1000.0), (1.0, 0.0, 0.01), (1.0, 0.0, 100.0)], g)
+    return prob, State(cell.reshape(3, 1, n), fx.reshape(1, 3, 1, n + 1), np.zeros((2, 3, 2, n)))
+
+
+# --------------------------------------------------------------------------
+# 2D
+# --------------------------------------------------------------------------
+
+def _vortex_fields(X, Y, g, eps, xc, yc):
+    dxp, dyp = X - xc, Y - yc
+    r2 = dxp * dxp + dyp * dyp
+    du = eps / (2 * math.pi) * np.exp(0.5 * (1.0 - r2)) * (-dyp)
+    dv = eps / (2 * math.pi) * np.exp(0.5 * (1.0 - r2)) * dxp
+    T = 1.0 - (g - 1.0) * eps * eps / (8.0 * g * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (g - 1.0))
+    return rho, 1.0 + du, 1.0 + dv, rho * T
+
+
+def vortex_2d(n=256, t_end=10.0, eps=5.0, cfl=0.2, nq=4, tau_eps=0.0, ny=None):
+    """Sec. 4.1 isentropic vortex: mean (rho, u, v, p) = (1, 1, 1, 1), strength
+    5, on the periodic square [0, 10]^2 with the vortex centred at (5, 5)."""
+    g = 1.4
+    ny = n if ny is None else ny
+    prob = Problem(dim=2, nx=n, ny=ny, x0=0.0, x1=10.0, y0=0.0, y1=10.0, gamma=g,
+                   tau_eps=tau_eps, tau_c=1.0, cfl=cfl, t_end=t_end, name=f"vortex2d_{n}")
+
+    def fun(X, Y):
+        return cons(g, *_vortex_fields(X, Y, g, eps, 5.0, 5.0))
+
+    cell = _cell_average_2d(fun, prob, nq=nq)
+    fx, fy = _face_values_2d(fun, prob)
+    return prob, State(cell, fx, fy)
+
+
+def vortex_2d_exact_density(prob: Problem, t, eps=5.0, nq=6):
+    """Exact cell-average density at time t: the initial vortex carried by the
+    mean flow (1, 1); the nearest periodic image of its centre is used."""
+    L = prob.x1 - prob.x0
+    xc = prob.x0 + ((5.0 + t) - prob.x0) % L
+    yc = prob.y0 + ((5.0 + t) - prob.y0) % L
+
+    def fun(X, Y):
+        dX = (X - xc + 0.5 * L) % L - 0.5 * L
+        dY = (Y - yc + 0.5 * L) % L - 0.5 * L
+        rho, *_ = _vortex_fields(dX, dY, prob.gamma, eps, 0.0, 0.0)
+        return np.stack([rho] * prob.nvar)
+
+    return _cell_average_2d(fun, prob, nq=nq)[0]
+
+
+def _piecewise_2d(prob: Problem, state_at, nsub=8):
+    """Cell averages by nsub x nsub sub-cell midpoints; point values exact
+    (mean of the two sides where the point lies on a discontinuity is left to
+    state_at)."""
+    h, k = prob.dx, prob.dy
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * h
+    yc = prob.y0 + (np.arange(prob.ny) + 0.5) * k
+    sub = (np.arange(nsub) + 0.5) / nsub - 0.5
+    acc = np.zeros((prob.nvar, prob.ny, prob.nx))
+    for a in sub:
+        for b in sub:
+            X, Y = np.broadcast_arrays(xc[None, :] + a * h, yc[:, None] + b * k)
+            acc += state_at(X, Y)
+    cell = acc / (nsub * nsub)
+    fx, fy = _face_values_2d(state_at, prob)
+    return cell, fx, fy
+
+
+RIEMANN_CASES = {
+    # (rho, u, v, p) in quadrants NE, NW, SW, SE (Sec. 4.3)
+    1: [(0.5313, 0.0, 0.0, 0.4), (1.0, 0.7276, 0.0, 1.0), (0.8, 0.0, 0.0, 1.0), (1.0, 0.0, 0.7276, 1.0)],
+    2: [(1.0, 0.75, -0.5, 1.0), (2.0, 0.75, 0.5, 1.0), (1.0, -0.75, 0.5, 1.0), (3.0, -0.75, -0.5, 1.0)],
+}
+
+
+def riemann_2d(case=1, n=200, t_end=0.2, nx=None, ny=None):
+    """Sec. 4.3: quadrant Riemann problems on [0, 1]^2, non-reflecting
+    (zero-gradient) boundaries."""
+    g = 1.4
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end,
+                   bc=[BC("outflow") for _ in range(4)], name=f"riemann{case}_{nx}x{ny}")
+    Q = np.stack([cons(g, *s) for s in RIEMANN_CASES[case]])
+
+    def raw(X, Y):
+        east, north = X > 0.5, Y > 0.5
+        quad = np.where(north, np.where(east, 0, 1), np.where(east, 3, 2))
+        return np.moveaxis(Q[quad], -1, 0)
+
+    def state_at(X, Y):
+        # mean over four tiny offsets: the exact state off the discontinuity
+        # lines, the mean of the adjacent states on them
+        d = 1e-9
+        return 0.25 * sum(raw(X + sx, Y + sy) for sx in (-d, d) for sy in (-d, d))
+
+    cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
+DMR_POST = (8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5)
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+
+
+def dmr(nx=1920, ny=480, t_end=0.2):
+    """Sec. 4.5 double Mach reflection on [0, 4] x [0, 1]: a Mach 10 shock
+    through (1/6, 0) at 60 degrees; post-shock inflow at the left edge and on
+    the bottom for x < 1/6, slip wall beyond, exact shock motion on top,
+    zero-gradient outflow on the right."""
+    g = 1.4
+    bc = [BC("inflow", state=DMR_POST), BC("outflow"),
+          BC("dmr_bottom", state=DMR_POST), BC("dmr_top", state=DMR_POST, alt=DMR_PRE)]
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, bc=bc, name=f"dmr_{nx}x{ny}")
+    post, pre = cons(g, *DMR_POST), cons(g, *DMR_PRE)
+    s3 = math.sqrt(3.0)
+
+    def state_at(X, Y):
+        behind = X < 1.0 / 6.0 + Y / s3
+        out = np.where(behind[None], post.reshape(4, *([1] * X.ndim)), pre.reshape(4, *([1] * X.ndim)))
+        return out
+
+    cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
+def cavity(n=512, re=1000.0, mach=0.15, prandtl=0.72, gamma=5.0 / 3.0, lid_transits=20.0):
+    """Sec. 4.8 lid-driven cavity on [0, 1]^2: gas at rest (rho = 1, T = 1),
+    isothermal no-slip walls at T = 1, lid velocity Ma * sqrt(gamma) on top;
+    constant mu = U_lid / Re."""
+    g = gamma
+    ulid = mach * math.sqrt(g)
+    mu = ulid / re
+    bc = [BC("noslip_iso", wall=(0.0, 0.0, 1.0)), BC("noslip_iso", wall=(0.0, 0.0, 1.0)),
+          BC("noslip_iso", wall=(0.0, 0.0, 1.0)), BC("noslip_iso", wall=(ulid, 0.0, 1.0))]
+    prob = Problem(dim=2, nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=g, viscous=True,
+                   mu=mu, prandtl=prandtl, tau_eps=0.0, tau_c=1.0, cfl=0.2,
+                   t_end=lid_transits / ulid, bc=bc, name=f"cavity_{n}_re{int(re)}")
+    cell = np.zeros((4, n, n))
+    cell[:] = cons(g, 1.0, 0.0, 0.0, 1.0)[:, None, None]
+    fx = np.broadcast_to(cell[:, :, :1], (4, n, n + 1))[None].repeat(2, axis=0).copy()
+    fy = np.broadcast_to(cell[:, :1, :], (4, n + 1, n))[None].repeat(2, axis=0).copy()
+    return prob, State(cell, fx, fy)
+
+
+def uniform_2d(nx=16, ny=12, state=(1.3, 0.4, -0.7, 2.1), gamma=1.4, bc="periodic", **kw):
+    """Free stream: one uniform state everywhere."""
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=0.75, gamma=gamma,
+                   bc=[BC(bc) for _ in range(4)], name="uniform", **kw)
+    q = cons(gamma, *state)
+    cell = np.broadcast_to(q[:, None, None], (4, ny, nx)).copy()
+    fx = np.broadcast_to(q[None, :, None, None], (2, 4, ny, nx + 1)).copy()
+    fy = np.broadcast_to(q[None, :, None, None], (2, 4, ny + 1, nx)).copy()
+    return prob, State(cell, fx, fy)
+
+
+def smooth_periodic_2d(nx=24, ny=20, seed=0, amp=0.1, gamma=1.4, viscous=False, mu=0.0,
+                       prandtl=1.0, tau_eps=0.05, lx=1.0, ly=1.0):
+    """A seeded smooth periodic flow: low-mode Fourier perturbations of a
+    uniform state in rho, u, v, p (for parity and conservation tests)."""
+    rng = np.random.default_rng(seed)
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=lx, y0=0.0, y1=ly, gamma=gamma,
+                   viscous=viscous, mu=mu, prandtl=prandtl, tau_eps=tau_eps,
+                   name=f"smooth_{nx}x{ny}_s{seed}")
+    base = np.array([1.0, 0.3, -0.2, 1.0])
+    modes = []
+    for q in range(4):
+        for _ in range(3):
+            kx, ky = rng.integers(0, 3, size=2)
+            a, ph = rng.uniform(-amp, amp), rng.uniform(0, 2 * math.pi)
+            modes.append((q, kx, ky, a, ph))
+
+    def fun(X, Y):
+        prim = [np.full(X.shape, base[q]) for q in range(4)]
+        for q, kx, ky, a, ph in modes:
+            prim[q] = prim[q] + a * np.sin(2 * math.pi * (kx * X / lx + ky * Y / ly) + ph)
+        return cons(gamma, *prim)
+
+    cell = _cell_average_2d(fun, prob, nq=4)
+    fx, fy = _face_values_2d(fun, prob)
+    return prob, State(cell, fx, fy)
+
+
+def random_perturbed_2d(nx=24, ny=20, seed=0, amp=0.2, gamma=1.4, bc="periodic", **kw):
+    """Seeded rough data: a uniform state with independent random cell and
+    point-value perturbations (exercises every limiter branch)."""
+    rng = np.random.default_rng(seed)
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=ny / nx,
+                   gamma=gamma, bc=[BC(bc) for _ in range(4)], name=f"rough_{nx}x{ny}_s{seed}", **kw)
+
+    def draw(shape):
+        rho = 1.0 + amp * rng.uniform(-1, 1, shape)
+        u = 0.5 * amp * rng.uniform(-1, 1, shape) + 0.2
+        v = 0.5 * amp * rng.uniform(-1, 1, shape) - 0.1
+        p = 1.0 + amp * rng.uniform(-1, 1, shape)
+        return cons(gamma, rho, u, v, p)
+
+    cell = draw((ny, nx))
+    fx = np.stack([draw((ny, nx + 1)), draw((ny, nx + 1))], axis=0)
+    fy = np.stack([draw((ny + 1, nx)), draw((ny + 1, nx))], axis=0)
+    if bc == "periodic":  # the first and last interfaces are the same interface
+        fx[..., nx] = fx[..., 0]
+        fy[..., ny, :] = fy[..., 0, :]
+    return prob, State(np.ascontiguousarray(cell), np.ascontiguousarray(fx), np.ascontiguousarray(fy))
+
+
+def state_for(prob: Problem, cell, fx, fy=None) -> State:
+    if fy is None:
+        fy = np.zeros((2, prob.nvar, prob.ny + 1, prob.nx))
+    return State(cell, fx, fy)
