@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the compact third-order gas-kinetic scheme on one MI355X.
+
+Workload: the 2D isentropic vortex of Sec. 4.1 (Table 2) on the periodic
+square [0, 10]^2 with 256 x 256 cells, gamma = 1.4, CFL 0.2 (time step from
+the CFL condition on the device every step), synthetic initial data.
+
+A step is one pass of the whole scheme: boundary images, CFL time step,
+compact reconstruction, every x and y interface (flux and point values),
+conservative update.  The state stays resident in HBM; W untimed warm-up
+steps, then K timed steps bracketed by device synchronisation.
+
+Printed: one JSON line.  value = Mcell-updates/s of the GKS_FP32_MIXED form
+(the headline form); the GKS_FP64 form is reported beside it.  The dominant
+kernel (the interface kernel) is timed live with HIP events on the stream it
+runs on; `roofline` prices its algorithmic floating-point operations (the
+straight-line operation count of the generated interface arithmetic plus the
+double-precision prologue) against the vector ALU peak.  `cpu_baseline` times
+the FP64 oracle on this host for a bounded number of steps of the same
+workload; the same steps on the GPU give the L1 difference to the oracle.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+N = 256
+PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
+PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
+# double-precision work per interface outside the generated functions
+# (interface values, primitives, half-space moments, U0, equilibrium
+# quadratic, collision time, time integrals, frame transforms, leading terms)
+PROLOGUE_FLOPS = 1000
+
+
+def interface_flops(viscous=False):
+    ops = json.load(open(os.path.join(ROOT, "paper_1412_4489_amd", "csrc", "interface_ops.json")))
+    side = "ns" if viscous else "euler"
+    return (ops["coef_g0_2d"] + ops["hydro_2d"] + 2 * ops[f"coef_side_{side}_2d"] + 2 * ops[f"kin_{side}_2d"]
+            + PROLOGUE_FLOPS)
+
+
+def run_gpu(precision, steps, warmup):
+    import torch
+    from paper_1412_4489_amd import gks
+    from paper_1412_4489_amd import workloads as W
+
+    prob, st = W.vortex_2d(N)
+    stream = torch.cuda.current_stream().cuda_stream
+    S = gks.Solver(prob, st, precision, stream=stream)
+    S.step(warmup)
+    torch.cuda.synchronize()
+    gks.gks_profile(S.h, 1)
+    gks.gks_profile(S.h, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gks.gks_profile(S.h, 0)
+    kt = {k: gks.gks_kernel_time(S.h, k) for k in gks.KERNELS}
+    S.fetch()  # raises if the run produced a nonphysical state
+    S.close()
+    # the profiled run records events around every launch; time it again
+    # without events for the wall-clock figure
+    S = gks.Solver(prob, st, precision, stream=stream)
+    S.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    S.fetch()
+    S.close()
+    return min(wall, wall_plain), kt, prob
+
+
+def gpu_fixed_steps(precision, nsteps, dt):
+    from paper_1412_4489_amd import gks
+    from paper_1412_4489_amd import workloads as W
+    prob, st = W.vortex_2d(N)
+    with gks.Solver(prob, st, precision) as S:
+        S.step(nsteps, dt=dt)
+        got, t, n = S.fetch()
+    return got
+
+
+def cpu_baseline(budget_s=15.0):
+    import oracle
+    from paper_1412_4489_amd import workloads as W
+    prob, st = W.vortex_2d(N)
+    oracle.lib()
+    dt = oracle.dt(prob, st)
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or (time.perf_counter() - t0 < budget_s and n < 40):
+        oracle.step(prob, st, dt, n * dt)
+        n += 1
+    sec = time.perf_counter() - t0
+    return {"value": round(prob.ncells * n / sec / 1e6, 4), "unit": "Mcell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} steps of the same 256x256 vortex (fixed dt {dt:.6g}), FP64, OpenMP over rows"}, st, n, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the method's single-GPU path); "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_1412_4489_amd import gks
+
+    res = {}
+    for name, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
+        wall, kt, prob = run_gpu(prec, a.steps, a.warmup)
+        res[name] = (wall, kt, prob)
+        print(f"# {name}: {a.steps} steps in {wall * 1e3:.2f} ms; kernel ms: "
+              + ", ".join(f"{k} {v[0]:.2f} ({v[1]})" for k, v in kt.items()), file=sys.stderr, flush=True)
+
+    wall, kt, prob = res["fp32_mixed"]
+    cells = prob.ncells
+    value = cells * a.steps / wall / 1e6
+    wall64, kt64, _ = res["fp64"]
+    value64 = cells * a.steps / wall64 / 1e6
+    n_if = (prob.nx + 1) * prob.ny + prob.nx * (prob.ny + 1)
+    fl = interface_flops(False) * n_if
+    ms_if, nl = kt["interface"]
+    t_if = ms_if / 1e3 / max(nl, 1)
+    achieved = fl / t_if
+    ms64, nl64 = kt64["interface"]
+    achieved64 = fl / (ms64 / 1e3 / max(nl64, 1))
+
+    out = {
+        "metric": "Mcell-updates/s (FP32 & batched vs FP64) at stated L1 err vs oracle",
+        "value": round(value, 3),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "isentropic vortex (Sec. 4.1), 256x256 cells, periodic [0,10]^2, gamma 1.4, "
+                               "CFL 0.2, Euler, GKS_FP32_MIXED", "cells": cells, "interfaces": n_if},
+        "fp64": {"value": round(value64, 3), "ms_per_step": round(wall64 / a.steps * 1e3, 5),
+                 "interface_ms": round(ms64 / max(nl64, 1), 5),
+                 "interface_tflops": round(achieved64 / 1e12, 3)},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
+                     "kernel": "k_interfaces_2d<float>", "flops_per_interface": interface_flops(False),
+                     "interface_ms": round(t_if * 1e3, 5)},
+    }
+    if not a.no_cpu:
+        cb, ref, nref, dt = cpu_baseline()
+        out["cpu_baseline"] = cb
+        errs = {}
+        for name, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
+            got = gpu_fixed_steps(prec, nref, dt)
+            errs[name] = float(np.abs(got.cell[0] - ref.cell[0]).mean() / np.abs(ref.cell[0]).mean())
+        out["l1_rel_err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
+        out["l1_sample_steps"] = nref
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

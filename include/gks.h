@@ -1,0 +1,153 @@
+/*
+ * gks.h -- C ABI of the MI355X (gfx950) implementation of the compact
+ * third-order gas-kinetic scheme of Pan & Xu, "A Compact Third-order
+ * Gas-kinetic Scheme for Compressible Euler and Navier-Stokes Equations"
+ * (arXiv:1412.4489).
+ *
+ * One time step of the scheme (a single stage, no Runge-Kutta; Sec. 1, 5):
+ *   1. boundary images of the cell averages and interface point values;
+ *   2. time step from the CFL condition (Sec. 4) unless a fixed one is given;
+ *   3. compact reconstruction of every cell from its average, its face
+ *      neighbours' averages and the tracked interface Gauss-point values
+ *      (Sec. 3.1, 3.2: one-sided stencils, limiter eq. limiter, central
+ *      stencil, nonlinear weights eq. average);
+ *   4. at every interface: the equilibrium state U0 (eq. compatibility2), its
+ *      quadratic (Sec. 3.3), the collision time (Sec. 4), the expansion
+ *      coefficients (system after eq. dis3), the time- and interface-integrated
+ *      flux (eq. finite with eq. dis1 + eq. dis2) and the point values at the
+ *      next time level (eq. point);
+ *   5. the conservative update (eq. finite).
+ *
+ * Every call returns an int status (GKS_OK or a negative GKS_E* code); no C++
+ * exception crosses the ABI.  All arrays are plain memory with the layouts
+ * stated below; the library never keeps a pointer to caller memory after a
+ * call returns.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  GKS_OK = 0,
+  GKS_EINVAL = -1,   /* invalid argument (checked before any device work) */
+  GKS_ENOMEM = -2,   /* device allocation failed */
+  GKS_EDEVICE = -3,  /* HIP runtime error */
+  GKS_ENONPHYS = -4, /* a cell reached rho <= 0, p <= 0 or a non-finite value */
+  GKS_ESTATE = -5    /* the handle is in an error state (call gks_destroy) */
+};
+
+/* arithmetic of the interface evaluation */
+enum {
+  GKS_FP64 = 0,       /* double precision throughout */
+  GKS_FP32_MIXED = 1  /* single precision for the derivative (correction) terms of the
+                         interface distribution and for the stored point values and
+                         reconstruction; double for the cell averages, the conservative
+                         accumulation, the equilibrium state U0, the leading flux terms
+                         and the exponential time integrals */
+};
+
+/* boundary kinds (one per side W, E, S, N) */
+enum {
+  GKS_BC_PERIODIC = 0,
+  GKS_BC_OUTFLOW = 1,             /* zero normal gradient (mirror image) */
+  GKS_BC_REFLECT = 2,             /* slip wall: mirror image, normal momentum negated */
+  GKS_BC_NOSLIP_ISOTHERMAL = 3,   /* ghost velocity 2 u_w - u, ghost temperature 2 T_w - T */
+  GKS_BC_NOSLIP_ADIABATIC = 4,    /* ghost velocity 2 u_w - u, temperature mirrored */
+  GKS_BC_INFLOW = 5,              /* fixed primitive state `state` */
+  GKS_BC_DMR_BOTTOM = 6,          /* `state` for x < 1/6, slip wall beyond (Sec. 4.5) */
+  GKS_BC_DMR_TOP = 7              /* `state` behind the Mach-10 shock line
+                                     x = 1/6 + (y + 20 t)/sqrt(3), `alt` ahead of it */
+};
+
+typedef struct {
+  int32_t kind;
+  double state[4]; /* primitive (rho, u, v, p) */
+  double alt[4];   /* second primitive state (DMR pre-shock) */
+  double wall_u, wall_v, wall_T;
+} gks_bc;
+
+/* The problem, as the paper states it: Euler or Navier-Stokes for
+ * W = (rho, rho u, rho v, rho E) in 2D, (rho, rho u, rho E) in 1D (eq. finite);
+ * gamma fixes the internal degrees of freedom K = (4 - 2 gamma)/(gamma - 1) in
+ * 2D and (3 - gamma)/(gamma - 1) in 1D (Sec. 2.1); collision time
+ * tau = tau_eps dt + tau_c |p_l - p_r|/(p_l + p_r) dt (Euler) or
+ * mu/p + tau_c |p_l - p_r|/(p_l + p_r) dt (Navier-Stokes) (Sec. 4). */
+typedef struct {
+  int32_t dim;              /* 1 or 2 */
+  int32_t nx, ny;           /* cells; ny = 1 when dim == 1 */
+  double x0, x1, y0, y1;    /* domain [x0, x1] x [y0, y1] */
+  double gamma;
+  int32_t viscous;          /* 0 Euler, 1 Navier-Stokes */
+  double mu, prandtl;       /* constant viscosity; Prandtl number (1 = plain BGK) */
+  double tau_eps, tau_c;
+  double cfl;               /* dt = cfl * min over cells of min(dx/(|u|+c+2nu/dx), dy/(|v|+c+2nu/dy)) */
+  double weno_eps, weno_c;  /* small number and C of I(U1) = C h^2 in the weights */
+  int32_t recon_vars;       /* 0: conservative variables (the only kind in 2D) */
+  int32_t precision;        /* GKS_FP64 or GKS_FP32_MIXED */
+  gks_bc bc[4];             /* W, E, S, N */
+  double t0;                /* time of the initial state (restart from a fetched state) */
+} gks_problem;
+
+typedef struct gks_handle gks_handle; /* opaque, owned by the library */
+
+/* Create a handle for n_problems independent grids (n_problems > 1: a batch,
+ * advanced together by gks_step) and upload their initial state.
+ *   cell[p]   : host, [nvar][ny][nx] cell averages, nvar = dim + 2
+ *   face_x[p] : host, [ng][nvar][ny][nx+1] point values on the x interfaces,
+ *               ng = 2 (2D: Gauss points y_j -/+ sqrt(3)/6 dy, in that order) or 1 (1D)
+ *   face_y[p] : host, [2][nvar][ny+1][nx] point values on the y interfaces
+ *               (Gauss points x_i -/+ sqrt(3)/6 dx); NULL when dim == 1
+ *   stream    : a hipStream_t the library launches on (borrowed; it must
+ *               outlive the handle), or NULL for a stream of the library's own.
+ * Host arrays are read during the call only.  Returns GKS_EINVAL for an
+ * inconsistent problem (sizes, gamma, unknown boundary kind, nonphysical
+ * initial state), GKS_ENOMEM / GKS_EDEVICE on device failures. */
+int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs,
+             const double* const* cell, const double* const* face_x,
+             const double* const* face_y, void* stream);
+
+/* Enqueue nsteps time steps of every problem (asynchronous; returns after the
+ * launches).  dt_fixed: NULL to take each step from the CFL condition on the
+ * device, else dt_fixed[p] for every step of problem p.  t_end: NULL for no
+ * limit, else the last step of problem p is shortened to end at t_end[p] and
+ * later steps leave it unchanged.  Arguments are validated before anything
+ * is enqueued (GKS_EINVAL). */
+int gks_step(gks_handle* h, int32_t nsteps, const double* dt_fixed, const double* t_end);
+
+/* Wait for the enqueued work and copy the state of one problem to host
+ * arrays with the layouts of gks_init (any pointer may be NULL to skip it),
+ * plus its time and number of steps taken.  Returns the first sticky error:
+ * GKS_ENONPHYS if some step produced rho <= 0, p <= 0 or a non-finite value
+ * (gks_last_error names the problem and cell), after which the handle only
+ * accepts gks_fetch, gks_last_error and gks_destroy (GKS_ESTATE). */
+int gks_fetch(gks_handle* h, int32_t problem, double* cell, double* face_x, double* face_y,
+              double* t, int64_t* steps);
+
+/* Release all device memory, streams and events of the handle. */
+int gks_destroy(gks_handle* h);
+
+/* Human-readable description of the last error on this handle (static
+ * storage owned by the handle, valid until the next call on it).  With
+ * h == NULL: the reason of the last gks_init that failed on this thread. */
+const char* gks_last_error(const gks_handle* h);
+
+/* Kernel timing.  gks_profile(h, 1) makes every following gks_step record
+ * HIP events on the library's stream around each kernel launch; the
+ * accumulated time (ms) and launch count of kernel k (GKS_K_*) since the last
+ * reset are returned by gks_kernel_time (which synchronises the stream).
+ * gks_profile(h, 0) stops recording; gks_profile(h, 2) resets the sums. */
+enum { GKS_K_GHOST = 0, GKS_K_DT = 1, GKS_K_RECON = 2, GKS_K_INTERFACE = 3, GKS_K_UPDATE = 4,
+       GKS_K_COUNT = 5 };
+int gks_profile(gks_handle* h, int32_t mode);
+int gks_kernel_time(gks_handle* h, int32_t kernel, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKS_H */

@@ -1,0 +1,206 @@
+"""Thin ctypes binding of the C ABI in include/gks.h (libgks.so, gfx950).
+
+The functions keep the C names (gks_init, gks_step, gks_fetch, gks_destroy,
+gks_last_error, gks_profile, gks_kernel_time) and only marshal arguments;
+every step of the scheme runs in the HIP kernels of the library.  `Solver`
+wraps a handle for numpy arrays laid out as in paper_1412_4489_amd.workloads.
+
+There is no CPU fallback: if the library is not built or no HIP device is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libgks.so")
+
+GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_ENONPHYS, GKS_ESTATE = 0, -1, -2, -3, -4, -5
+GKS_FP64, GKS_FP32_MIXED = 0, 1
+BC_CODES = {"periodic": 0, "outflow": 1, "reflect": 2, "noslip_iso": 3, "noslip_adia": 4,
+            "inflow": 5, "dmr_bottom": 6, "dmr_top": 7}
+KERNELS = {"ghost": 0, "dt": 1, "recon": 2, "interface": 3, "update": 4}
+STATUS = {0: "GKS_OK", -1: "GKS_EINVAL", -2: "GKS_ENOMEM", -3: "GKS_EDEVICE", -4: "GKS_ENONPHYS",
+          -5: "GKS_ESTATE"}
+
+
+class gks_bc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("state", C.c_double * 4), ("alt", C.c_double * 4),
+                ("wall_u", C.c_double), ("wall_v", C.c_double), ("wall_T", C.c_double)]
+
+
+class gks_problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("gamma", C.c_double), ("viscous", C.c_int32), ("mu", C.c_double),
+                ("prandtl", C.c_double), ("tau_eps", C.c_double), ("tau_c", C.c_double),
+                ("cfl", C.c_double), ("weno_eps", C.c_double), ("weno_c", C.c_double),
+                ("recon_vars", C.c_int32), ("precision", C.c_int32), ("bc", gks_bc * 4),
+                ("t0", C.c_double)]
+
+
+class GKSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load libgks.so (built by paper_1412_4489_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_1412_4489_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.gks_init.argtypes = [C.POINTER(_P), C.c_int32, C.POINTER(gks_problem), C.POINTER(_D), C.POINTER(_D),
+                               C.POINTER(_D), _P]
+        L.gks_step.argtypes = [_P, C.c_int32, _D, _D]
+        L.gks_fetch.argtypes = [_P, C.c_int32, _D, _D, _D, _D, C.POINTER(C.c_int64)]
+        L.gks_destroy.argtypes = [_P]
+        L.gks_last_error.argtypes = [_P]
+        L.gks_last_error.restype = C.c_char_p
+        L.gks_profile.argtypes = [_P, C.c_int32]
+        L.gks_kernel_time.argtypes = [_P, C.c_int32, _D, C.POINTER(C.c_int64)]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("gks_init", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error", "gks_profile",
+            "gks_kernel_time")
+
+
+def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
+    P = gks_problem()
+    P.t0 = t0
+    P.dim, P.nx, P.ny = prob.dim, prob.nx, prob.ny
+    P.x0, P.x1, P.y0, P.y1 = prob.x0, prob.x1, prob.y0, prob.y1
+    P.gamma, P.viscous, P.mu, P.prandtl = prob.gamma, int(prob.viscous), prob.mu, prob.prandtl
+    P.tau_eps, P.tau_c, P.cfl = prob.tau_eps, prob.tau_c, prob.cfl
+    P.weno_eps, P.weno_c, P.recon_vars = prob.weno_eps, prob.weno_c, prob.recon_vars
+    P.precision = precision
+    for s, bc in enumerate(prob.bc):
+        P.bc[s].kind = BC_CODES[bc.kind]
+        for i in range(4):
+            P.bc[s].state[i] = bc.state[i]
+            P.bc[s].alt[i] = bc.alt[i]
+        P.bc[s].wall_u, P.bc[s].wall_v, P.bc[s].wall_T = bc.wall
+    return P
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def gks_init(probs, states, precision=GKS_FP64, stream=None, t0=None):
+    """probs: list of workloads.Problem; states: list of workloads.State;
+    t0: initial times (default 0).  Returns an opaque handle (c_void_p)."""
+    n = len(probs)
+    t0 = [0.0] * n if t0 is None else list(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
+    cp = (gks_problem * n)(*[to_c_problem(p, precision, t) for p, t in zip(probs, t0)])
+    keep = []
+    cells, fxs, fys = (_D * n)(), (_D * n)(), (_D * n)()
+    for k, (p, st) in enumerate(zip(probs, states)):
+        c = np.ascontiguousarray(st.cell, dtype=np.float64)
+        fx = np.ascontiguousarray(st.fx, dtype=np.float64)
+        fy = np.ascontiguousarray(st.fy, dtype=np.float64)
+        keep += [c, fx, fy]
+        cells[k], fxs[k], fys[k] = _ptr(c), _ptr(fx), _ptr(fy)
+    h = _P()
+    rc = lib().gks_init(C.byref(h), n, cp, cells, fxs, fys, stream)
+    if rc != GKS_OK:
+        raise GKSError(rc, "gks_init: " + lib().gks_last_error(None).decode())
+    return h
+
+
+def gks_step(h, nsteps, dt_fixed=None, t_end=None):
+    d = None if dt_fixed is None else np.ascontiguousarray(dt_fixed, dtype=np.float64)
+    e = None if t_end is None else np.ascontiguousarray(t_end, dtype=np.float64)
+    rc = lib().gks_step(h, int(nsteps), None if d is None else _ptr(d), None if e is None else _ptr(e))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+
+
+def gks_fetch(h, problem, prob):
+    """Returns (State, t, steps) of one problem."""
+    from .workloads import State
+    nv = prob.nvar
+    cell = np.zeros((nv, prob.ny, prob.nx))
+    ng = 2 if prob.dim == 2 else 1
+    fx = np.zeros((ng, nv, prob.ny, prob.nx + 1))
+    fy = np.zeros((2, nv, prob.ny + 1, prob.nx))
+    t = C.c_double()
+    steps = C.c_int64()
+    rc = lib().gks_fetch(h, int(problem), _ptr(cell), _ptr(fx), _ptr(fy) if prob.dim == 2 else None,
+                         C.byref(t), C.byref(steps))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+    return State(cell, fx, fy), t.value, steps.value
+
+
+def gks_destroy(h):
+    lib().gks_destroy(h)
+
+
+def gks_last_error(h):
+    return lib().gks_last_error(h).decode()
+
+
+def gks_profile(h, mode):
+    rc = lib().gks_profile(h, int(mode))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+
+
+def gks_kernel_time(h, kernel):
+    ms = C.c_double()
+    n = C.c_int64()
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    rc = lib().gks_kernel_time(h, k, C.byref(ms), C.byref(n))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+    return ms.value, n.value
+
+
+class Solver:
+    """A handle over one or more problems (context manager)."""
+
+    def __init__(self, probs, states, precision=GKS_FP64, stream=None, t0=None):
+        if not isinstance(probs, (list, tuple)):
+            probs, states = [probs], [states]
+        self.probs = list(probs)
+        self.h = None
+        self.h = gks_init(self.probs, states, precision, stream, t0)
+
+    def step(self, nsteps=1, dt=None, t_end=None):
+        n = len(self.probs)
+        d = None if dt is None else np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)).copy()
+        e = None if t_end is None else np.broadcast_to(np.asarray(t_end, dtype=np.float64), (n,)).copy()
+        gks_step(self.h, nsteps, d, e)
+
+    def fetch(self, k=0):
+        return gks_fetch(self.h, k, self.probs[k])
+
+    def close(self):
+        if self.h is not None:
+            gks_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,175 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides start from the same seeded initial data (paper_1412_4489_amd.workloads)
+and take the same fixed time steps; cell averages and interface point values
+are compared element by element.
+
+Tolerances:
+  * GKS_FP64: the two sides evaluate the same formulas in different orders
+    (closed-form peculiar-frame moments on the GPU, term-by-term polynomial
+    moments in the oracle); after n steps the relative difference stays at a
+    few ulps times the condition of the step: 1e-11 relative to the field's
+    magnitude.
+  * GKS_FP32_MIXED: the derivative terms of the interface distribution are
+    single precision (unit roundoff 6e-8) while cell averages, U0 and the
+    leading flux terms are double; the per-step relative error is ~1e-7 of the
+    flux correction, so 5e-6 after tens of steps on smooth data.
+Where floating point decides a branch (minmod zero, smallest cross
+derivative), both sides take it in double precision (the reconstruction is
+double precision in both forms).
+"""
+import numpy as np
+import pytest
+
+from paper_1412_4489_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_4489_amd import gks
+    gks.lib()
+    return gks
+
+
+def _compare(a, b, rtol, what):
+    scale = np.abs(b).max(axis=tuple(range(1, b.ndim)), keepdims=True) if b.ndim > 1 else np.abs(b).max()
+    err = np.abs(a - b) / np.maximum(scale, 1e-300)
+    assert np.isfinite(a).all(), f"{what}: non-finite values"
+    assert err.max() <= rtol, f"{what}: max relative diff {err.max():.3e} > {rtol:.1e} at {np.unravel_index(err.argmax(), err.shape)}"
+
+
+def _run_both(G, oracle, prob, st, nsteps, dt, precision):
+    ref = st.copy()
+    t = 0.0
+    for n in range(nsteps):
+        oracle.step(prob, ref, dt, t)
+        t += dt
+    with G.Solver(prob, st, precision) as S:
+        S.step(nsteps, dt=dt)
+        got, tg, steps = S.fetch()
+    assert steps == nsteps
+    assert tg == pytest.approx(t, rel=1e-14)
+    return got, ref
+
+
+CASES = {
+    "smooth": lambda: W.smooth_periodic_2d(nx=24, ny=19, seed=1),
+    "rough": lambda: W.random_perturbed_2d(nx=21, ny=17, seed=2, amp=0.15),
+    "vortex": lambda: W.vortex_2d(32),
+    "riemann": lambda: W.riemann_2d(1, n=30),
+    "ns_smooth": lambda: W.smooth_periodic_2d(nx=20, ny=18, seed=3, viscous=True, mu=2e-3, prandtl=0.72,
+                                              tau_eps=0.0),
+    "dmr": lambda: W.dmr(48, 12),
+    "cavity": lambda: W.cavity(24, re=100.0),
+}
+SMOOTH = ["smooth", "vortex", "ns_smooth"]
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_parity_fp64_one_step(G, oracle, case):
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    got, ref = _run_both(G, oracle, prob, st, 1, dt, G.GKS_FP64)
+    _compare(got.cell, ref.cell, 1e-11, "cell")
+    _compare(got.fx, ref.fx, 1e-10, "x point values")
+    _compare(got.fy, ref.fy, 1e-10, "y point values")
+
+
+@pytest.mark.parametrize("case", SMOOTH)
+def test_parity_fp64_free_running(G, oracle, case):
+    """Smooth data: no limiter decision sits near a tie, both sides run on their own."""
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    got, ref = _run_both(G, oracle, prob, st, 8, dt, G.GKS_FP64)
+    _compare(got.cell, ref.cell, 1e-11, "cell")
+    _compare(got.fx, ref.fx, 1e-10, "x point values")
+    _compare(got.fy, ref.fy, 1e-10, "y point values")
+
+
+@pytest.mark.parametrize("case", ["rough", "riemann", "dmr", "cavity"])
+def test_parity_fp64_per_step(G, oracle, case):
+    """Discontinuous data: the smallest-|cross derivative| choice and minmod
+    are discontinuous in their arguments, so rounding-level differences left
+    by an earlier step can legitimately select another branch.  Each step is
+    therefore compared from the oracle's own state (the GPU restarts from it,
+    with its time), for several consecutive steps."""
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    t = 0.0
+    for n in range(4):
+        ref = st.copy()
+        oracle.step(prob, ref, dt, t)
+        with G.Solver(prob, st, G.GKS_FP64, t0=t) as S:
+            S.step(1, dt=dt)
+            got, tg, steps = S.fetch()
+        _compare(got.cell, ref.cell, 1e-11, f"cell, step {n}")
+        _compare(got.fx, ref.fx, 1e-10, f"x point values, step {n}")
+        _compare(got.fy, ref.fy, 1e-10, f"y point values, step {n}")
+        st, t = ref, t + dt
+
+
+@pytest.mark.parametrize("case", ["smooth", "vortex", "ns_smooth"])
+def test_parity_fp32_mixed(G, oracle, case):
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    got, ref = _run_both(G, oracle, prob, st, 10, dt, G.GKS_FP32_MIXED)
+    _compare(got.cell, ref.cell, 5e-6, "cell")
+    _compare(got.fx, ref.fx, 2e-5, "x point values")
+    _compare(got.fy, ref.fy, 2e-5, "y point values")
+
+
+def test_cfl_step_matches_oracle(G, oracle):
+    prob, st = W.vortex_2d(24)
+    ref = st.copy()
+    dt = oracle.dt(prob, ref)
+    oracle.step(prob, ref, dt, 0.0)
+    with G.Solver(prob, st) as S:
+        S.step(1)
+        got, t, steps = S.fetch()
+    assert t == pytest.approx(dt, rel=1e-14)
+    _compare(got.cell, ref.cell, 1e-11, "cell")
+
+
+def test_t_end_clips_last_step(G, oracle):
+    prob, st = W.vortex_2d(16)
+    with G.Solver(prob, st) as S:
+        dt = 0.05
+        S.step(5, dt=dt, t_end=0.12)
+        got, t, steps = S.fetch()
+    assert t == pytest.approx(0.12, rel=1e-14) and steps == 3
+
+
+def test_batch_of_uneven_grids(G, oracle):
+    probs, states = [], []
+    for k, (n, seed) in enumerate([(12, 0), (17, 1), (9, 2)]):
+        p, s = W.smooth_periodic_2d(nx=n, ny=n + k, seed=seed)
+        probs.append(p)
+        states.append(s)
+    dts = [0.7 * oracle.dt(p, s) for p, s in zip(probs, states)]
+    refs = [s.copy() for s in states]
+    for p, r, dt in zip(probs, refs, dts):
+        for n in range(3):
+            oracle.step(p, r, dt, n * dt)
+    with G.Solver(probs, states) as S:
+        S.step(3, dt=np.array(dts))
+        for k in range(3):
+            got, t, steps = S.fetch(k)
+            _compare(got.cell, refs[k].cell, 1e-11, f"cell {k}")
+
+
+def test_nonphysical_state_is_reported(G):
+    prob, st = W.riemann_2d(2, n=16)
+    with G.Solver(prob, st) as S:
+        S.step(3, dt=5.0)  # far beyond any CFL limit: the state blows up (no memory access depends on values)
+        with pytest.raises(G.GKSError) as e:
+            S.fetch()
+        assert e.value.code == G.GKS_ENONPHYS
+        assert "nonphysical" in G.gks_last_error(S.h)
+        with pytest.raises(G.GKSError) as e2:
+            S.step(1, dt=0.01)
+        assert e2.value.code == G.GKS_ESTATE
