@@ -1124,16 +1124,30 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
   }
 }
 
-/* reconstruction of cell (i, j), all components (conservative variables) */
+/* reconstruction of cell (i, j), all components (conservative variables).
+ * Reading (robustness at strong shocks, not printed): if the reconstructed
+ * polynomial gives rho <= 0 or p <= 0 at the centre of any of the cell's four
+ * interfaces, the cell is reconstructed as its constant average for this step. */
 static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
-  for (int v = 0; v < G->nv; ++v) {
-    double p[5];
+  double pc[4][5];
+  for (int v = 0; v < G->nv; ++v)
     orc_recon2d_scalar(GW(G, v, j, i), GW(G, v, j, i + 1), GW(G, v, j, i - 1), GW(G, v, j + 1, i),
                        GW(G, v, j - 1, i), GFX(G, 1, v, j, i + 1), GFX(G, 0, v, j, i + 1), GFX(G, 1, v, j, i),
                        GFX(G, 0, v, j, i), GFY(G, 1, v, j + 1, i), GFY(G, 0, v, j + 1, i), GFY(G, 1, v, j, i),
-                       GFY(G, 0, v, j, i), h, k, P->weno_eps, P->weno_c, p);
-    for (int m = 0; m < 5; ++m) GPC(G, v, m, j, i) = p[m];
+                       GFY(G, 0, v, j, i), h, k, P->weno_eps, P->weno_c, pc[v]);
+  int ok = 1;
+  for (int f = 0; f < 4; ++f) {
+    /* interface centres: x = +-h/2 (y = 0), y = +-k/2 (x = 0) */
+    double x = f == 0 ? 0.5 * h : f == 1 ? -0.5 * h : 0.0;
+    double y = f == 2 ? 0.5 * k : f == 3 ? -0.5 * k : 0.0;
+    double W[4];
+    for (int v = 0; v < 4; ++v)
+      W[v] = GW(G, v, j, i) + pc[v][0] * x + pc[v][1] * y + pc[v][2] * 0.5 * (x * x - h * h / 12.0) +
+             pc[v][3] * 0.5 * (y * y - k * k / 12.0) + pc[v][4] * x * y;
+    if (!(W[0] > 0.0) || !(pressure(2, P->gamma, W) > 0.0)) ok = 0;
   }
+  for (int v = 0; v < G->nv; ++v)
+    for (int m = 0; m < 5; ++m) GPC(G, v, m, j, i) = ok ? pc[v][m] : 0.0;
 }
 
 /* interface values of a cell polynomial on the side facing the interface

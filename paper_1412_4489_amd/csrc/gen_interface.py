@@ -11,10 +11,12 @@ the interface point values need (Pan & Xu, arXiv:1412.4489, Sec. 2.2):
                 variables (the compatibility systems after eq. dis3), solved
                 in closed form in the peculiar frame, where the Gram matrix
                 <psi psi^T> is block diagonal;
-  * hydro_*  -- moments of the hydrodynamic part (eq. dis1, weight g0, whole
-                velocity space) without its leading C1 g0 term;
-  * kin_*    -- moments of the kinetic part of one side (eq. dis2, weight g_k
-                on a half space) without its leading C7 g_k term.
+  * mom_full_<term>, mom_half_<term>
+             -- for one velocity polynomial X of eq. dis1 / eq. dis2 (a product
+                of coefficient polynomials and particle velocities), the moments
+                m0 = <psi' X> and (for flux terms) m1 = <c psi' X> over the whole
+                velocity space (g0) or over the half space of one side (g_l on
+                u > 0, g_r on u < 0).  The time weights are applied by the caller.
 
 Whole-space central moments are closed forms in theta = 1/(2 lambda) and K;
 half-space moments enter as the runtime table h[n] = <c^n>_half.  Products of
@@ -168,7 +170,7 @@ PR = Printer()
 def emit(assign, outputs, indent="  "):
     """assign: list of (name, expr) final outputs; cse and print."""
     names = [n for n, _ in outputs]
-    exprs = [e for _, e in outputs]
+    exprs = [sp.sympify(e) for _, e in outputs]
     repl, red = sp.cse(exprs, symbols=sp.numbered_symbols("t_"), optimizations="basic")
     lines = []
     for s, e in repl:
@@ -299,84 +301,50 @@ def coefficient_polys(dim, viscous_side, role):
     return P
 
 
-def gen_hydro(dim):
-    """Moments of eq. dis1 without the leading C1 term, whole space (g0).
-
-    Flux weights (time integrals): wI[2..6] = int C2..C6; wI1y = int C1 * ds^2/24.
-    Point-value weights (at t = dt): wC[2..6] = C2..C6 ; wC1 = C1.
-    Outputs: AF = <psi' P_F>, BF = <c psi' P_F>, V0/V1/V2 = <psi' P_V> for the
-    y^0, y^1, y^2 parts of the point value."""
+# terms of the interface distribution: name -> (velocity polynomial builder,
+# coefficient vectors it reads, whether its flux moment <c psi' X> is needed)
+def term_polys(dim):
     nv = dim + 2
-    TH, KP = theta_syms()
-    M = Moments(dim, False, TH, KP)
     U, V = sp.Symbol("U"), sp.Symbol("V")
     u, v = C + U, Wv + V
-    P = coefficient_polys(dim, True, "hydro")
-    wI = [None, None] + [sp.Symbol(f"wI[{k}]") for k in range(2, 7)]
-    wC = [None, sp.Symbol("wC[1]")] + [sp.Symbol(f"wC[{k}]") for k in range(2, 7)]
-    wI1y = sp.Symbol("wI1y")
-    conv = P["AX"] * u + P["AY"] * v                       # a1 u + a2 v
-    quad = P["DXX"] * u * u + P["DXY"] * u * v * 2 + P["DYY"] * v * v
-    tlin = P["TX"] * u + P["TY"] * v
-    PF = conv * wI[2] + P["AT"] * wI[3] + quad * (wI[4] / 2) + P["TTT"] * (wI[5] / 2) + tlin * wI[6] \
-        + P["DYY"] * wI1y
-    out = []
-    AF = M.psi(PF)
-    BF = M.psi(PF, C)
-    out += [(f"AF[{i}]", AF[i]) for i in range(nv)]
-    out += [(f"BF[{i}]", BF[i]) for i in range(nv)]
-    PV0 = conv * wC[2] + P["AT"] * wC[3] + quad * (wC[4] / 2) + P["TTT"] * (wC[5] / 2) + tlin * wC[6]
-    V0 = M.psi(PV0)
-    out += [(f"V0[{i}]", V0[i]) for i in range(nv)]
-    if dim == 2:
-        PV1 = P["AY"] * wC[1] + (P["DYY"] * v + P["DXY"] * u) * wC[2] + P["TY"] * wC[3]
-        PV2 = P["DYY"] * (wC[1] / 2)
-        V1 = M.psi(PV1)
-        V2 = M.psi(PV2)
-        out += [(f"V1[{i}]", V1[i]) for i in range(nv)]
-        out += [(f"V2[{i}]", V2[i]) for i in range(nv)]
-    return out
+    vec = {n: lin(symvec(n, nv), dim) for n in ("ax", "ay", "At", "dxx", "dxy", "dyy", "bxt", "byt", "Bt")}
+    if dim == 1:
+        for n in ("ay", "dxy", "dyy", "byt"):
+            vec[n] = VP()
+    AX, AY, AT = vec["ax"], vec["ay"], vec["At"]
+    DXX = AX * AX + vec["dxx"]
+    DXY = AX * AY + vec["dxy"]
+    DYY = AY * AY + vec["dyy"]
+    TX = AT * AX + vec["bxt"]
+    TY = AT * AY + vec["byt"]
+    TTT = AT * AT + vec["Bt"]
+    T = {
+        # term       polynomial                                   inputs                     flux
+        "conv": (AX * u + AY * v, ["ax", "ay"], True),
+        "A": (AT, ["At"], True),
+        "quad": (DXX * u * u + DXY * u * v * 2 + DYY * v * v, ["ax", "ay", "dxx", "dxy", "dyy"], True),
+        "ttt": (TTT, ["At", "Bt"], True),
+        "tlin": (TX * u + TY * v, ["ax", "ay", "At", "bxt", "byt"], True),
+        "dyy": (DYY, ["ay", "dyy"], True),
+        "ay": (AY, ["ay"], False),
+        "inner": (DXY * u + DYY * v, ["ax", "ay", "dxy", "dyy"], False),
+        "ty": (TY, ["ay", "At", "byt"], False),
+    }
+    if dim == 1:
+        for n in ("dyy", "ay", "inner", "ty"):
+            del T[n]
+    return T
 
 
-def gen_kinetic(dim, viscous):
-    """Moments of eq. dis2 of one side without the leading C7 term (half space).
-
-    Flux weights: kI8 = int C8, kI72 = int C7 t^2 / 2, kI7y = int C7 * ds^2/24,
-    and for Navier-Stokes kI7tau = tau int C7, kI8tau = tau int C8.
-    Point-value weights: kC8, kC72 = C7 t^2/2, kC7, kC7t and kC7tau, kC8tau."""
-    nv = dim + 2
+def gen_term(dim, name, half):
     TH, KP = theta_syms()
-    H = [sp.Symbol(f"h[{n}]") for n in range(12)]
-    M = Moments(dim, True, TH, KP, H)
-    U, V = sp.Symbol("U"), sp.Symbol("V")
-    u, v = C + U, Wv + V
-    P = coefficient_polys(dim, viscous, "kin")
-    conv = P["AX"] * u + P["AY"] * v
-    quad = P["DXX"] * u * u + P["DXY"] * u * v * 2 + P["DYY"] * v * v
-    s = {n: sp.Symbol(n) for n in ("kI8", "kI72", "kI7y", "kI7tau", "kI8tau",
-                                   "kC8", "kC72", "kC7", "kC7t", "kC7tau", "kC8tau")}
-    PF = conv * s["kI8"] + quad * s["kI72"] + P["DYY"] * s["kI7y"]
-    PV0 = conv * s["kC8"] + quad * s["kC72"]
-    if viscous:
-        tlin = P["TX"] * u + P["TY"] * v
-        PF = PF - (conv + P["AT"]) * s["kI7tau"] - (quad + tlin) * s["kI8tau"]
-        PV0 = PV0 - (conv + P["AT"]) * s["kC7tau"] - (quad + tlin) * s["kC8tau"]
-    out = []
-    AF = M.psi(PF)
-    BF = M.psi(PF, C)
-    out += [(f"AF[{i}]", AF[i]) for i in range(nv)]
-    out += [(f"BF[{i}]", BF[i]) for i in range(nv)]
-    V0 = M.psi(PV0)
-    out += [(f"V0[{i}]", V0[i]) for i in range(nv)]
-    if dim == 2:
-        inner = P["DXY"] * u + P["DYY"] * v
-        PV1 = P["AY"] * s["kC7"] - inner * s["kC7t"]
-        if viscous:
-            PV1 = PV1 - (inner + P["TY"]) * s["kC7tau"]
-        PV2 = P["DYY"] * (s["kC7"] / 2)
-        out += [(f"V1[{i}]", e) for i, e in enumerate(M.psi(PV1))]
-        out += [(f"V2[{i}]", e) for i, e in enumerate(M.psi(PV2))]
-    return out
+    H = [sp.Symbol(f"h[{n}]") for n in range(12)] if half else None
+    M = Moments(dim, half, TH, KP, H)
+    P, ins, flux = term_polys(dim)[name]
+    out = [(f"m0[{i}]", e) for i, e in enumerate(M.psi(P))]
+    if flux:
+        out += [(f"m1[{i}]", e) for i, e in enumerate(M.psi(P, C))]
+    return ins, flux, out
 
 
 HEADER = """// interface_gen.h -- GENERATED by gen_interface.py; do not edit by hand.
@@ -412,28 +380,21 @@ def main():
             lines.append("}\n")
             body += lines
             report.append((f"coef_{tag}_{dim}d", total))
-        l, n = emit(None, gen_hydro(dim))
-        body.append(f"template <typename T>\n__device__ __forceinline__ void hydro_{dim}d(\n"
-                    f"    const T* __restrict__ th, const T* __restrict__ kp, T U, T V,\n"
-                    f"    const T* ax, const T* ay, const T* At, const T* dxx, const T* dxy, const T* dyy,\n"
-                    f"    const T* bxt, const T* byt, const T* Bt, const T* wI, T wI1y, const T* wC,\n"
-                    f"    T* AF, T* BF, T* V0, T* V1, T* V2) {{")
-        body += l
-        body.append("}\n")
-        report.append((f"hydro_{dim}d", n))
-        for visc in (False, True):
-            tag = "ns" if visc else "euler"
-            l, n = emit(None, gen_kinetic(dim, visc))
-            body.append(f"template <typename T>\n__device__ __forceinline__ void kin_{tag}_{dim}d(\n"
-                        f"    const T* __restrict__ th, const T* __restrict__ kp, const T* __restrict__ h,\n"
-                        f"    T U, T V, const T* ax, const T* ay, const T* At, const T* dxx, const T* dxy,\n"
-                        f"    const T* dyy, const T* bxt, const T* byt,\n"
-                        f"    T kI8, T kI72, T kI7y, T kI7tau, T kI8tau,\n"
-                        f"    T kC8, T kC72, T kC7, T kC7t, T kC7tau, T kC8tau,\n"
-                        f"    T* AF, T* BF, T* V0, T* V1, T* V2) {{")
-            body += l
-            body.append("}\n")
-            report.append((f"kin_{tag}_{dim}d", n))
+        for half, tag in ((False, "full"), (True, "half")):
+            for name in term_polys(dim):
+                ins, flux, outs = gen_term(dim, name, half)
+                if half and name in ("ttt",):
+                    continue  # B is not part of the kinetic part
+                l, n = emit(None, outs)
+                args = ", ".join(f"const T* {a}" for a in ins)
+                hh = "const T* __restrict__ h, " if half else ""
+                res = "T* m0, T* m1" if flux else "T* m0"
+                body.append(f"template <typename T>\n__device__ __forceinline__ void mom_{tag}_{name}_{dim}d(\n"
+                            f"    const T* __restrict__ th, const T* __restrict__ kp, {hh}T U, T V, {args},\n"
+                            f"    {res}) {{")
+                body += l
+                body.append("}\n")
+                report.append((f"mom_{tag}_{name}_{dim}d", n))
     out = os.path.join(HERE, "interface_gen.h")
     with open(out, "w") as f:
         f.write("\n".join(body))

@@ -87,7 +87,8 @@ struct Grid {
   double* t;      // time
   double* dt;     // step of the current step
   long long* steps;
-  unsigned long long* err;  // 0, or 1 + (j+1) * 65536 * 65536 + (i+1) * 65536 ... of the first bad cell
+  unsigned long long* err;
+  unsigned long long* dtmin;  // running minimum of the CFL bound (double bits)  // 0, or 1 + (j+1) * 65536 * 65536 + (i+1) * 65536 ... of the first bad cell
 };
 
 // ---------------------------------------------------------------------------
@@ -269,49 +270,62 @@ __global__ void k_ghost_sn(Grid<TS, TP> g, BCDev bs, BCDev bn, double gamma) {
 }
 
 // ---------------------------------------------------------------------------
-// time step
+// time step: dt = cfl * min over cells of min(h/(|u|+c+2nu/h), k/(|v|+c+2nu/k))
+// The per-cell bound is reduced into g.dtmin (bits of a positive double,
+// ordered like unsigned integers) by k_update_2d for the next step, and by
+// k_dt_scan for the initial state; k_dt_finalize turns it into the step.
 // ---------------------------------------------------------------------------
-constexpr int kDtThreads = 1024;
+__device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, double h, double k) {
+  const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
+  const double p = (P.gamma - 1.0) * (W[3] - 0.5 * rho * (u * u + v * v));
+  const double cs = sqrt(P.gamma * p / rho);
+  const double nu = P.viscous ? P.mu / rho : 0.0;
+  return fmin(h / (fabs(u) + cs + 2.0 * nu / h), k / (fabs(v) + cs + 2.0 * nu / k));
+}
 
-// dt = cfl * min over cells of min(h/(|u|+c+2nu/h), k/(|v|+c+2nu/k)), clipped
-// to t_end (t_end <= 0: no clip).  One block.
+// wave minimum of a positive bound, one atomic per wave (NaN bounds of a
+// nonphysical cell are skipped; the update flags that cell)
+__device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slot) {
+  if (!(b > 0.0) || !isfinite(b)) b = 1e300;
+  for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(slot, (unsigned long long)__double_as_longlong(b));
+}
+
 template <typename TS, typename TP>
-__global__ void __launch_bounds__(kDtThreads) k_dt(Grid<TS, TP> g, Phys P, double t_end) {
-  __shared__ double red[kDtThreads / 64];
-  const int nx = g.ix.nx, ny = g.ix.ny, n = nx * ny;
-  const double h = g.geo.h, k = g.geo.k;
-  double best = 1e300;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+__global__ void __launch_bounds__(256) k_dt_scan(Grid<TS, TP> g, Phys P) {
+  const int nx = g.ix.nx, ny = g.ix.ny;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double b = 1e300;
+  if (c < nx * ny) {
     const int j = c / nx, i = c % nx;
-    const double rho = g.W[g.ix.w(0, j, i)], u = g.W[g.ix.w(1, j, i)] / rho, v = g.W[g.ix.w(2, j, i)] / rho;
-    const double p = (P.gamma - 1.0) * (g.W[g.ix.w(3, j, i)] - 0.5 * rho * (u * u + v * v));
-    const double cs = sqrt(fmax(P.gamma * p / rho, 0.0));
-    const double nu = P.viscous ? P.mu / rho : 0.0;
-    best = fmin(best, h / (fabs(u) + cs + 2.0 * nu / h));
-    best = fmin(best, k / (fabs(v) + cs + 2.0 * nu / k));
+    double W[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[v] = g.W[g.ix.w(v, j, i)];
+    b = cell_dt_bound(W, P, g.geo.h, g.geo.k);
   }
-  for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_down(best, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = fmin(best, red[w]);
-    double dt = P.cfl * best;
-    if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
-    *g.dt = dt;
-  }
+  reduce_dt_bound(b, g.dtmin);
+}
+
+template <typename TS, typename TP>
+__global__ void k_dt_finalize(Grid<TS, TP> g, double cfl, double t_end) {
+  double dt = cfl * __longlong_as_double((long long)*g.dtmin);
+  if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
+  *g.dt = dt;
+  *g.dtmin = (unsigned long long)__double_as_longlong(1e300);
 }
 
 template <typename TS, typename TP>
 __global__ void k_set_dt(Grid<TS, TP> g, double dt, double t_end) {
   if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
   *g.dt = dt;
+  *g.dtmin = (unsigned long long)__double_as_longlong(1e300);
 }
 
 // ---------------------------------------------------------------------------
 // reconstruction: cells -1..nx x -1..ny except the four corners
 // ---------------------------------------------------------------------------
 template <typename TS, typename TP>
-__global__ void __launch_bounds__(256) k_recon_2d(Grid<TS, TP> g, double eps, double Cw) {
+__global__ void __launch_bounds__(256) k_recon_2d(Grid<TS, TP> g, double eps, double Cw, double gamma) {
   const int nx = g.ix.nx, ny = g.ix.ny;
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 1;
   const int j = (int)blockIdx.y - 1;
@@ -319,35 +333,66 @@ __global__ void __launch_bounds__(256) k_recon_2d(Grid<TS, TP> g, double eps, do
   if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
   const double h = g.geo.h, k = g.geo.k;
   const Idx& x = g.ix;
+  double p[4][5], Wc[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    double p[5];
-    recon_2d(g.W[x.w(v, j, i)], g.W[x.w(v, j, i + 1)], g.W[x.w(v, j, i - 1)], g.W[x.w(v, j + 1, i)],
-             g.W[x.w(v, j - 1, i)], (double)g.FX[x.fx(1, v, j, i + 1)], (double)g.FX[x.fx(0, v, j, i + 1)],
-             (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)], (double)g.FY[x.fy(1, v, j + 1, i)],
-             (double)g.FY[x.fy(0, v, j + 1, i)], (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k,
-             eps, Cw, p);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) g.PC[x.pc(v, m, j, i)] = (TP)p[m];
+    Wc[v] = g.W[x.w(v, j, i)];
+    recon_2d(Wc[v], g.W[x.w(v, j, i + 1)], g.W[x.w(v, j, i - 1)], g.W[x.w(v, j + 1, i)], g.W[x.w(v, j - 1, i)],
+             (double)g.FX[x.fx(1, v, j, i + 1)], (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)],
+             (double)g.FX[x.fx(0, v, j, i)], (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)],
+             (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, p[v]);
   }
+  // a polynomial that is nonphysical at the centre of one of the cell's
+  // interfaces is replaced by the constant cell average for this step
+  const bool ok = recon_admissible_2d(Wc, p, h, k, gamma);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) g.PC[x.pc(v, m, j, i)] = ok ? (TP)p[v][m] : TP(0);
 }
 
 // ---------------------------------------------------------------------------
-// interfaces: one thread per interface; x interfaces first, then y interfaces
+// interfaces: one thread per interface, x interfaces first, then y
+// interfaces; three phase kernels (prologue, hydrodynamic part, kinetic part
+// of each side) communicating through the frame record R.
 // ---------------------------------------------------------------------------
+struct Face {
+  bool isx;   // x interface (else y)
+  int a, b;   // x: (j, fi); y: (fj, i)
+};
+
+__device__ __forceinline__ Face face_of(const Idx& x, int id) {
+  const int nfx = (x.nx + 1) * x.ny;
+  Face F;
+  F.isx = id < nfx;
+  if (F.isx) {
+    F.a = id / (x.nx + 1);
+    F.b = id % (x.nx + 1);
+  } else {
+    const int r = id - nfx;
+    F.a = r / x.nx;
+    F.b = r % x.nx;
+  }
+  return F;
+}
+
+// interface-frame component of global component v: y interfaces swap the
+// two momentum components
+__device__ __forceinline__ int loc(bool isx, int v) { return isx ? v : (v == 1 ? 2 : v == 2 ? 1 : v); }
+
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_interfaces_2d(Grid<TS, TP> g, Phys P) {
+__global__ void __launch_bounds__(256) k_iface_pro_2d(Grid<TS, TP> g, Phys P, Rec<TC> R) {
   const int nx = g.ix.nx, ny = g.ix.ny;
-  const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+  const int nf = (nx + 1) * ny + nx * (ny + 1);
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nfx + nfy) return;
+  if (id >= nf) return;
   const double dt = *g.dt;
   if (!(dt > 0.0)) return;
   const Idx& x = g.ix;
-  double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pvm[4], pvp[4];
-  bool ok;
-  if (id < nfx) {
-    const int j = id / (nx + 1), fi = id % (nx + 1);
+  const Face F = face_of(x, id);
+  double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
+  if (F.isx) {
+    const int j = F.a, fi = F.b;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int ic = fi - 1 + s;
@@ -367,24 +412,14 @@ __global__ void __launch_bounds__(256) k_interfaces_2d(Grid<TS, TP> g, Phys P) {
       for (int n = 0; n < 3; ++n)
 #pragma unroll
         for (int v = 0; v < 4; ++v) Ueq[m][n][v] = g.W[x.w(v, j - 1 + n, fi - 1 + m)];
-    ok = interface_2d<TC>(P, dt, g.geo.h, g.geo.k, Wc, pc, Ueq, flux, pvm, pvp);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      g.FLX[x.flx(v, j, fi)] = flux[v];
-      g.FX[x.fx(0, v, j, fi)] = (TS)pvm[v];
-      g.FX[x.fx(1, v, j, fi)] = (TS)pvp[v];
-    }
-    if (!ok) atomicCAS(g.err, 0ull, 1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(fi + 1));
   } else {
-    const int r = id - nfx, fj = r / nx, i = r % nx;
-    // transposed frame: n = y, s = x, components (rho, rho v, rho u, rho E)
-    const int sw[4] = {0, 2, 1, 3};
+    const int fj = F.a, i = F.b;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int jc = fj - 1 + s;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int vl = sw[v];
+        const int vl = loc(false, v);
         Wc[s][vl] = g.W[x.w(v, jc, i)];
         pc[s][vl][0] = (double)g.PC[x.pc(v, 1, jc, i)];  // p_n  = p3
         pc[s][vl][1] = (double)g.PC[x.pc(v, 0, jc, i)];  // p_s  = p2
@@ -398,17 +433,105 @@ __global__ void __launch_bounds__(256) k_interfaces_2d(Grid<TS, TP> g, Phys P) {
 #pragma unroll
       for (int n = 0; n < 3; ++n)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Ueq[m][n][sw[v]] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
-    ok = interface_2d<TC>(P, dt, g.geo.k, g.geo.h, Wc, pc, Ueq, flux, pvm, pvp);
+        for (int v = 0; v < 4; ++v) Ueq[m][n][loc(false, v)] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
+  }
+  const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
+  const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, (size_t)id, flux, pv);
+  if (!ok) {
+    R.D(D_RHO0, id) = 0.0;  // marks the record invalid for the later phases
+    atomicCAS(g.err, 0ull,
+              1ull + ((unsigned long long)(F.a + 1) << 32) + (unsigned long long)(F.b + 1) + (F.isx ? 0ull : 1ull << 62));
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int vl = sw[v];
-      g.FLY[x.fly(v, fj, i)] = flux[vl];
-      g.FY[x.fy(0, v, fj, i)] = (TS)pvm[vl];
-      g.FY[x.fy(1, v, fj, i)] = (TS)pvp[vl];
+    for (int v = 0; v < 4; ++v) flux[v] = pv[v] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int vl = loc(F.isx, v);
+    if (F.isx) {
+      g.FLX[x.flx(v, F.a, F.b)] = flux[vl];
+      g.FX[x.fx(0, v, F.a, F.b)] = (TS)pv[vl];
+      g.FX[x.fx(1, v, F.a, F.b)] = (TS)pv[vl];
+    } else {
+      g.FLY[x.fly(v, F.a, F.b)] = flux[vl];
+      g.FY[x.fy(0, v, F.a, F.b)] = (TS)pv[vl];
+      g.FY[x.fy(1, v, F.a, F.b)] = (TS)pv[vl];
     }
-    if (!ok)
-      atomicCAS(g.err, 0ull, 1ull + ((unsigned long long)(fj + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 62));
+  }
+}
+
+// adds interface-frame corrections to the stored flux and point values
+template <typename TS, typename TP>
+__device__ __forceinline__ void add_corrections(Grid<TS, TP>& g, const Face& F, const double (&flux)[4],
+                                                const double (&pvm)[4], const double (&pvp)[4]) {
+  const Idx& x = g.ix;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int vl = loc(F.isx, v);
+    if (F.isx) {
+      g.FLX[x.flx(v, F.a, F.b)] += flux[vl];
+      TS* a = &g.FX[x.fx(0, v, F.a, F.b)];
+      TS* b = &g.FX[x.fx(1, v, F.a, F.b)];
+      *a = (TS)((double)*a + pvm[vl]);
+      *b = (TS)((double)*b + pvp[vl]);
+    } else {
+      g.FLY[x.fly(v, F.a, F.b)] += flux[vl];
+      TS* a = &g.FY[x.fy(0, v, F.a, F.b)];
+      TS* b = &g.FY[x.fy(1, v, F.a, F.b)];
+      *a = (TS)((double)*a + pvm[vl]);
+      *b = (TS)((double)*b + pvp[vl]);
+    }
+  }
+}
+
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_hydro_2d(Grid<TS, TP> g, Phys P, Rec<TC> R) {
+  const int nx = g.ix.nx, ny = g.ix.ny;
+  const int nf = (nx + 1) * ny + nx * (ny + 1);
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nf) return;
+  if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const Face F = face_of(g.ix, id);
+  const double hs = F.isx ? g.geo.k : g.geo.h;
+  double flux[4], pvm[4], pvp[4], E[4];
+  iface_hydro_2d<TC>(P, hs, R, (size_t)id, flux, pvm, pvp, E);
+  add_corrections(g, F, flux, pvm, pvp);
+  if (P.viscous)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R.D(D_E0 + v, id) += E[v];
+}
+
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_kin_2d(Grid<TS, TP> g, Phys P, Rec<TC> R, int side) {
+  const int nx = g.ix.nx, ny = g.ix.ny;
+  const int nf = (nx + 1) * ny + nx * (ny + 1);
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nf) return;
+  if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const Face F = face_of(g.ix, id);
+  const double hs = F.isx ? g.geo.k : g.geo.h;
+  double flux[4], pvm[4], pvp[4], E[4];
+  iface_kinetic_2d<TC>(P, hs, side, R, (size_t)id, flux, pvm, pvp, E);
+  add_corrections(g, F, flux, pvm, pvp);
+  if (P.viscous) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R.D(D_E0 + v, id) += E[v];
+    if (side == 1) {
+      // Prandtl-number fix on the complete flux: energy flux += (1/Pr - 1) q,
+      // q the heat flux relative to the velocity of g0 (interface frame)
+      const Idx& x = g.ix;
+      double Fl[4], Ed[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Fl[loc(F.isx, v)] = F.isx ? g.FLX[x.flx(v, F.a, F.b)] : g.FLY[x.fly(v, F.a, F.b)];
+        Ed[v] = R.D(D_E0 + v, id);
+      }
+      const double U0 = R.D(D_U0, id), V0 = R.D(D_V0, id), k2 = 0.5 * (U0 * U0 + V0 * V0);
+      const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
+      if (F.isx)
+        g.FLX[x.flx(3, F.a, F.b)] += P.prfix * qh;
+      else
+        g.FLY[x.fly(3, F.a, F.b)] += P.prfix * qh;
+    }
   }
 }
 
@@ -416,28 +539,37 @@ __global__ void __launch_bounds__(256) k_interfaces_2d(Grid<TS, TP> g, Phys P) {
 // conservative update
 // ---------------------------------------------------------------------------
 template <typename TS, typename TP>
-__global__ void __launch_bounds__(256) k_update_2d(Grid<TS, TP> g, double gamma) {
+__global__ void __launch_bounds__(256) k_update_2d(Grid<TS, TP> g, Phys P) {
   const int nx = g.ix.nx, ny = g.ix.ny;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   const double dt = *g.dt;
-  if (i >= nx || !(dt > 0.0)) return;
-  const Idx& x = g.ix;
-  const double ia = 1.0 / (g.geo.h * g.geo.k);
-  double W[4];
+  double bound = 1e300;
+  if (i < nx) {
+    const Idx& x = g.ix;
+    double W[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double d = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, i + 1)] + g.FLY[x.fly(v, j, i)] -
-                     g.FLY[x.fly(v, j + 1, i)];
-    W[v] = g.W[x.w(v, j, i)] + d * ia;
-    g.W[x.w(v, j, i)] = W[v];
+    for (int v = 0; v < 4; ++v) W[v] = g.W[x.w(v, j, i)];
+    if (dt > 0.0) {
+      const double ia = 1.0 / (g.geo.h * g.geo.k);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double d = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, i + 1)] + g.FLY[x.fly(v, j, i)] -
+                         g.FLY[x.fly(v, j + 1, i)];
+        W[v] += d * ia;
+        g.W[x.w(v, j, i)] = W[v];
+      }
+      const double p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
+        atomicCAS(g.err, 0ull,
+                  1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
+      if (i == 0 && j == 0) {
+        *g.t += dt;
+        *g.steps += 1;
+      }
+    }
+    bound = cell_dt_bound(W, P, g.geo.h, g.geo.k);
   }
-  const double p = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-  if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
-    atomicCAS(g.err, 0ull, 1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
-  if (i == 0 && j == 0) {
-    *g.t += dt;
-    *g.steps += 1;
-  }
+  reduce_dt_bound(bound, g.dtmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,6 +590,8 @@ struct Problem {
   void* FLX = nullptr;
   void* FLY = nullptr;
   void* scal = nullptr;  // t, dt, steps, err
+  void* recd = nullptr;  // interface frame record, double fields
+  void* rect = nullptr;  // interface frame record, compute-type fields
 };
 
 }  // namespace
@@ -533,6 +667,17 @@ std::string validate(const gks_problem& p) {
   return "";
 }
 
+size_t n_interfaces(const Idx& x) { return (size_t)(x.nx + 1) * x.ny + (size_t)x.nx * (x.ny + 1); }
+
+template <typename TC>
+Rec<TC> rec_of(Problem& p) {
+  Rec<TC> r;
+  r.d = (double*)p.recd;
+  r.t = (TC*)p.rect;
+  r.nf = n_interfaces(p.ix);
+  return r;
+}
+
 template <typename TS, typename TP>
 Grid<TS, TP> grid_of(Problem& p) {
   Grid<TS, TP> g;
@@ -549,6 +694,7 @@ Grid<TS, TP> grid_of(Problem& p) {
   g.dt = s + 1;
   g.steps = (long long*)(s + 2);
   g.err = (unsigned long long*)(s + 3);
+  g.dtmin = (unsigned long long*)(s + 4);
   return g;
 }
 
@@ -601,19 +747,24 @@ int step_problem(gks_handle* h, Problem& p, const double* dtf, double t_end) {
   if (dtf)
     k_set_dt<TS, TP><<<1, 1, 0, st>>>(g, *dtf, t_end);
   else
-    k_dt<TS, TP><<<1, kDtThreads, 0, st>>>(g, p.phys, t_end);
+    k_dt_finalize<TS, TP><<<1, 1, 0, st>>>(g, p.phys.cfl, t_end);
   record_end(h, GKS_K_DT);
   record_begin(h);
-  k_recon_2d<TS, TP><<<dim3(cdiv(nx + 2, 256), ny + 2), 256, 0, st>>>(g, p.phys.weno_eps, p.phys.weno_c);
+  k_recon_2d<TS, TP><<<dim3(cdiv(nx + 2, 256), ny + 2), 256, 0, st>>>(g, p.phys.weno_eps, p.phys.weno_c,
+                                                                         p.phys.gamma);
   record_end(h, GKS_K_RECON);
   record_begin(h);
   {
-    const size_t nf = (size_t)(nx + 1) * ny + (size_t)nx * (ny + 1);
-    k_interfaces_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys);
+    const size_t nf = n_interfaces(p.ix);
+    Rec<TC> R = rec_of<TC>(p);
+    k_iface_pro_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R);
+    k_iface_hydro_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R);
+    k_iface_kin_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R, 0);
+    k_iface_kin_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R, 1);
   }
   record_end(h, GKS_K_INTERFACE);
   record_begin(h);
-  k_update_2d<TS, TP><<<dim3(cdiv(nx, 256), ny), 256, 0, st>>>(g, p.phys.gamma);
+  k_update_2d<TS, TP><<<dim3(cdiv(nx, 256), ny), 256, 0, st>>>(g, p.phys);
   record_end(h, GKS_K_UPDATE);
   HIP_OR(h, hipGetLastError());
   return GKS_OK;
@@ -696,9 +847,11 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
     Problem& p = h->probs[n];
     const size_t ts = p.mixed ? sizeof(float) : sizeof(double);
     const Idx& x = p.ix;
-    void** bufs[7] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal};
-    size_t sizes[7] = {x.nW() * 8, x.nFX() * ts, x.nFY() * ts, x.nPC() * ts, x.nFLX() * 8, x.nFLY() * 8, 64};
-    for (int b = 0; b < 7; ++b) {
+    const size_t nf = n_interfaces(x);
+    void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
+    size_t sizes[9] = {x.nW() * 8, x.nFX() * ts, x.nFY() * ts, x.nPC() * ts, x.nFLX() * 8, x.nFLY() * 8, 64,
+                       (size_t)ND_REC * nf * 8, (size_t)NT_REC * nf * ts};
+    for (int b = 0; b < 9; ++b) {
       if (hipMalloc(bufs[b], sizes[b]) != hipSuccess) {
         *bufs[b] = nullptr;
         int rc = fail(h, GKS_ENOMEM, "device allocation failed");
@@ -755,7 +908,21 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       }
     }
   }
-  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+  // CFL bound of the initial state
+  for (int n = 0; n < n_problems; ++n) {
+    Problem& p = h->probs[n];
+    const unsigned long long inf = (unsigned long long)0x7e37e43c8800759cull;  // bits of 1e300
+    if (hipMemcpy((char*)p.scal + 32, &inf, 8, hipMemcpyHostToDevice) != hipSuccess) {
+      gks_destroy(h);
+      return GKS_EDEVICE;
+    }
+    const unsigned nb = cdiv((size_t)p.ix.nx * p.ix.ny, 256);
+    if (p.mixed)
+      k_dt_scan<float, float><<<nb, 256, 0, h->stream>>>(grid_of<float, float>(p), p.phys);
+    else
+      k_dt_scan<double, double><<<nb, 256, 0, h->stream>>>(grid_of<double, double>(p), p.phys);
+  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
     gks_destroy(h);
     return GKS_EDEVICE;
   }
@@ -844,7 +1011,7 @@ int gks_destroy(gks_handle* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   collect(h);
   for (Problem& p : h->probs) {
-    void* bufs[7] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal};
+    void* bufs[9] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal, p.recd, p.rect};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }

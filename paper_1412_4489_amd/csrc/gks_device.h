@@ -164,24 +164,114 @@ __device__ __forceinline__ void theta_powers(double th, T* t) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// one interface, 2D, in the interface frame (n normal, s tangential)
-//   Wc[s][v], p[s][v][0..4] = (p_n, p_s, p_nn, p_ss, p_ns): cell averages and
-//   reconstruction coefficients of the left (s = 0) and right (s = 1) cells;
-//   Ueq[m][n][v]: averages of the six cells around the interface
-//   (m: normal column, n: tangential row -1, 0, +1).
-// Outputs: flux (time- and interface-integrated), point values at the
-// tangential Gauss points -delta and +delta, heat flux (Navier-Stokes).
-// Returns false for a nonphysical interface state.
-// ---------------------------------------------------------------------------
+// Accumulators of the correction moments of one Maxwellian in its frame:
+// flux moments AF = <psi' P_F>, BF = <c psi' P_F> and point-value moments
+// V0, V1, V2 of the y^0, y^1, y^2 parts.
 template <typename TC>
-__device__ __forceinline__ bool interface_2d(const Phys& P, double dt, double hn, double hs,
-                                             const double (&Wc)[2][4], const double (&pc)[2][4][5],
-                                             const double (&Ueq)[2][3][4], double (&flux)[4],
-                                             double (&pvm)[4], double (&pvp)[4]) {
+struct Acc {
+  TC AF[4] = {0, 0, 0, 0}, BF[4] = {0, 0, 0, 0}, V0[4] = {0, 0, 0, 0}, V1[4] = {0, 0, 0, 0}, V2[4] = {0, 0, 0, 0};
+  __device__ __forceinline__ void flux(const TC* m0, const TC* m1, TC w) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      AF[v] += w * m0[v];
+      BF[v] += w * m1[v];
+    }
+  }
+  __device__ __forceinline__ void pv0(const TC* m0, TC w) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) V0[v] += w * m0[v];
+  }
+  __device__ __forceinline__ void pv1(const TC* m0, TC w) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) V1[v] += w * m0[v];
+  }
+  __device__ __forceinline__ void pv2(const TC* m0, TC w) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) V2[v] += w * m0[v];
+  }
+  // back to lab-frame moments, times rho (and the interface length for the
+  // integrated flux), added to the double-precision totals
+  template <int NV>
+  __device__ __forceinline__ void add_to(double U, double V, double rho, double hs, double delta, double* flux,
+                                         double* pvm, double* pvp, double* Edens) const {
+    TC fl[4], pm[4], pp[4];
+    const TC d = (TC)delta, d2 = (TC)(delta * delta), u = (TC)U;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      fl[v] = BF[v] + u * AF[v];
+      pm[v] = V0[v] - d * V1[v] + d2 * V2[v];
+      pp[v] = V0[v] + d * V1[v] + d2 * V2[v];
+    }
+    double a[4];
+    from_frame_2d(fl, U, V, a);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) flux[v] += hs * rho * a[v];
+    from_frame_2d(pm, U, V, a);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pvm[v] += rho * a[v];
+    from_frame_2d(pp, U, V, a);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pvp[v] += rho * a[v];
+    if (Edens) {
+      from_frame_2d(AF, U, V, a);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Edens[v] += hs * rho * a[v];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// One 2D interface is evaluated in three phases (separate kernels), so that
+// each phase holds only its own working set in registers:
+//   prologue  (double)  interface values of the two cell polynomials, their
+//                       half-space moments, U0 (eq. compatibility2), the
+//                       equilibrium quadratic (Sec. 3.3), tau (Sec. 4), the
+//                       time integrals; leading flux and point values; the
+//                       frame record of the three Maxwellians;
+//   hydro     (TC)      coefficients of g0 and the terms of eq. dis1;
+//   kinetic   (TC)      coefficients of g_k and the terms of eq. dis2 (once
+//                       per side).
+// The frame record is a structure of arrays indexed by the interface.
+// ---------------------------------------------------------------------------
+enum RecD {  // double fields
+  D_RHO0, D_U0, D_V0, D_LAM0,
+  D_RHOL, D_UL, D_VL, D_LAML, D_H0L, D_H1L,
+  D_RHOR, D_UR, D_VR, D_LAMR, D_H0R, D_H1R,
+  D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux)
+  ND_REC
+};
+enum RecT {  // compute-type fields
+  T_B0 = 0,                 // g0 targets bx, by, bxx, bxy, byy (5 x 4), peculiar frame
+  T_WH = 20,                // hydro weights (13)
+  T_BL = 33, T_BR = 53,     // side targets (5 x 4 each)
+  T_WK = 73,                // kinetic weights (12)
+  NT_REC = 85
+};
+enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
+enum KinW { KW_ICONV, KW_CCONV, KW_IQUAD, KW_CQUAD, KW_IY, KW_C7H, KW_C7, KW_CINNER, KW_AI, KW_AC, KW_TI, KW_TC };
+
+template <typename TC>
+struct Rec {
+  double* d;
+  TC* t;
+  size_t nf;
+  __device__ __forceinline__ double& D(int k, size_t f) const { return d[(size_t)k * nf + f]; }
+  __device__ __forceinline__ TC& T(int k, size_t f) const { return t[(size_t)k * nf + f]; }
+};
+
+// Prologue of interface f.  Wc[s][v], pc[s][v][0..4] = (p_n, p_s, p_nn, p_ss,
+// p_ns): averages and reconstruction coefficients of the left (s = 0) and
+// right (s = 1) cells in the interface frame; Ueq[m][n][v]: the six averages
+// around the interface.  Writes the frame record and returns the leading
+// flux (C1 g0 and C7 g_k terms) and the leading point value U0.
+template <typename TC>
+__device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, double hn, double hs,
+                                                  const double (&Wc)[2][4], const double (&pc)[2][4][5],
+                                                  const double (&Ueq)[2][3][4], const Rec<TC>& R, size_t f,
+                                                  double (&flux)[4], double (&pv)[4]) {
   const double g1 = P.gamma - 1.0;
-  // interface values and derivatives of the two cell polynomials
-  double W[2][4], Wn[2][4], Ws[2][4];
+  double W[2][4];
+  double rho[2], U[2], V[2], pr[2], lam[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const double xn = s == 0 ? 0.5 * hn : -0.5 * hn;
@@ -189,13 +279,7 @@ __device__ __forceinline__ bool interface_2d(const Phys& P, double dt, double hn
     for (int v = 0; v < 4; ++v) {
       const double* p = pc[s][v];
       W[s][v] = Wc[s][v] + p[0] * xn + p[2] * (hn * hn * (1.0 / 12.0)) - p[3] * (hs * hs * (1.0 / 24.0));
-      Wn[s][v] = p[0] + p[2] * xn;
-      Ws[s][v] = p[1] + p[4] * xn;
     }
-  }
-  double rho[2], U[2], V[2], pr[2], lam[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
     rho[s] = W[s][0];
     U[s] = W[s][1] / rho[s];
     V[s] = W[s][2] / rho[s];
@@ -203,14 +287,12 @@ __device__ __forceinline__ bool interface_2d(const Phys& P, double dt, double hn
     lam[s] = 0.5 * rho[s] / pr[s];
   }
   if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !(pr[0] > 0.0) || !(pr[1] > 0.0)) return false;
-  // U0 from the two half-space Maxwellians; free-transport flux of the sides
-  const Half hm[2] = {half_moments(U[0], lam[0], 1.0), half_moments(U[1], lam[1], -1.0)};
   double W0[4] = {0, 0, 0, 0}, Fk[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
+    const Half m = half_moments(U[s], lam[s], s == 0 ? 1.0 : -1.0);
     const double th = 0.5 / lam[s];
     const double e2 = V[s] * V[s] + (1.0 + P.K) * th;  // <v^2> + <xi^2>
-    const Half& m = hm[s];
     W0[0] += rho[s] * m.M0;
     W0[1] += rho[s] * m.M1;
     W0[2] += rho[s] * V[s] * m.M0;
@@ -219,167 +301,227 @@ __device__ __forceinline__ bool interface_2d(const Phys& P, double dt, double hn
     Fk[1] += rho[s] * m.M2;
     Fk[2] += rho[s] * V[s] * m.M1;
     Fk[3] += rho[s] * 0.5 * (m.M3 + e2 * m.M1);
+    const int o = s == 0 ? D_RHOL : D_RHOR;
+    R.D(o + 0, f) = rho[s];
+    R.D(o + 1, f) = U[s];
+    R.D(o + 2, f) = V[s];
+    R.D(o + 3, f) = lam[s];
+    R.D(o + 4, f) = m.M0;
+    R.D(o + 5, f) = m.h1;
+    // targets of the side's coefficient systems, divided by rho, in its frame
+    const double ir = 1.0 / rho[s];
+    const int tb = s == 0 ? T_BL : T_BR;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double d[4], b[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double* p = pc[s][v];
+        const double xn = s == 0 ? 0.5 * hn : -0.5 * hn;
+        // dU/dn, dU/ds, d2U/dn2, d2U/dnds, d2U/ds2 of the cell polynomial at the interface
+        d[v] = (k == 0 ? p[0] + p[2] * xn : k == 1 ? p[1] + p[4] * xn : k == 2 ? p[2] : k == 3 ? p[4] : p[3]) * ir;
+      }
+      to_frame_2d(d, U[s], V[s], b);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R.T(tb + 4 * k + v, f) = (TC)b[v];
+    }
   }
   const double rho0 = W0[0], U0 = W0[1] / rho0, V0 = W0[2] / rho0;
   const double p0 = g1 * (W0[3] - 0.5 * rho0 * (U0 * U0 + V0 * V0));
   if (!(p0 > 0.0)) return false;
   const double lam0 = 0.5 * rho0 / p0;
-  // equilibrium quadratic (Sec. 3.3): slopes / curvatures of U0 + b2 x + b3 y + ...
-  double q[5][4];
+  R.D(D_RHO0, f) = rho0;
+  R.D(D_U0, f) = U0;
+  R.D(D_V0, f) = V0;
+  R.D(D_LAM0, f) = lam0;
+  // equilibrium quadratic (Sec. 3.3) -> targets of the g0 systems
+  {
+    const double ir = 1.0 / rho0;
+    double qd[5][4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
-    const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
-    q[0][v] = ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)) / (4.0 * hn);
-    q[1][v] = (R2 - R0 + L2 - L0) / (4.0 * hs);
-    q[2][v] = (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]) / (8.0 * hn * hn);
-    q[3][v] = (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0) / (2.0 * hs * hs);
-    q[4][v] = (R2 - L2 - R0 + L0) / (2.0 * hn * hs);
+    for (int v = 0; v < 4; ++v) {
+      const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
+      const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
+      qd[0][v] = ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)) / (4.0 * hn) * ir;                          // b2: U_x
+      qd[1][v] = (R2 - R0 + L2 - L0) / (4.0 * hs) * ir;                                                // b3: U_y
+      qd[2][v] = (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]) / (8.0 * hn * hn) * ir;     // b4: U_xx
+      qd[3][v] = (R2 - L2 - R0 + L0) / (2.0 * hn * hs) * ir;                                           // b6: U_xy
+      qd[4][v] = (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0) / (2.0 * hs * hs) * ir;                     // b5: U_yy
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double b[4];
+      to_frame_2d(qd[k], U0, V0, b);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R.T(T_B0 + 4 * k + v, f) = (TC)b[v];
+    }
   }
-  // collision time (Sec. 4)
+  // collision time (Sec. 4) and the time weights
   const double jump = fabs((pr[0] - pr[1]) / (pr[0] + pr[1]));
   const double tau = P.viscous ? P.mu / p0 + P.tau_c * jump * dt : (P.tau_eps + P.tau_c * jump) * dt;
   TimeWeights w;
   time_weights(tau, dt, w);
-  // leading terms: Euler flux of U0 and free transport of the sides
-  {
-    const double pe = p0;
-    const double FE[4] = {W0[1], W0[1] * U0 + pe, W0[1] * V0, U0 * (W0[3] + pe)};
+  const double hs2 = hs * hs * (1.0 / 24.0);
+  const double hw[13] = {w.I[2], w.I[3], 0.5 * w.I[4], 0.5 * w.I[5], w.I[6], w.I[1] * hs2, w.C[2],
+                         w.C[3], 0.5 * w.C[4], 0.5 * w.C[5], w.C[6], w.C[1], 0.5 * w.C[1]};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      flux[v] = hs * (w.I[1] * FE[v] + w.I[7] * Fk[v]);
-      pvm[v] = W0[v];
-      pvp[v] = W0[v];
-    }
-  }
-  double Edens[4];  // time- and interface-integrated <psi f> (for the heat flux)
+  for (int k = 0; k < 13; ++k) R.T(T_WH + k, f) = (TC)hw[k];
+  const double tv = P.viscous ? tau : 0.0;  // Euler: f_G = g_k
+  const double kw[12] = {w.I[8] - tv * w.I[7],       w.C[8] - tv * w.C[7],       0.5 * w.I[10] - tv * w.I[8],
+                         0.5 * w.C[10] - tv * w.C[8], w.I[7] * hs2,               0.5 * w.C[7],
+                         w.C[7],                      -w.C[9] - tv * w.C[7],      -tau * w.I[7],
+                         -tau * w.C[7],               -tau * w.I[8],              -tau * w.C[8]};
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Edens[v] = hs * dt * W0[v];
-
-  TC kp[4];
+  for (int k = 0; k < 12; ++k) R.T(T_WK + k, f) = (TC)kw[k];
+  // leading terms: Euler flux of U0 (C1 g0) and free transport of the sides (C7 g_k)
+  const double FE[4] = {W0[1], W0[1] * U0 + p0, W0[1] * V0, U0 * (W0[3] + p0)};
 #pragma unroll
-  for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
-  const TC nth = (TC)P.nth;
-  const double delta = kGaussOffset * hs;
-
-  // ---- hydrodynamic part, g0 -------------------------------------------
-  {
-    TC th[5];
-    theta_powers(0.5 / lam0, th);
-    const double ir = 1.0 / rho0;
-    TC bx[4], by[4], bxx[4], bxy[4], byy[4];
-    frame_rhs_2d(q[0], ir, U0, V0, bx);
-    frame_rhs_2d(q[1], ir, U0, V0, by);
-    frame_rhs_2d(q[2], ir, U0, V0, bxx);
-    frame_rhs_2d(q[4], ir, U0, V0, bxy);
-    frame_rhs_2d(q[3], ir, U0, V0, byy);
-    TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
-    coef_g0_2d<TC>(th, kp, nth, (TC)U0, (TC)V0, bx, by, bxx, bxy, byy, ax, ay, At, dxx, dxy, dyy, bxt, byt, Bt);
-    TC wI[7], wC[7];
-#pragma unroll
-    for (int k = 1; k < 7; ++k) {
-      wI[k] = (TC)w.I[k];
-      wC[k] = (TC)w.C[k];
-    }
-    const TC wI1y = (TC)(w.I[1] * hs * hs * (1.0 / 24.0));
-    TC AF[4], BF[4], V0m[4], V1m[4], V2m[4];
-    hydro_2d<TC>(th, kp, (TC)U0, (TC)V0, ax, ay, At, dxx, dxy, dyy, bxt, byt, Bt, wI, wI1y, wC, AF, BF, V0m, V1m,
-                 V2m);
-    TC fl[4], pm[4], pp[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      fl[v] = BF[v] + (TC)U0 * AF[v];
-      pm[v] = V0m[v] - (TC)delta * V1m[v] + (TC)(delta * delta) * V2m[v];
-      pp[v] = V0m[v] + (TC)delta * V1m[v] + (TC)(delta * delta) * V2m[v];
-    }
-    double a[4];
-    from_frame_2d(fl, U0, V0, a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) flux[v] += hs * rho0 * a[v];
-    from_frame_2d(pm, U0, V0, a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) pvm[v] += rho0 * a[v];
-    from_frame_2d(pp, U0, V0, a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) pvp[v] += rho0 * a[v];
-    if (P.viscous) {
-      from_frame_2d(AF, U0, V0, a);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Edens[v] += hs * rho0 * a[v];
-    }
-  }
-
-  // ---- kinetic parts of the two sides ----------------------------------
-  const TC kI8 = (TC)w.I[8], kI72 = (TC)(0.5 * w.I[10]), kI7y = (TC)(w.I[7] * hs * hs * (1.0 / 24.0));
-  const TC kI7tau = (TC)(tau * w.I[7]), kI8tau = (TC)(tau * w.I[8]);
-  const TC kC8 = (TC)w.C[8], kC72 = (TC)(0.5 * w.C[10]), kC7 = (TC)w.C[7], kC7t = (TC)w.C[9];
-  const TC kC7tau = (TC)(tau * w.C[7]), kC8tau = (TC)(tau * w.C[8]);
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    TC th[5];
-    theta_powers(0.5 / lam[s], th);
-    const double ir = 1.0 / rho[s];
-    TC bx[4], by[4], bxx[4], bxy[4], byy[4];
-    {
-      double dnn[4], dns[4], dss[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        dnn[v] = pc[s][v][2];
-        dns[v] = pc[s][v][4];
-        dss[v] = pc[s][v][3];
-      }
-      frame_rhs_2d(Wn[s], ir, U[s], V[s], bx);
-      frame_rhs_2d(Ws[s], ir, U[s], V[s], by);
-      frame_rhs_2d(dnn, ir, U[s], V[s], bxx);
-      frame_rhs_2d(dns, ir, U[s], V[s], bxy);
-      frame_rhs_2d(dss, ir, U[s], V[s], byy);
-    }
-    TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
-    TC h[10];
-    half_table(hm[s], U[s], lam[s], h);
-    TC AF[4], BF[4], V0m[4], V1m[4], V2m[4];
-    if (P.viscous) {
-      coef_side_ns_2d<TC>(th, kp, nth, (TC)U[s], (TC)V[s], bx, by, bxx, bxy, byy, ax, ay, At, dxx, dxy, dyy, bxt,
-                          byt, Bt);
-      kin_ns_2d<TC>(th, kp, h, (TC)U[s], (TC)V[s], ax, ay, At, dxx, dxy, dyy, bxt, byt, kI8, kI72, kI7y, kI7tau,
-                    kI8tau, kC8, kC72, kC7, kC7t, kC7tau, kC8tau, AF, BF, V0m, V1m, V2m);
-    } else {
-      coef_side_euler_2d<TC>(th, kp, nth, (TC)U[s], (TC)V[s], bx, by, bxx, bxy, byy, ax, ay, At, dxx, dxy, dyy,
-                             bxt, byt, Bt);
-      kin_euler_2d<TC>(th, kp, h, (TC)U[s], (TC)V[s], ax, ay, At, dxx, dxy, dyy, bxt, byt, kI8, kI72, kI7y, kI7tau,
-                       kI8tau, kC8, kC72, kC7, kC7t, kC7tau, kC8tau, AF, BF, V0m, V1m, V2m);
-    }
-    TC fl[4], pm[4], pp[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      fl[v] = BF[v] + (TC)U[s] * AF[v];
-      pm[v] = V0m[v] - (TC)delta * V1m[v] + (TC)(delta * delta) * V2m[v];
-      pp[v] = V0m[v] + (TC)delta * V1m[v] + (TC)(delta * delta) * V2m[v];
-    }
-    double a[4];
-    from_frame_2d(fl, U[s], V[s], a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) flux[v] += hs * rho[s] * a[v];
-    from_frame_2d(pm, U[s], V[s], a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) pvm[v] += rho[s] * a[v];
-    from_frame_2d(pp, U[s], V[s], a);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) pvp[v] += rho[s] * a[v];
-    if (P.viscous) {
-      from_frame_2d(AF, U[s], V[s], a);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Edens[v] += hs * rho[s] * a[v];
-    }
-  }
-  if (P.viscous) {
-    // heat flux relative to the velocity of g0, added with weight 1/Pr - 1
-    const double k2 = 0.5 * (U0 * U0 + V0 * V0);
-    const double qh = flux[3] - U0 * flux[1] - V0 * flux[2] + k2 * flux[0] -
-                      U0 * (Edens[3] - U0 * Edens[1] - V0 * Edens[2] + k2 * Edens[0]);
-    flux[3] += P.prfix * qh;
+  for (int v = 0; v < 4; ++v) {
+    flux[v] = hs * (w.I[1] * FE[v] + w.I[7] * Fk[v]);
+    pv[v] = W0[v];  // C1 + C7 = 1
+    R.D(D_E0 + v, f) = hs * dt * W0[v];
   }
   return true;
+}
+
+// coefficient-set arrays of one Maxwellian (peculiar frame)
+template <typename TC>
+struct Coefs {
+  TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
+};
+
+// Hydrodynamic phase of interface f: corrections to flux, point values and
+// the integrated density (lab frame, interface frame components).
+template <typename TC>
+__device__ __forceinline__ void iface_hydro_2d(const Phys& P, double hs, const Rec<TC>& R, size_t f,
+                                               double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
+                                               double (&E)[4]) {
+  const double rho0 = R.D(D_RHO0, f), U0 = R.D(D_U0, f), V0 = R.D(D_V0, f), lam0 = R.D(D_LAM0, f);
+  TC th[5], kp[4];
+  theta_powers(0.5 / lam0, th);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
+  const TC u0 = (TC)U0, v0 = (TC)V0;
+  Coefs<TC> c;
+  {
+    TC b[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[k][v] = R.T(T_B0 + 4 * k + v, f);
+    coef_g0_2d<TC>(th, kp, (TC)P.nth, u0, v0, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy, c.dyy,
+                   c.bxt, c.byt, c.Bt);
+  }
+  TC w[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) w[k] = R.T(T_WH + k, f);
+  Acc<TC> A;
+  TC m0[4], m1[4];
+  // C2 g0 (a1 u + a2 v)
+  mom_full_conv_2d<TC>(th, kp, u0, v0, c.ax, c.ay, m0, m1);
+  A.flux(m0, m1, w[HW_I2]);
+  A.pv0(m0, w[HW_C2]);
+  // C3 g0 A
+  mom_full_A_2d<TC>(th, kp, u0, v0, c.At, m0, m1);
+  A.flux(m0, m1, w[HW_I3]);
+  A.pv0(m0, w[HW_C3]);
+  // 1/2 C4 g0 [(a1^2 + d11) u^2 + 2 (a1 a2 + d12) u v + (a2^2 + d22) v^2]
+  mom_full_quad_2d<TC>(th, kp, u0, v0, c.ax, c.ay, c.dxx, c.dxy, c.dyy, m0, m1);
+  A.flux(m0, m1, w[HW_I4H]);
+  A.pv0(m0, w[HW_C4H]);
+  // 1/2 C5 g0 (A^2 + B)
+  mom_full_ttt_2d<TC>(th, kp, u0, v0, c.At, c.Bt, m0, m1);
+  A.flux(m0, m1, w[HW_I5H]);
+  A.pv0(m0, w[HW_C5H]);
+  // C6 g0 [(A a1 + b1) u + (A a2 + b2) v]
+  mom_full_tlin_2d<TC>(th, kp, u0, v0, c.ax, c.ay, c.At, c.bxt, c.byt, m0, m1);
+  A.flux(m0, m1, w[HW_I6]);
+  A.pv0(m0, w[HW_C6]);
+  // 1/2 C1 g0 (a2^2 + d22) y^2: int y^2 dy over the interface = ds^3/12
+  mom_full_dyy_2d<TC>(th, kp, u0, v0, c.ay, c.dyy, m0, m1);
+  A.flux(m0, m1, w[HW_I1Y]);
+  A.pv2(m0, w[HW_C1H]);
+  // terms linear in y vanish in the flux; point values:
+  // C1 g0 a2 y + C2 g0 [(a2^2 + d22) v + (a1 a2 + d12) u] y + C3 g0 (A a2 + b2) y
+  mom_full_ay_2d<TC>(th, kp, u0, v0, c.ay, m0);
+  A.pv1(m0, w[HW_C1]);
+  mom_full_inner_2d<TC>(th, kp, u0, v0, c.ax, c.ay, c.dxy, c.dyy, m0);
+  A.pv1(m0, w[HW_C2]);
+  mom_full_ty_2d<TC>(th, kp, u0, v0, c.ay, c.At, c.byt, m0);
+  A.pv1(m0, w[HW_C3]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) flux[v] = pvm[v] = pvp[v] = E[v] = 0.0;
+  A.template add_to<4>(U0, V0, rho0, hs, kGaussOffset * hs, flux, pvm, pvp, P.viscous ? E : nullptr);
+}
+
+// Kinetic phase of interface f, side s (0: g_l on u > 0, 1: g_r on u < 0).
+template <typename TC>
+__device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double hs, int s, const Rec<TC>& R, size_t f,
+                                                 double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
+                                                 double (&E)[4]) {
+  const int o = s == 0 ? D_RHOL : D_RHOR;
+  const double rho = R.D(o, f), U = R.D(o + 1, f), V = R.D(o + 2, f), lam = R.D(o + 3, f);
+  Half hm;
+  hm.M0 = R.D(o + 4, f);
+  hm.h1 = R.D(o + 5, f);
+  TC th[5], kp[4], h[10];
+  theta_powers(0.5 / lam, th);
+  half_table(hm, U, lam, h);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
+  const TC us = (TC)U, vs = (TC)V;
+  Coefs<TC> c;
+  {
+    const int tb = s == 0 ? T_BL : T_BR;
+    TC b[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[k][v] = R.T(tb + 4 * k + v, f);
+    if (P.viscous)
+      coef_side_ns_2d<TC>(th, kp, (TC)P.nth, us, vs, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy,
+                          c.dyy, c.bxt, c.byt, c.Bt);
+    else
+      coef_side_euler_2d<TC>(th, kp, (TC)P.nth, us, vs, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx,
+                             c.dxy, c.dyy, c.bxt, c.byt, c.Bt);
+  }
+  TC w[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) w[k] = R.T(T_WK + k, f);
+  Acc<TC> A;
+  TC m0[4], m1[4];
+  // C8 g (a1 u + a2 v)  [and -tau C7 g (a1 u + a2 v)]
+  mom_half_conv_2d<TC>(th, kp, h, us, vs, c.ax, c.ay, m0, m1);
+  A.flux(m0, m1, w[KW_ICONV]);
+  A.pv0(m0, w[KW_CCONV]);
+  // 1/2 C7 t^2 g [(a1^2+d11) u^2 + 2 (a1 a2+d12) u v + (a2^2+d22) v^2]  [and -tau C8 g (same)]
+  mom_half_quad_2d<TC>(th, kp, h, us, vs, c.ax, c.ay, c.dxx, c.dxy, c.dyy, m0, m1);
+  A.flux(m0, m1, w[KW_IQUAD]);
+  A.pv0(m0, w[KW_CQUAD]);
+  // 1/2 C7 g (a2^2 + d22) y^2
+  mom_half_dyy_2d<TC>(th, kp, h, us, vs, c.ay, c.dyy, m0, m1);
+  A.flux(m0, m1, w[KW_IY]);
+  A.pv2(m0, w[KW_C7H]);
+  // point values, linear in y: C7 g a2 y - C7 t g [(a1 a2+d12) u + (a2^2+d22) v] y
+  //   [and -tau C7 g ((a1 a2+d12) u + (a2^2+d22) v + A a2 + b2) y]
+  mom_half_ay_2d<TC>(th, kp, h, us, vs, c.ay, m0);
+  A.pv1(m0, w[KW_C7]);
+  mom_half_inner_2d<TC>(th, kp, h, us, vs, c.ax, c.ay, c.dxy, c.dyy, m0);
+  A.pv1(m0, w[KW_CINNER]);
+  if (P.viscous) {
+    // -tau C7 g A, -tau C8 g [(A a1 + b1) u + (A a2 + b2) v], -tau C7 g (A a2 + b2) y
+    mom_half_A_2d<TC>(th, kp, h, us, vs, c.At, m0, m1);
+    A.flux(m0, m1, w[KW_AI]);
+    A.pv0(m0, w[KW_AC]);
+    mom_half_tlin_2d<TC>(th, kp, h, us, vs, c.ax, c.ay, c.At, c.bxt, c.byt, m0, m1);
+    A.flux(m0, m1, w[KW_TI]);
+    A.pv0(m0, w[KW_TC]);
+    mom_half_ty_2d<TC>(th, kp, h, us, vs, c.ay, c.At, c.byt, m0);
+    A.pv1(m0, w[KW_AC]);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) flux[v] = pvm[v] = pvp[v] = E[v] = 0.0;
+  A.template add_to<4>(U, V, rho, hs, kGaussOffset * hs, flux, pvm, pvp, P.viscous ? E : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,6 +580,27 @@ __device__ __forceinline__ void recon_2d(double c, double e, double w, double n,
   p[2] = w1 * a4 + w2 * c4;
   p[3] = w1 * a5 + w2 * c5;
   p[4] = w1 * a6 + w2 * c6;
+}
+
+// true if the cell polynomial Wc + p2 x + p3 y + p4 w_x + p5 w_y + p6 x y
+// (per conservative variable) has rho > 0 and p > 0 at the centres of the
+// four interfaces of the cell
+__device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const double (&p)[4][5], double h,
+                                                    double k, double gamma) {
+  bool ok = true;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const double x = f == 0 ? 0.5 * h : f == 1 ? -0.5 * h : 0.0;
+    const double y = f == 2 ? 0.5 * k : f == 3 ? -0.5 * k : 0.0;
+    double W[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      W[v] = Wc[v] + p[v][0] * x + p[v][1] * y + p[v][2] * 0.5 * (x * x - h * h / 12.0) +
+             p[v][3] * 0.5 * (y * y - k * k / 12.0) + p[v][4] * x * y;
+    const double pr = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+    ok = ok && (W[0] > 0.0) && (pr > 0.0);
+  }
+  return ok;
 }
 
 }  // namespace gks
