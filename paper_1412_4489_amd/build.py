@@ -26,20 +26,21 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
     os.makedirs(LIB_DIR, exist_ok=True)
+    lib = out or LIB
     cmd = [hipcc(), "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-shared",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result", "-o", LIB + ".tmp", SRC]
+           "-Wno-unused-result"] + [f"-D{d}" for d in defines] + ["-o", lib + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
