@@ -44,6 +44,56 @@ KIN_TERMS_EULER = ("conv", "quad", "dyy", "ay", "inner")
 KIN_TERMS_NS = KIN_TERMS_EULER + ("A", "tlin", "ty")
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_iface_vortex256_fp32mixed.json")
+KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
+
+
+def source_hash():
+    """Hash of the kernel sources: a stored counter record is valid only for them."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_4489_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record():
+    """HBM bytes per launch set of the interface kernels from the committed
+    counter record (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    factors), or None if there is none for the present kernel sources."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch_set")
+
+
+def pmc_probe():
+    """Workload for counter collection: a plain 256 MiB device copy (the
+    calibration of FETCH_SIZE / WRITE_SIZE), then the tuned FP32-mixed 256^2
+    vortex for a few steps with eager launches."""
+    import torch
+    from paper_1412_4489_amd import gks
+    from paper_1412_4489_amd import workloads as W
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    prob, st = W.vortex_2d(N)
+    with gks.Solver(prob, st, gks.GKS_FP32_MIXED, stream=torch.cuda.current_stream().cuda_stream) as S:
+        S.tune(3)
+        gks.gks_profile(S.h, 1)
+        S.step(5)
+        S.fetch()
+    torch.cuda.synchronize()
+    print("pmc probe done", flush=True)
+
+
 def interface_flops(viscous=False):
     """Floating-point operations of one 2D interface: the generated coefficient
     systems and term moments of g0 and of the two sides, plus the prologue."""
@@ -55,39 +105,39 @@ def interface_flops(viscous=False):
     return hydro + 2 * kin + PROLOGUE_FLOPS
 
 
-def run_gpu(precision, steps, warmup):
+def run_gpu(precision, steps, warmup, items=None):
+    """Times `steps` steps of the given problems (default: the 256^2 vortex)
+    after autotuning the launch shapes: once with HIP events around every
+    kernel class (kernel times), once as plain graph replays (wall time)."""
     import torch
     from paper_1412_4489_amd import gks
     from paper_1412_4489_amd import workloads as W
 
-    prob, st = W.vortex_2d(N)
+    if items is None:
+        items = [W.vortex_2d(N)]
+    probs, states = [p for p, _ in items], [s for _, s in items]
     stream = torch.cuda.current_stream().cuda_stream
-    S = gks.Solver(prob, st, precision, stream=stream)
+    S = gks.Solver(probs, states, precision, stream=stream)
+    sizes = S.tune(3)
     S.step(warmup)
     torch.cuda.synchronize()
     gks.gks_profile(S.h, 1)
     gks.gks_profile(S.h, 2)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     S.step(steps)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     gks.gks_profile(S.h, 0)
     kt = {k: gks.gks_kernel_time(S.h, k) for k in gks.KERNELS}
-    S.fetch()  # raises if the run produced a nonphysical state
-    S.close()
-    # the profiled run records events around every launch; time it again
-    # without events for the wall-clock figure
-    S = gks.Solver(prob, st, precision, stream=stream)
     S.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.step(steps)
     torch.cuda.synchronize()
-    wall_plain = time.perf_counter() - t0
-    S.fetch()
+    wall = time.perf_counter() - t0
+    for k in range(len(probs)):
+        S.fetch(k)  # raises if the run produced a nonphysical state
     S.close()
-    return min(wall, wall_plain), kt, prob
+    return wall, kt, probs, sizes
 
 
 def gpu_fixed_steps(precision, nsteps, dt):
@@ -123,6 +173,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 96-grid batched form")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only run the copy calibration and a few vortex steps (for rocprofv3 --pmc)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the method's single-GPU path); "
@@ -133,19 +186,23 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.pmc_probe:
+        pmc_probe()
+        return
     from paper_1412_4489_amd import gks
 
     res = {}
     for name, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
-        wall, kt, prob = run_gpu(prec, a.steps, a.warmup)
-        res[name] = (wall, kt, prob)
-        print(f"# {name}: {a.steps} steps in {wall * 1e3:.2f} ms; kernel ms: "
+        res[name] = run_gpu(prec, a.steps, a.warmup)
+        wall, kt, _, sizes = res[name]
+        print(f"# {name}: {a.steps} steps in {wall * 1e3:.2f} ms; block sizes {sizes}; kernel ms: "
               + ", ".join(f"{k} {v[0]:.2f} ({v[1]})" for k, v in kt.items()), file=sys.stderr, flush=True)
 
-    wall, kt, prob = res["fp32_mixed"]
+    wall, kt, probs, _ = res["fp32_mixed"]
+    prob = probs[0]
     cells = prob.ncells
     value = cells * a.steps / wall / 1e6
-    wall64, kt64, _ = res["fp64"]
+    wall64, kt64, _, _ = res["fp64"]
     value64 = cells * a.steps / wall64 / 1e6
     n_if = (prob.nx + 1) * prob.ny + prob.nx * (prob.ny + 1)
     fl = interface_flops(False) * n_if
@@ -154,6 +211,25 @@ def main():
     achieved = fl / t_if
     ms64, nl64 = kt64["interface"]
     achieved64 = fl / (ms64 / 1e3 / max(nl64, 1))
+
+    batched = None
+    if not a.no_batch:
+        from paper_1412_4489_amd import workloads as W
+        items = W.batch()
+        bsteps = max(2, a.steps // 10)
+        bwall, bkt, bprobs, bsizes = run_gpu(gks.GKS_FP32_MIXED, bsteps, 2, items)
+        bcells = sum(p.ncells for p in bprobs)
+        batched = {"value": round(bcells * bsteps / bwall / 1e6, 3), "unit": "Mcell-updates/s",
+                   "problems": len(bprobs), "cells": bcells, "steps": bsteps,
+                   "ms_per_step": round(bwall / bsteps * 1e3, 4),
+                   "viscous": sum(bool(p.viscous) for p in bprobs),
+                   "interface_ms": round(bkt["interface"][0] / max(bkt["interface"][1], 1), 4),
+                   "block_sizes": bsizes,
+                   "workload": "96 grids (isentropic vortex 1/2, 2D Riemann cases 1 and 2 1/4 each), n^2 cells with "
+                               "n in {64,96,128,192,256,384}, Euler or Navier-Stokes (Re 100-5000), seed 14124489, "
+                               "GKS_FP32_MIXED, one launch per phase for all grids, one hipGraph per step"}
+        print(f"# batched: {bsteps} steps of {len(bprobs)} grids ({bcells} cells) in {bwall * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
 
     out = {
         "metric": "Mcell-updates/s (FP32 & batched vs FP64) at stated L1 err vs oracle",
@@ -173,9 +249,11 @@ def main():
         "fp64": {"value": round(value64, 3), "ms_per_step": round(wall64 / a.steps * 1e3, 5),
                  "interface_ms": round(ms64 / max(nl64, 1), 5),
                  "interface_tflops": round(achieved64 / 1e12, 3)},
+        "batched": batched,
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
-                     "kernel": "k_iface_{pro,hydro,kin}_2d<float> (one launch set per step)", "flops_per_interface": interface_flops(False),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": traffic_record(),
+                     "kernel": "k_iface_{pro,hydro,kin}_2d<float> (one launch set per step)",
+                     "flops_per_interface": interface_flops(False),
                      "interface_ms": round(t_if * 1e3, 5)},
     }
     if not a.no_cpu:

@@ -147,6 +147,20 @@ enum { GKS_K_GHOST = 0, GKS_K_DT = 1, GKS_K_RECON = 2, GKS_K_INTERFACE = 3, GKS_
 int gks_profile(gks_handle* h, int32_t mode);
 int gks_kernel_time(gks_handle* h, int32_t kernel, double* ms, int64_t* launches);
 
+/* Autotuner of the launch shapes (not part of the method): every kernel class
+ * of the handle's launch sequence is timed with 64, 128 and 256 threads per
+ * block over `steps` steps (1..1000) of the handle's own problems, with HIP
+ * events as above, and the fastest size is kept per class.  The averages,
+ * point values, times and step counts are restored afterwards, so the call
+ * does not advance any problem; results of later steps are bitwise those of
+ * any block size (each thread's arithmetic does not depend on it).  Returns
+ * GKS_EINVAL, GKS_ESTATE, GKS_ENOMEM or GKS_EDEVICE (the latter two leave the
+ * handle in its error state).
+ * gks_block_size reports the present block size of kernel class `kernel`
+ * (GKS_K_*; the CFL kernel always uses 64). */
+int gks_tune(gks_handle* h, int32_t steps);
+int gks_block_size(gks_handle* h, int32_t kernel, int32_t* threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,24 +1,33 @@
 // gks.hip -- kernels and C-ABI host library of the compact third-order
 // gas-kinetic scheme (Pan & Xu, arXiv:1412.4489) for MI355X (gfx950).
 //
-// Per problem and step (all on one HIP stream, no host synchronisation):
-//   k_ghost_we / k_ghost_sn  boundary images (cells: two layers incl. corners;
-//                            interface point values of the edge ghost cells)
-//   k_dt / k_set_dt          CFL time step (one block) or the fixed step
-//   k_recon_2d               compact reconstruction of interior and edge
-//                            ghost cells -> p2..p6 per variable (Sec. 3.2)
-//   k_interfaces_2d          every x and y interface: flux and new point values
-//                            (Sec. 2.2, 3.3, 4)
-//   k_update_2d              conservative update (eq. finite), nonphysical-state
-//                            flag, time and step counters
+// A handle holds any number of independent grids ("problems").  Problems of
+// the same dimension and precision form a group; one time step of a group is
+// a fixed sequence of launches, each covering every problem of the group
+// (a block-owner table maps each block to its problem and tile):
+//   2D: k_ghost_we, k_ghost_sn   boundary images (cells: two layers incl.
+//                                corners; interface values of edge ghosts)
+//       k_dt                     CFL time step or the fixed step, per problem
+//       k_recon_2d               compact reconstruction (Sec. 3.2)
+//       k_iface_pro_2d           interface prologue: U0, equilibrium quadratic,
+//                                tau, time integrals, leading terms (double)
+//       k_iface_hydro_2d         eq. dis1 corrections (g0)
+//       k_iface_kin_2d (x2)      eq. dis2 corrections (g_l on u > 0, g_r on u < 0)
+//       k_update_2d              conservative update (eq. finite), nonphysical
+//                                flag, CFL bound of the new state
+//   1D: k_ghost_1d, k_dt, k_recon_1d, k_face_1d (fused interface), k_update_1d
+// The step of all groups is captured once in a hipGraph and replayed.
 //
-// Memory (per problem, structure of arrays, x fastest):
-//   W  double [4][ny+4][nx+4]           cell averages with two ghost layers
-//   FX TS     [2][4][ny+2][nx+3]        x-interface Gauss values, interfaces -1..nx+1, rows -1..ny
-//   FY TS     [2][4][ny+3][nx+2]        y-interface Gauss values, interfaces -1..ny+1, cols -1..nx
-//   PC TP     [4][5][ny+2][nx+2]        reconstruction coefficients, cells -1..nx
-//   FLX double [4][ny][nx+1], FLY double [4][ny+1][nx]  integrated fluxes
-// TS = TP = double (GKS_FP64) or float (GKS_FP32_MIXED).
+// Memory per 2D problem (structure of arrays, x fastest):
+//   W   double [4][ny+4][nx+4]      cell averages with two ghost layers
+//   FX  TS     [2][4][ny+2][nx+3]   x-interface Gauss values, interfaces -1..nx+1, rows -1..ny
+//   FY  TS     [2][4][ny+3][nx+2]   y-interface Gauss values, interfaces -1..ny+1, cols -1..nx
+//   PC  TP     [4][5][ny+2][nx+2]   reconstruction coefficients, cells -1..nx
+//   FLX double [4][ny][nx+1], FLY double [4][ny+1][nx]   integrated fluxes
+//   frame record of the interfaces (20 doubles + 85 TC each)
+// per 1D problem: W double [3][nx+4], FX TS [3][nx+3] (interfaces -1..nx+1),
+//   PC TP [3][2][nx+2], FLX double [3][nx+1].
+// TS = TP = TC = double (GKS_FP64) or float (GKS_FP32_MIXED).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -55,12 +64,11 @@ struct Idx {
   }
   __device__ __host__ size_t flx(int v, int j, int fi) const { return ((size_t)v * ny + j) * (nx + 1) + fi; }
   __device__ __host__ size_t fly(int v, int fj, int i) const { return ((size_t)v * (ny + 1) + fj) * nx + i; }
-  size_t nW() const { return (size_t)4 * (ny + 4) * (nx + 4); }
-  size_t nFX() const { return (size_t)2 * 4 * (ny + 2) * (nx + 3); }
-  size_t nFY() const { return (size_t)2 * 4 * (ny + 3) * (nx + 2); }
-  size_t nPC() const { return (size_t)4 * 5 * (ny + 2) * (nx + 2); }
-  size_t nFLX() const { return (size_t)4 * ny * (nx + 1); }
-  size_t nFLY() const { return (size_t)4 * (ny + 1) * nx; }
+  // 1D layouts (ny = 1)
+  __device__ __host__ size_t w1(int v, int i) const { return (size_t)v * (nx + 4) + (size_t)(i + 2); }
+  __device__ __host__ size_t f1(int v, int fi) const { return (size_t)v * (nx + 3) + (size_t)(fi + 1); }
+  __device__ __host__ size_t pc1(int v, int m, int i) const { return ((size_t)v * 2 + m) * (nx + 2) + (size_t)(i + 1); }
+  __device__ __host__ size_t fl1(int v, int fi) const { return (size_t)v * (nx + 1) + fi; }
 };
 
 struct BCDev {
@@ -84,38 +92,77 @@ struct Grid {
   TP* PC;
   double* FLX;
   double* FLY;
-  double* t;      // time
-  double* dt;     // step of the current step
+  double* t;                  // time
+  double* dt;                 // step of the current step
   long long* steps;
-  unsigned long long* err;
-  unsigned long long* dtmin;  // running minimum of the CFL bound (double bits)  // 0, or 1 + (j+1) * 65536 * 65536 + (i+1) * 65536 ... of the first bad cell
+  unsigned long long* err;    // 0, or the location of the first nonphysical state (see gks_fetch)
+  unsigned long long* dtmin;  // running minimum of the CFL bound (bits of a positive double)
 };
+
+// work decomposition of one launch kind over the problems of a group
+enum Kind { KK_GA = 0, KK_GB, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };
+
+// device descriptor of one problem, read by every kernel
+template <typename TS, typename TP, typename TC>
+struct Prob {
+  Grid<TS, TP> g;
+  Phys P;
+  BCDev bc[4];
+  Rec<TC> R;
+  int recon_vars;            // 1D: 0 conservative, 1 characteristic variables
+  unsigned first[KK_COUNT];  // first logical block of the problem in each kind's launch
+};
+
+// kernel argument: the group's descriptors and the block-owner table of one kind
+template <class PR>
+struct KA {
+  const PR* __restrict__ probs;
+  const uint16_t* __restrict__ owner;
+  unsigned nblk;
+};
+
+// Blocks are dispatched round robin over the eight XCDs (each with its own
+// L2); logical blocks are assigned so that every XCD works on a contiguous
+// range of tiles (neighbouring rows share stencil data in its L2).  The map
+// is a bijection of [0, nblk).
+__device__ __forceinline__ unsigned logical_block(unsigned nblk) {
+  const unsigned b = blockIdx.x, per = nblk >> 3, rem = nblk & 7u, xcd = b & 7u, idx = b >> 3;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <class PR>
+__device__ __forceinline__ const PR& locate(const KA<PR>& a, int kind, int& local) {
+  const unsigned L = logical_block(a.nblk);
+  const PR& Q = a.probs[a.owner[L]];
+  local = (int)((L - Q.first[kind]) * blockDim.x + threadIdx.x);
+  return Q;
+}
 
 // ---------------------------------------------------------------------------
 // boundary images
 // ---------------------------------------------------------------------------
 
 // fixed state at location (x, y) at time t; false where the boundary mirrors
-__device__ bool bc_fixed(const BCDev& b, double x, double y, double t, double* out) {
+__device__ bool bc_fixed(const BCDev& b, int nv, double x, double y, double t, double* out) {
   if (b.kind == GKS_BC_INFLOW) {
-    for (int v = 0; v < 4; ++v) out[v] = b.state[v];
+    for (int v = 0; v < nv; ++v) out[v] = b.state[v];
     return true;
   }
   if (b.kind == GKS_BC_DMR_BOTTOM) {
     if (!(x < 1.0 / 6.0)) return false;
-    for (int v = 0; v < 4; ++v) out[v] = b.state[v];
+    for (int v = 0; v < nv; ++v) out[v] = b.state[v];
     return true;
   }
   if (b.kind == GKS_BC_DMR_TOP) {
     const double xs = 1.0 / 6.0 + (y + 20.0 * t) * 0.57735026918962576451;
     const double* src = x < xs ? b.state : b.alt;
-    for (int v = 0; v < 4; ++v) out[v] = src[v];
+    for (int v = 0; v < nv; ++v) out[v] = src[v];
     return true;
   }
   return false;
 }
 
-// mirror image of a state across a boundary with normal `axis`
+// mirror image of a 2D state across a boundary with normal `axis`
 __device__ void bc_mirror(const BCDev& b, int axis, double gamma, const double* s, double* o) {
   for (int v = 0; v < 4; ++v) o[v] = s[v];
   const int kind = b.kind;
@@ -134,22 +181,42 @@ __device__ void bc_mirror(const BCDev& b, int axis, double gamma, const double* 
   }
 }
 
+// mirror image of a 1D state (rho, rho u, rho E)
+__device__ void bc_mirror_1d(const BCDev& b, double gamma, const double* s, double* o) {
+  for (int v = 0; v < 3; ++v) o[v] = s[v];
+  const int kind = b.kind;
+  if (kind == GKS_BC_REFLECT) {
+    o[1] = -s[1];
+  } else if (kind == GKS_BC_NOSLIP_ISOTHERMAL || kind == GKS_BC_NOSLIP_ADIABATIC) {
+    const double rho = s[0], u = s[1] / rho;
+    const double T = (gamma - 1.0) * (s[2] - 0.5 * rho * u * u) / rho;
+    const double Tg = kind == GKS_BC_NOSLIP_ISOTHERMAL ? 2.0 * b.wT - T : T;
+    const double ug = 2.0 * b.wu - u;
+    o[0] = rho;
+    o[1] = rho * ug;
+    o[2] = rho * Tg / (gamma - 1.0) + 0.5 * rho * ug * ug;
+  }
+}
+
 // West (side 0) / east (side 1): ghost cells of rows 0..ny-1, ghost x
 // interfaces -1 / nx+1, and the y interfaces of the ghost columns -1 / nx.
-template <typename TS, typename TP>
-__global__ void k_ghost_we(Grid<TS, TP> g, BCDev bw, BCDev be, double gamma) {
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_ghost_we(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+  const Grid<TS, TP> g = Q.g;
+  const double gamma = Q.P.gamma;
   const int nx = g.ix.nx, ny = g.ix.ny;
   const int ncell = 2 * ny * 2, nfx = 2 * ny * 2, nfy = 2 * (ny + 1) * 2;
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= ncell + nfx + nfy) return;
   const double t = *g.t, h = g.geo.h, k = g.geo.k;
   double src[4], out[4];
   if (id < ncell) {
     const int side = id / (2 * ny), r = id % (2 * ny), j = r / 2, m = r % 2;
-    const BCDev& b = side == 0 ? bw : be;
+    const BCDev& b = Q.bc[side];
     const int ig = side == 0 ? -1 - m : nx + m;
     const double xc = g.geo.x0 + (ig + 0.5) * h, yc = g.geo.y0 + (j + 0.5) * k;
-    if (!bc_fixed(b, xc, yc, t, out)) {
+    if (!bc_fixed(b, 4, xc, yc, t, out)) {
       int is;
       if (b.kind == GKS_BC_PERIODIC)
         is = side == 0 ? ig + nx : ig - nx;
@@ -167,10 +234,10 @@ __global__ void k_ghost_we(Grid<TS, TP> g, BCDev bw, BCDev be, double gamma) {
   id -= ncell;
   if (id < nfx) {
     const int side = id / (2 * ny), r = id % (2 * ny), j = r / 2, gp = r % 2;
-    const BCDev& b = side == 0 ? bw : be;
+    const BCDev& b = Q.bc[side];
     const int fg = side == 0 ? -1 : nx + 1;
     const double xg = g.geo.x0 + fg * h, yg = g.geo.y0 + (j + 0.5 + (gp ? kGaussOffset : -kGaussOffset)) * k;
-    if (!bc_fixed(b, xg, yg, t, out)) {
+    if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const int fs = b.kind == GKS_BC_PERIODIC ? (side == 0 ? nx - 1 : 1) : (side == 0 ? 1 : nx - 1);
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FX[g.ix.fx(gp, v, j, fs)];
       if (b.kind == GKS_BC_PERIODIC)
@@ -184,10 +251,10 @@ __global__ void k_ghost_we(Grid<TS, TP> g, BCDev bw, BCDev be, double gamma) {
   id -= nfx;
   {
     const int side = id / (2 * (ny + 1)), r = id % (2 * (ny + 1)), fj = r / 2, gp = r % 2;
-    const BCDev& b = side == 0 ? bw : be;
+    const BCDev& b = Q.bc[side];
     const int ig = side == 0 ? -1 : nx;
     const double xg = g.geo.x0 + (ig + 0.5 + (gp ? kGaussOffset : -kGaussOffset)) * h, yg = g.geo.y0 + fj * k;
-    if (!bc_fixed(b, xg, yg, t, out)) {
+    if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const bool per = b.kind == GKS_BC_PERIODIC;
       const int is = per ? (side == 0 ? nx - 1 : 0) : (side == 0 ? 0 : nx - 1);
       const int gs = per ? gp : 1 - gp;  // a mirror swaps the tangential Gauss points
@@ -204,20 +271,23 @@ __global__ void k_ghost_we(Grid<TS, TP> g, BCDev bw, BCDev be, double gamma) {
 // South (side 2) / north (side 3): ghost cells of columns -2..nx+1 (corners
 // from the west/east images), ghost y interfaces -1 / ny+1, and the x
 // interfaces of the ghost rows -1 / ny.
-template <typename TS, typename TP>
-__global__ void k_ghost_sn(Grid<TS, TP> g, BCDev bs, BCDev bn, double gamma) {
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_ghost_sn(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GB, id);
+  const Grid<TS, TP> g = Q.g;
+  const double gamma = Q.P.gamma;
   const int nx = g.ix.nx, ny = g.ix.ny;
   const int ncell = 2 * (nx + 4) * 2, nfy = 2 * nx * 2, nfx = 2 * (nx + 1) * 2;
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= ncell + nfy + nfx) return;
   const double t = *g.t, h = g.geo.h, k = g.geo.k;
   double src[4], out[4];
   if (id < ncell) {
     const int side = id / (2 * (nx + 4)), r = id % (2 * (nx + 4)), i = r / 2 - 2, m = r % 2;
-    const BCDev& b = side == 0 ? bs : bn;
+    const BCDev& b = Q.bc[2 + side];
     const int jg = side == 0 ? -1 - m : ny + m;
     const double xc = g.geo.x0 + (i + 0.5) * h, yc = g.geo.y0 + (jg + 0.5) * k;
-    if (!bc_fixed(b, xc, yc, t, out)) {
+    if (!bc_fixed(b, 4, xc, yc, t, out)) {
       int js;
       if (b.kind == GKS_BC_PERIODIC)
         js = side == 0 ? jg + ny : jg - ny;
@@ -235,10 +305,10 @@ __global__ void k_ghost_sn(Grid<TS, TP> g, BCDev bs, BCDev bn, double gamma) {
   id -= ncell;
   if (id < nfy) {
     const int side = id / (2 * nx), r = id % (2 * nx), i = r / 2, gp = r % 2;
-    const BCDev& b = side == 0 ? bs : bn;
+    const BCDev& b = Q.bc[2 + side];
     const int fg = side == 0 ? -1 : ny + 1;
     const double xg = g.geo.x0 + (i + 0.5 + (gp ? kGaussOffset : -kGaussOffset)) * h, yg = g.geo.y0 + fg * k;
-    if (!bc_fixed(b, xg, yg, t, out)) {
+    if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const int fs = b.kind == GKS_BC_PERIODIC ? (side == 0 ? ny - 1 : 1) : (side == 0 ? 1 : ny - 1);
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FY[g.ix.fy(gp, v, fs, i)];
       if (b.kind == GKS_BC_PERIODIC)
@@ -252,10 +322,10 @@ __global__ void k_ghost_sn(Grid<TS, TP> g, BCDev bs, BCDev bn, double gamma) {
   id -= nfy;
   {
     const int side = id / (2 * (nx + 1)), r = id % (2 * (nx + 1)), fi = r / 2, gp = r % 2;
-    const BCDev& b = side == 0 ? bs : bn;
+    const BCDev& b = Q.bc[2 + side];
     const int jg = side == 0 ? -1 : ny;
     const double xg = g.geo.x0 + fi * h, yg = g.geo.y0 + (jg + 0.5 + (gp ? kGaussOffset : -kGaussOffset)) * k;
-    if (!bc_fixed(b, xg, yg, t, out)) {
+    if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const bool per = b.kind == GKS_BC_PERIODIC;
       const int js = per ? (side == 0 ? ny - 1 : 0) : (side == 0 ? 0 : ny - 1);
       const int gs = per ? gp : 1 - gp;
@@ -269,11 +339,50 @@ __global__ void k_ghost_sn(Grid<TS, TP> g, BCDev bs, BCDev bn, double gamma) {
   }
 }
 
+// 1D: tasks (side, m), m = 0, 1 ghost cells -1-m / nx+m, m = 2 the ghost
+// interface -1 / nx+1
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+  if (id >= 6) return;
+  const Grid<TS, TP> g = Q.g;
+  const double gamma = Q.P.gamma;
+  const int nx = g.ix.nx, side = id / 3, m = id % 3;
+  const BCDev& b = Q.bc[side];
+  const bool per = b.kind == GKS_BC_PERIODIC;
+  const double t = *g.t;
+  double src[4], out[4];
+  if (m < 2) {
+    const int ig = side == 0 ? -1 - m : nx + m;
+    if (!bc_fixed(b, 3, 0.0, 0.0, t, out)) {
+      const int is = per ? (side == 0 ? ig + nx : ig - nx) : (side == 0 ? -1 - ig : 2 * nx - 1 - ig);
+      for (int v = 0; v < 3; ++v) src[v] = g.W[g.ix.w1(v, is)];
+      if (per)
+        for (int v = 0; v < 3; ++v) out[v] = src[v];
+      else
+        bc_mirror_1d(b, gamma, src, out);
+    }
+    for (int v = 0; v < 3; ++v) g.W[g.ix.w1(v, ig)] = out[v];
+  } else {
+    const int fg = side == 0 ? -1 : nx + 1;
+    if (!bc_fixed(b, 3, 0.0, 0.0, t, out)) {
+      const int fs = per ? (side == 0 ? nx - 1 : 1) : (side == 0 ? 1 : nx - 1);
+      for (int v = 0; v < 3; ++v) src[v] = (double)g.FX[g.ix.f1(v, fs)];
+      if (per)
+        for (int v = 0; v < 3; ++v) out[v] = src[v];
+      else
+        bc_mirror_1d(b, gamma, src, out);
+    }
+    for (int v = 0; v < 3; ++v) g.FX[g.ix.f1(v, fg)] = (TS)out[v];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // time step: dt = cfl * min over cells of min(h/(|u|+c+2nu/h), k/(|v|+c+2nu/k))
 // The per-cell bound is reduced into g.dtmin (bits of a positive double,
-// ordered like unsigned integers) by k_update_2d for the next step, and by
-// k_dt_scan for the initial state; k_dt_finalize turns it into the step.
+// ordered like unsigned integers) by the update kernel for the next step (and
+// by its scan form for the initial state); k_dt turns it into the step.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, double h, double k) {
   const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
@@ -283,55 +392,53 @@ __device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, 
   return fmin(h / (fabs(u) + cs + 2.0 * nu / h), k / (fabs(v) + cs + 2.0 * nu / k));
 }
 
+__device__ __forceinline__ double cell_dt_bound_1d(const double* W, const Phys& P, double h) {
+  const double rho = W[0], u = W[1] / rho;
+  const double p = (P.gamma - 1.0) * (W[2] - 0.5 * rho * u * u);
+  const double cs = sqrt(P.gamma * p / rho);
+  const double nu = P.viscous ? P.mu / rho : 0.0;
+  return h / (fabs(u) + cs + 2.0 * nu / h);
+}
+
 // wave minimum of a positive bound, one atomic per wave (NaN bounds of a
-// nonphysical cell are skipped; the update flags that cell)
+// nonphysical cell are skipped; the update flags that cell).  Every lane of
+// the wave takes part.
 __device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slot) {
   if (!(b > 0.0) || !isfinite(b)) b = 1e300;
   for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMin(slot, (unsigned long long)__double_as_longlong(b));
 }
 
-template <typename TS, typename TP>
-__global__ void __launch_bounds__(256) k_dt_scan(Grid<TS, TP> g, Phys P) {
-  const int nx = g.ix.nx, ny = g.ix.ny;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double b = 1e300;
-  if (c < nx * ny) {
-    const int j = c / nx, i = c % nx;
-    double W[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) W[v] = g.W[g.ix.w(v, j, i)];
-    b = cell_dt_bound(W, P, g.geo.h, g.geo.k);
-  }
-  reduce_dt_bound(b, g.dtmin);
-}
-
-template <typename TS, typename TP>
-__global__ void k_dt_finalize(Grid<TS, TP> g, double cfl, double t_end) {
-  double dt = cfl * __longlong_as_double((long long)*g.dtmin);
-  if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
-  *g.dt = dt;
-  *g.dtmin = (unsigned long long)__double_as_longlong(1e300);
-}
-
-template <typename TS, typename TP>
-__global__ void k_set_dt(Grid<TS, TP> g, double dt, double t_end) {
+// one thread per problem: ctl[2p] = fixed step (0: CFL), ctl[2p+1] = end
+// time (0: none; the step is shortened to reach it, later steps are empty)
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_dt(const Prob<TS, TP, TC>* __restrict__ probs, const double* __restrict__ ctl,
+                                            int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Grid<TS, TP> g = probs[p].g;
+  const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1];
+  double dt = fixed > 0.0 ? fixed : probs[p].P.cfl * __longlong_as_double((long long)*g.dtmin);
   if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
   *g.dt = dt;
   *g.dtmin = (unsigned long long)__double_as_longlong(1e300);
 }
 
 // ---------------------------------------------------------------------------
-// reconstruction: cells -1..nx x -1..ny except the four corners
+// reconstruction
 // ---------------------------------------------------------------------------
-template <typename TS, typename TP>
-__global__ void __launch_bounds__(256) k_recon_2d(Grid<TS, TP> g, double eps, double Cw, double gamma) {
+
+// 2D: cells -1..nx x -1..ny except the four corners
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_RECON, id);
+  const Grid<TS, TP> g = Q.g;
   const int nx = g.ix.nx, ny = g.ix.ny;
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - 1;
-  const int j = (int)blockIdx.y - 1;
-  if (i > nx) return;
+  if (id >= (nx + 2) * (ny + 2)) return;
+  const int j = id / (nx + 2) - 1, i = id % (nx + 2) - 1;
   if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
-  const double h = g.geo.h, k = g.geo.k;
+  const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, Cw = Q.P.weno_c;
   const Idx& x = g.ix;
   double p[4][5], Wc[4];
 #pragma unroll
@@ -344,15 +451,78 @@ __global__ void __launch_bounds__(256) k_recon_2d(Grid<TS, TP> g, double eps, do
   }
   // a polynomial that is nonphysical at the centre of one of the cell's
   // interfaces is replaced by the constant cell average for this step
-  const bool ok = recon_admissible_2d(Wc, p, h, k, gamma);
+  const bool ok = recon_admissible_2d(Wc, p, h, k, Q.P.gamma);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int m = 0; m < 5; ++m) g.PC[x.pc(v, m, j, i)] = ok ? (TP)p[v][m] : TP(0);
 }
 
+// 1D: cells -1..nx, in conservative or characteristic variables (Sec. 4:
+// characteristic variables of the cell's own state)
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_recon_1d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_RECON, id);
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx;
+  if (id >= nx + 2) return;
+  const int i = id - 1;
+  const double h = g.geo.h, eps = Q.P.weno_eps, Cw = Q.P.weno_c;
+  const Idx& x = g.ix;
+  double s[5][3];  // cell, east, west averages; right and left interface values
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    s[0][v] = g.W[x.w1(v, i)];
+    s[1][v] = g.W[x.w1(v, i + 1)];
+    s[2][v] = g.W[x.w1(v, i - 1)];
+    s[3][v] = (double)g.FX[x.f1(v, i + 1)];
+    s[4][v] = (double)g.FX[x.f1(v, i)];
+  }
+  double p[3][2];
+  if (Q.recon_vars == 1) {
+    double R[3][3], L[3][3];
+    if (!euler_eigen_1d(Q.P.gamma, s[0], R, L)) {
+      // a nonphysical average is reported by the interfaces and the update
+#pragma unroll
+      for (int v = 0; v < 3; ++v) p[v][0] = p[v][1] = 0.0;
+    } else {
+      double c[5][3];
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma clang fp contract(off)
+          double acc = 0.0;
+#pragma unroll
+          for (int v = 0; v < 3; ++v) acc += L[r][v] * s[q][v];
+          c[q][r] = acc;
+        }
+      double pc[3][2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) recon_1d(c[0][r], c[1][r], c[2][r], c[3][r], c[4][r], h, eps, Cw, pc[r]);
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          double acc = 0.0;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) acc += R[v][r] * pc[r][m];
+          p[v][m] = acc;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) recon_1d(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], h, eps, Cw, p[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) g.PC[x.pc1(v, m, i)] = (TP)p[v][m];
+}
+
 // ---------------------------------------------------------------------------
-// interfaces: one thread per interface, x interfaces first, then y
+// 2D interfaces: one thread per interface, x interfaces first, then y
 // interfaces; three phase kernels (prologue, hydrodynamic part, kinetic part
 // of each side) communicating through the frame record R.
 // ---------------------------------------------------------------------------
@@ -380,14 +550,18 @@ __device__ __forceinline__ Face face_of(const Idx& x, int id) {
 // two momentum components
 __device__ __forceinline__ int loc(bool isx, int v) { return isx ? v : (v == 1 ? 2 : v == 2 ? 1 : v); }
 
+__device__ __forceinline__ int n_faces(const Idx& x) { return (x.nx + 1) * x.ny + x.nx * (x.ny + 1); }
+
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_pro_2d(Grid<TS, TP> g, Phys P, Rec<TC> R) {
-  const int nx = g.ix.nx, ny = g.ix.ny;
-  const int nf = (nx + 1) * ny + nx * (ny + 1);
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nf) return;
+__global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  const Grid<TS, TP> g = Q.g;
+  if (id >= n_faces(g.ix)) return;
   const double dt = *g.dt;
   if (!(dt > 0.0)) return;
+  const Phys P = Q.P;
+  const Rec<TC> R = Q.R;
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
   double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
@@ -461,7 +635,7 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(Grid<TS, TP> g, Phys P, Re
 
 // adds interface-frame corrections to the stored flux and point values
 template <typename TS, typename TP>
-__device__ __forceinline__ void add_corrections(Grid<TS, TP>& g, const Face& F, const double (&flux)[4],
+__device__ __forceinline__ void add_corrections(const Grid<TS, TP>& g, const Face& F, const double (&flux)[4],
                                                 const double (&pvm)[4], const double (&pvp)[4]) {
   const Idx& x = g.ix;
 #pragma unroll
@@ -484,12 +658,14 @@ __device__ __forceinline__ void add_corrections(Grid<TS, TP>& g, const Face& F, 
 }
 
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_hydro_2d(Grid<TS, TP> g, Phys P, Rec<TC> R) {
-  const int nx = g.ix.nx, ny = g.ix.ny;
-  const int nf = (nx + 1) * ny + nx * (ny + 1);
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nf) return;
+__global__ void __launch_bounds__(256) k_iface_hydro_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  const Grid<TS, TP> g = Q.g;
+  if (id >= n_faces(g.ix)) return;
+  const Rec<TC> R = Q.R;
   if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
@@ -501,12 +677,14 @@ __global__ void __launch_bounds__(256) k_iface_hydro_2d(Grid<TS, TP> g, Phys P, 
 }
 
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_kin_2d(Grid<TS, TP> g, Phys P, Rec<TC> R, int side) {
-  const int nx = g.ix.nx, ny = g.ix.ny;
-  const int nf = (nx + 1) * ny + nx * (ny + 1);
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nf) return;
+__global__ void __launch_bounds__(256) k_iface_kin_2d(KA<Prob<TS, TP, TC>> a, int side) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  const Grid<TS, TP> g = Q.g;
+  if (id >= n_faces(g.ix)) return;
+  const Rec<TC> R = Q.R;
   if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
@@ -535,20 +713,57 @@ __global__ void __launch_bounds__(256) k_iface_kin_2d(Grid<TS, TP> g, Phys P, Re
   }
 }
 
-// ---------------------------------------------------------------------------
-// conservative update
-// ---------------------------------------------------------------------------
-template <typename TS, typename TP>
-__global__ void __launch_bounds__(256) k_update_2d(Grid<TS, TP> g, Phys P) {
-  const int nx = g.ix.nx, ny = g.ix.ny;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+// 1D interfaces 0..nx, fused
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_face_1d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx;
+  if (id > nx) return;
   const double dt = *g.dt;
+  if (!(dt > 0.0)) return;
+  const Phys P = Q.P;
+  const Idx& x = g.ix;
+  const int fi = id;
+  double Wc[2][3], pc[2][3][2], flux[3], pv[3];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      Wc[s][v] = g.W[x.w1(v, fi - 1 + s)];
+      pc[s][v][0] = (double)g.PC[x.pc1(v, 0, fi - 1 + s)];
+      pc[s][v][1] = (double)g.PC[x.pc1(v, 1, fi - 1 + s)];
+    }
+  if (!iface_1d<TC>(P, dt, g.geo.h, Wc, pc, flux, pv)) {
+    atomicCAS(g.err, 0ull, 1ull + (1ull << 32) + (unsigned long long)(fi + 1));
+#pragma unroll
+    for (int v = 0; v < 3; ++v) flux[v] = pv[v] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    g.FLX[x.fl1(v, fi)] = flux[v];
+    g.FX[x.f1(v, fi)] = (TS)pv[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conservative update (kScan: only the CFL bound of the present state)
+// ---------------------------------------------------------------------------
+template <typename TS, typename TP, typename TC, bool kScan>
+__global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_CELL, id);
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx, ny = g.ix.ny;
   double bound = 1e300;
-  if (i < nx) {
+  if (id < nx * ny) {
+    const int j = id / nx, i = id % nx;
     const Idx& x = g.ix;
     double W[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) W[v] = g.W[x.w(v, j, i)];
+    const double dt = kScan ? 0.0 : *g.dt;
     if (dt > 0.0) {
       const double ia = 1.0 / (g.geo.h * g.geo.k);
 #pragma unroll
@@ -558,16 +773,50 @@ __global__ void __launch_bounds__(256) k_update_2d(Grid<TS, TP> g, Phys P) {
         W[v] += d * ia;
         g.W[x.w(v, j, i)] = W[v];
       }
-      const double p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+      const double p = (Q.P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
       if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
         atomicCAS(g.err, 0ull,
                   1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
-      if (i == 0 && j == 0) {
+      if (id == 0) {
         *g.t += dt;
         *g.steps += 1;
       }
     }
-    bound = cell_dt_bound(W, P, g.geo.h, g.geo.k);
+    bound = cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
+  }
+  reduce_dt_bound(bound, g.dtmin);
+}
+
+template <typename TS, typename TP, typename TC, bool kScan>
+__global__ void __launch_bounds__(256) k_update_1d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_CELL, id);
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx;
+  double bound = 1e300;
+  if (id < nx) {
+    const int i = id;
+    const Idx& x = g.ix;
+    double W[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) W[v] = g.W[x.w1(v, i)];
+    const double dt = kScan ? 0.0 : *g.dt;
+    if (dt > 0.0) {
+      const double ih = 1.0 / g.geo.h;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        W[v] += (g.FLX[x.fl1(v, i)] - g.FLX[x.fl1(v, i + 1)]) * ih;
+        g.W[x.w1(v, i)] = W[v];
+      }
+      const double p = (Q.P.gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
+      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
+        atomicCAS(g.err, 0ull, 1ull + (1ull << 32) + (unsigned long long)(i + 1) + (1ull << 63));
+      if (id == 0) {
+        *g.t += dt;
+        *g.steps += 1;
+      }
+    }
+    bound = cell_dt_bound_1d(W, Q.P, g.geo.h);
   }
   reduce_dt_bound(bound, g.dtmin);
 }
@@ -589,21 +838,38 @@ struct Problem {
   void* PC = nullptr;
   void* FLX = nullptr;
   void* FLY = nullptr;
-  void* scal = nullptr;  // t, dt, steps, err
-  void* recd = nullptr;  // interface frame record, double fields
-  void* rect = nullptr;  // interface frame record, compute-type fields
+  void* scal = nullptr;  // t, dt, steps, err, dtmin
+  void* recd = nullptr;  // interface frame record, double fields (2D)
+  void* rect = nullptr;  // interface frame record, compute-type fields (2D)
+};
+
+// problems of one dimension and precision, advanced by one launch sequence
+struct Group {
+  int dim = 2;
+  bool mixed = false;
+  std::vector<int> members;
+  void* dprobs = nullptr;                  // device Prob<...>[members]
+  uint16_t* owner[KK_COUNT] = {};          // device block-owner tables
+  unsigned nblk[KK_COUNT] = {};
+  unsigned cap[KK_COUNT] = {};             // allocated owner entries
+  int bs[KK_COUNT] = {256, 256, 256, 256, 256};  // block size of each kind
+  double* ctl = nullptr;                   // device [members][2]: fixed step, end time
+  std::vector<double> ctl_host;            // values last uploaded
 };
 
 }  // namespace
 
 struct gks_handle {
   std::vector<Problem> probs;
+  std::vector<Group> groups;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   int sticky = GKS_OK;
   std::string msg;
   int profiling = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
   double ktime[GKS_K_COUNT] = {0};
   long long klaunch[GKS_K_COUNT] = {0};
   std::vector<hipEvent_t> pend_a, pend_b;
@@ -611,6 +877,8 @@ struct gks_handle {
 };
 
 namespace {
+
+constexpr int kMaxProblems = 65535;  // block-owner tables hold 16-bit problem indices
 
 thread_local std::string g_init_msg;  // message of the last failed gks_init on this thread
 
@@ -645,19 +913,22 @@ void cons_of(int dim, double gamma, const double* q, double* W) {
 }
 
 std::string validate(const gks_problem& p) {
-  if (p.dim != 2) return "only dim == 2 is available in this build";
-  if (p.nx < 2 || p.ny < 2) return "nx, ny must be >= 2";
-  if ((long long)(p.nx + 4) * (p.ny + 4) > (1ll << 30)) return "grid too large";
-  if (!(p.x1 > p.x0) || !(p.y1 > p.y0)) return "empty domain";
+  if (p.dim != 1 && p.dim != 2) return "dim must be 1 or 2";
+  if (p.dim == 2 && (p.nx < 2 || p.ny < 2)) return "nx, ny must be >= 2";
+  if (p.dim == 1 && (p.nx < 2 || p.ny != 1)) return "1D: nx >= 2 and ny == 1 required";
+  if ((long long)(p.nx + 4) * (p.ny + 4) > (1ll << 28)) return "grid too large";
+  if (!(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return "empty domain";
   if (!(p.gamma > 1.0) || !(p.gamma < 3.0)) return "gamma must lie in (1, 3)";
   if (!(internal_dof(p.dim, p.gamma) >= 0.0)) return "gamma gives negative internal degrees of freedom";
   if (p.viscous && !(p.mu >= 0.0 && p.prandtl > 0.0)) return "mu >= 0 and prandtl > 0 required";
   if (!(p.cfl > 0.0) || !(p.weno_eps > 0.0) || !(p.weno_c >= 0.0)) return "cfl, weno_eps must be > 0";
   if (!(p.tau_eps >= 0.0) || !(p.tau_c >= 0.0)) return "tau constants must be >= 0";
   if (!std::isfinite(p.t0)) return "t0 must be finite";
-  if (p.recon_vars != 0) return "2D reconstruction is in conservative variables (recon_vars = 0)";
+  if (p.dim == 2 && p.recon_vars != 0) return "2D reconstruction is in conservative variables (recon_vars = 0)";
+  if (p.dim == 1 && p.recon_vars != 0 && p.recon_vars != 1) return "recon_vars must be 0 or 1";
   if (p.precision != GKS_FP64 && p.precision != GKS_FP32_MIXED) return "unknown precision";
-  for (int s = 0; s < 4; ++s) {
+  const int nsides = p.dim == 2 ? 4 : 2;
+  for (int s = 0; s < nsides; ++s) {
     const int k = p.bc[s].kind;
     if (k < GKS_BC_PERIODIC || k > GKS_BC_DMR_TOP) return "unknown boundary kind";
     if ((k == GKS_BC_PERIODIC) != (p.bc[s ^ 1].kind == GKS_BC_PERIODIC)) return "periodic sides must pair";
@@ -669,13 +940,27 @@ std::string validate(const gks_problem& p) {
 
 size_t n_interfaces(const Idx& x) { return (size_t)(x.nx + 1) * x.ny + (size_t)x.nx * (x.ny + 1); }
 
-template <typename TC>
-Rec<TC> rec_of(Problem& p) {
-  Rec<TC> r;
-  r.d = (double*)p.recd;
-  r.t = (TC*)p.rect;
-  r.nf = n_interfaces(p.ix);
-  return r;
+unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+// threads of one problem in a launch of kind k
+size_t work_items(const Problem& p, int dim, int k) {
+  const size_t nx = p.ix.nx, ny = p.ix.ny;
+  if (dim == 2) {
+    switch (k) {
+      case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1);
+      case KK_GB: return 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
+      case KK_RECON: return (nx + 2) * (ny + 2);
+      case KK_FACE: return n_interfaces(p.ix);
+      default: return nx * ny;
+    }
+  }
+  switch (k) {
+    case KK_GA: return 6;
+    case KK_GB: return 0;
+    case KK_RECON: return nx + 2;
+    case KK_FACE: return nx + 1;
+    default: return nx;
+  }
 }
 
 template <typename TS, typename TP>
@@ -698,30 +983,79 @@ Grid<TS, TP> grid_of(Problem& p) {
   return g;
 }
 
-unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+// descriptors and block-owner tables of a group for its present block sizes
+template <typename TS, typename TP, typename TC>
+int build_tables(gks_handle* h, Group& G) {
+  using PR = Prob<TS, TP, TC>;
+  const size_t n = G.members.size();
+  std::vector<PR> host(n);
+  std::vector<std::vector<uint16_t>> own(KK_COUNT);
+  for (size_t m = 0; m < n; ++m) {
+    Problem& p = h->probs[G.members[m]];
+    PR& d = host[m];
+    memset(&d, 0, sizeof(d));
+    d.g = grid_of<TS, TP>(p);
+    d.P = p.phys;
+    for (int s = 0; s < 4; ++s) d.bc[s] = p.bc[s];
+    d.R.d = (double*)p.recd;
+    d.R.t = (TC*)p.rect;
+    d.R.nf = G.dim == 2 ? n_interfaces(p.ix) : 0;
+    d.recon_vars = p.spec.recon_vars;
+  }
+  for (int k = 0; k < KK_COUNT; ++k) {
+    for (size_t m = 0; m < n; ++m) {
+      host[m].first[k] = (unsigned)own[k].size();
+      const unsigned nb = cdiv(work_items(h->probs[G.members[m]], G.dim, k), (size_t)G.bs[k]);
+      own[k].insert(own[k].end(), nb, (uint16_t)m);
+    }
+    G.nblk[k] = (unsigned)own[k].size();
+    if (G.nblk[k] > G.cap[k]) {
+      if (G.owner[k]) (void)hipFree(G.owner[k]);
+      G.owner[k] = nullptr;
+      G.cap[k] = 0;
+      HIP_OR(h, hipMalloc(&G.owner[k], own[k].size() * sizeof(uint16_t)));
+      G.cap[k] = G.nblk[k];
+    }
+    if (G.nblk[k]) HIP_OR(h, hipMemcpy(G.owner[k], own[k].data(), own[k].size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
+  if (!G.dprobs) HIP_OR(h, hipMalloc(&G.dprobs, n * sizeof(PR)));
+  HIP_OR(h, hipMemcpy(G.dprobs, host.data(), n * sizeof(PR), hipMemcpyHostToDevice));
+  return GKS_OK;
+}
 
-int record_begin(gks_handle* h) {
-  if (h->profiling != 1) return 0;
+int build_tables(gks_handle* h, Group& G) {
+  return G.mixed ? build_tables<float, float, float>(h, G) : build_tables<double, double, double>(h, G);
+}
+
+// kernel timing: events around each kernel class when profiling is on
+void record_begin(gks_handle* h, hipStream_t st) {
+  if (h->profiling != 1) return;
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
-  (void)hipEventRecord(a, h->stream);
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  (void)hipEventRecord(a, st);
   h->pend_a.push_back(a);
   h->pend_b.push_back(b);
-  return 0;
+  h->pend_k.push_back(-1);
 }
-void record_end(gks_handle* h, int kernel) {
-  if (h->profiling != 1) return;
-  (void)hipEventRecord(h->pend_b.back(), h->stream);
-  h->pend_k.push_back(kernel);
+void record_end(gks_handle* h, hipStream_t st, int kernel) {
+  if (h->profiling != 1 || h->pend_k.empty() || h->pend_k.back() != -1) return;
+  (void)hipEventRecord(h->pend_b.back(), st);
+  h->pend_k.back() = kernel;
 }
 
 void collect(gks_handle* h) {
   for (size_t n = 0; n < h->pend_k.size(); ++n) {
     float ms = 0.f;
-    (void)hipEventSynchronize(h->pend_b[n]);
-    (void)hipEventElapsedTime(&ms, h->pend_a[n], h->pend_b[n]);
-    h->ktime[h->pend_k[n]] += ms;
-    h->klaunch[h->pend_k[n]] += 1;
+    if (h->pend_k[n] >= 0) {
+      (void)hipEventSynchronize(h->pend_b[n]);
+      (void)hipEventElapsedTime(&ms, h->pend_a[n], h->pend_b[n]);
+      h->ktime[h->pend_k[n]] += ms;
+      h->klaunch[h->pend_k[n]] += 1;
+    }
     (void)hipEventDestroy(h->pend_a[n]);
     (void)hipEventDestroy(h->pend_b[n]);
   }
@@ -731,42 +1065,109 @@ void collect(gks_handle* h) {
 }
 
 template <typename TS, typename TP, typename TC>
-int step_problem(gks_handle* h, Problem& p, const double* dtf, double t_end) {
-  Grid<TS, TP> g = grid_of<TS, TP>(p);
-  const int nx = p.ix.nx, ny = p.ix.ny;
-  hipStream_t st = h->stream;
-  record_begin(h);
-  {
-    const int n1 = 4 * ny + 4 * ny + 4 * (ny + 1);
-    k_ghost_we<TS, TP><<<cdiv(n1, 256), 256, 0, st>>>(g, p.bc[0], p.bc[1], p.phys.gamma);
-    const int n2 = 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
-    k_ghost_sn<TS, TP><<<cdiv(n2, 256), 256, 0, st>>>(g, p.bc[2], p.bc[3], p.phys.gamma);
+void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
+  using PR = Prob<TS, TP, TC>;
+  const PR* probs = (const PR*)G.dprobs;
+  KA<PR> A[KK_COUNT];
+  for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k]};
+  double* ctl = G.ctl;
+  const int n = (int)G.members.size();
+  record_begin(h, st);
+  if (G.dim == 2) {
+    k_ghost_we<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
+    k_ghost_sn<TS, TP, TC><<<G.nblk[KK_GB], G.bs[KK_GB], 0, st>>>(A[KK_GB]);
+  } else {
+    k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
   }
-  record_end(h, GKS_K_GHOST);
-  record_begin(h);
-  if (dtf)
-    k_set_dt<TS, TP><<<1, 1, 0, st>>>(g, *dtf, t_end);
+  record_end(h, st, GKS_K_GHOST);
+  record_begin(h, st);
+  k_dt<TS, TP, TC><<<cdiv(n, 64), 64, 0, st>>>(probs, ctl, n);
+  record_end(h, st, GKS_K_DT);
+  record_begin(h, st);
+  if (G.dim == 2)
+    k_recon_2d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
   else
-    k_dt_finalize<TS, TP><<<1, 1, 0, st>>>(g, p.phys.cfl, t_end);
-  record_end(h, GKS_K_DT);
-  record_begin(h);
-  k_recon_2d<TS, TP><<<dim3(cdiv(nx + 2, 256), ny + 2), 256, 0, st>>>(g, p.phys.weno_eps, p.phys.weno_c,
-                                                                         p.phys.gamma);
-  record_end(h, GKS_K_RECON);
-  record_begin(h);
-  {
-    const size_t nf = n_interfaces(p.ix);
-    Rec<TC> R = rec_of<TC>(p);
-    k_iface_pro_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R);
-    k_iface_hydro_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R);
-    k_iface_kin_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R, 0);
-    k_iface_kin_2d<TS, TP, TC><<<cdiv(nf, 256), 256, 0, st>>>(g, p.phys, R, 1);
+    k_recon_1d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  record_end(h, st, GKS_K_RECON);
+  record_begin(h, st);
+  if (G.dim == 2) {
+    k_iface_pro_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+    k_iface_hydro_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+    k_iface_kin_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE], 0);
+    k_iface_kin_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE], 1);
+  } else {
+    k_face_1d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   }
-  record_end(h, GKS_K_INTERFACE);
-  record_begin(h);
-  k_update_2d<TS, TP><<<dim3(cdiv(nx, 256), ny), 256, 0, st>>>(g, p.phys);
-  record_end(h, GKS_K_UPDATE);
-  HIP_OR(h, hipGetLastError());
+  record_end(h, st, GKS_K_INTERFACE);
+  record_begin(h, st);
+  if (G.dim == 2)
+    k_update_2d<TS, TP, TC, false><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  else
+    k_update_1d<TS, TP, TC, false><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  record_end(h, st, GKS_K_UPDATE);
+}
+
+void enqueue_step(gks_handle* h, hipStream_t st) {
+  for (Group& G : h->groups) {
+    if (G.mixed)
+      enqueue_group<float, float, float>(h, G, st);
+    else
+      enqueue_group<double, double, double>(h, G, st);
+  }
+}
+
+template <typename TS, typename TP, typename TC>
+void enqueue_scan(Group& G, hipStream_t st) {
+  using PR = Prob<TS, TP, TC>;
+  KA<PR> a{(const PR*)G.dprobs, G.owner[KK_CELL], G.nblk[KK_CELL]};
+  if (G.dim == 2)
+    k_update_2d<TS, TP, TC, true><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(a);
+  else
+    k_update_1d<TS, TP, TC, true><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(a);
+}
+
+void drop_graph(gks_handle* h) {
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->exec = nullptr;
+  h->graph = nullptr;
+}
+
+// capture one step of every group into a graph (kernel arguments are the
+// fixed device tables, so the graph stays valid until the tables change)
+int ensure_graph(gks_handle* h) {
+  if (h->exec) return GKS_OK;
+  HIP_OR(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int saved = h->profiling;
+  h->profiling = 0;
+  enqueue_step(h, h->cap_stream);
+  h->profiling = saved;
+  hipGraph_t gr = nullptr;
+  HIP_OR(h, hipStreamEndCapture(h->cap_stream, &gr));
+  h->graph = gr;
+  HIP_OR(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  return GKS_OK;
+}
+
+// per-problem fixed step and end time; uploaded only when they change
+int set_controls(gks_handle* h, const double* dt_fixed, const double* t_end) {
+  bool synced = false;
+  for (Group& G : h->groups) {
+    std::vector<double> c(2 * G.members.size());
+    for (size_t m = 0; m < G.members.size(); ++m) {
+      const int p = G.members[m];
+      c[2 * m] = dt_fixed ? dt_fixed[p] : 0.0;
+      c[2 * m + 1] = t_end ? t_end[p] : 0.0;
+    }
+    if (c == G.ctl_host) continue;
+    if (!synced) {
+      // earlier steps may still read the old values
+      HIP_OR(h, hipStreamSynchronize(h->stream));
+      synced = true;
+    }
+    G.ctl_host = c;
+    HIP_OR(h, hipMemcpy(G.ctl, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   return GKS_OK;
 }
 
@@ -778,24 +1179,30 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
              const double* const* face_x, const double* const* face_y, void* stream) {
   if (!out) return GKS_EINVAL;
   *out = nullptr;
-  if (n_problems < 1 || !probs || !cell || !face_x) return GKS_EINVAL;
+  g_init_msg.clear();
+  if (n_problems < 1 || n_problems > kMaxProblems || !probs || !cell || !face_x) {
+    g_init_msg = "n_problems must lie in [1, 65535] and probs, cell, face_x must be given";
+    return GKS_EINVAL;
+  }
   gks_handle* h = new (std::nothrow) gks_handle();
   if (!h) return GKS_ENOMEM;
+  auto init_fail = [&](int code, const std::string& m) {
+    h->msg = m;
+    g_init_msg = m;
+    gks_destroy(h);
+    return code;
+  };
   h->probs.resize(n_problems);
   for (int n = 0; n < n_problems; ++n) {
     const gks_problem& s = probs[n];
     std::string why = validate(s);
-    if (!why.empty() || !cell[n] || !face_x[n] || (s.dim == 2 && (!face_y || !face_y[n]))) {
-      int rc = fail(h, GKS_EINVAL, "problem " + std::to_string(n) + ": " + (why.empty() ? "null array" : why));
-      g_init_msg = h->msg;
-      gks_destroy(h);
-      return rc;
-    }
+    if (!why.empty() || !cell[n] || !face_x[n] || (s.dim == 2 && (!face_y || !face_y[n])))
+      return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": " + (why.empty() ? "null array" : why));
     Problem& p = h->probs[n];
     p.spec = s;
     p.mixed = s.precision == GKS_FP32_MIXED;
-    p.ix = Idx{s.nx, s.ny};
-    p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, (s.y1 - s.y0) / s.ny};
+    p.ix = Idx{s.nx, s.dim == 2 ? s.ny : 1};
+    p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, s.dim == 2 ? (s.y1 - s.y0) / s.ny : 1.0};
     Phys& P = p.phys;
     memset(&P, 0, sizeof(P));
     P.gamma = s.gamma;
@@ -813,6 +1220,7 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
     P.viscous = s.viscous ? 1 : 0;
     for (int side = 0; side < 4; ++side) {
       BCDev& b = p.bc[side];
+      memset(&b, 0, sizeof(b));
       b.kind = s.bc[side].kind;
       cons_of(s.dim, s.gamma, s.bc[side].state, b.state);
       cons_of(s.dim, s.gamma, s.bc[side].alt, b.alt);
@@ -820,112 +1228,126 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       b.wv = s.bc[side].wall_v;
       b.wT = s.bc[side].wall_T;
     }
-    // initial state must be physical
-    const size_t nc = (size_t)s.nx * s.ny;
+    // the initial state must be physical
+    const size_t nc = (size_t)s.nx * p.ix.ny;
     for (size_t c = 0; c < nc; ++c) {
-      const double r = cell[n][c], mu_ = cell[n][nc + c], mv = cell[n][2 * nc + c], E = cell[n][3 * nc + c];
+      const double r = cell[n][c], mu_ = cell[n][nc + c];
+      const double mv = s.dim == 2 ? cell[n][2 * nc + c] : 0.0, E = cell[n][(s.dim + 1) * nc + c];
       const double pr = (s.gamma - 1.0) * (E - 0.5 * (mu_ * mu_ + mv * mv) / r);
-      if (!(r > 0.0) || !(pr > 0.0) || !std::isfinite(pr)) {
-        int rc = fail(h, GKS_EINVAL, "problem " + std::to_string(n) + ": nonphysical initial cell " +
+      if (!(r > 0.0) || !(pr > 0.0) || !std::isfinite(pr))
+        return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": nonphysical initial cell " +
                                          std::to_string(c));
-        g_init_msg = h->msg;
-        gks_destroy(h);
-        return rc;
-      }
     }
   }
   if (stream) {
     h->stream = (hipStream_t)stream;
   } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-      gks_destroy(h);
-      return GKS_EDEVICE;
-    }
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "hipStreamCreateWithFlags failed");
     h->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return init_fail(GKS_EDEVICE, "hipStreamCreateWithFlags failed");
   for (int n = 0; n < n_problems; ++n) {
     Problem& p = h->probs[n];
+    const gks_problem& s = p.spec;
     const size_t ts = p.mixed ? sizeof(float) : sizeof(double);
     const Idx& x = p.ix;
-    const size_t nf = n_interfaces(x);
+    const size_t nx = s.nx, ny = x.ny;
     void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
-    size_t sizes[9] = {x.nW() * 8, x.nFX() * ts, x.nFY() * ts, x.nPC() * ts, x.nFLX() * 8, x.nFLY() * 8, 64,
-                       (size_t)ND_REC * nf * 8, (size_t)NT_REC * nf * ts};
+    size_t sizes[9];
+    if (s.dim == 2) {
+      const size_t nf = n_interfaces(x);
+      const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,        2 * 4 * (ny + 2) * (nx + 3) * ts,
+                            2 * 4 * (ny + 3) * (nx + 2) * ts,   4 * 5 * (ny + 2) * (nx + 2) * ts,
+                            4 * ny * (nx + 1) * 8,              4 * (ny + 1) * nx * 8,
+                            64,                                 (size_t)ND_REC * nf * 8,
+                            (size_t)NT_REC * nf * ts};
+      memcpy(sizes, sz, sizeof(sz));
+    } else {
+      const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, 64, 0, 0};
+      memcpy(sizes, sz, sizeof(sz));
+    }
     for (int b = 0; b < 9; ++b) {
+      if (!sizes[b]) continue;
       if (hipMalloc(bufs[b], sizes[b]) != hipSuccess) {
         *bufs[b] = nullptr;
-        int rc = fail(h, GKS_ENOMEM, "device allocation failed");
-        gks_destroy(h);
-        return rc;
+        return init_fail(GKS_ENOMEM, "device allocation failed");
       }
-      if (hipMemsetAsync(*bufs[b], 0, sizes[b], h->stream) != hipSuccess) {
-        gks_destroy(h);
-        return GKS_EDEVICE;
-      }
+      if (hipMemsetAsync(*bufs[b], 0, sizes[b], h->stream) != hipSuccess)
+        return init_fail(GKS_EDEVICE, "hipMemsetAsync failed");
     }
     // the clears above must land before the blocking uploads below
-    if (hipStreamSynchronize(h->stream) != hipSuccess) {
-      gks_destroy(h);
-      return GKS_EDEVICE;
-    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return init_fail(GKS_EDEVICE, "hipStreamSynchronize failed");
     // upload: host layouts without ghosts -> ghosted device layouts
-    const gks_problem& s = p.spec;
-    std::vector<double> W(x.nW(), 0.0);
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < s.ny; ++j)
-        for (int i = 0; i < s.nx; ++i) W[x.w(v, j, i)] = cell[n][((size_t)v * s.ny + j) * s.nx + i];
-    std::vector<double> FX(x.nFX(), 0.0), FY(x.nFY(), 0.0);
-    for (int g = 0; g < 2; ++g)
-      for (int v = 0; v < 4; ++v) {
+    std::vector<double> W(sizes[0] / 8, 0.0), FX(sizes[1] / ts, 0.0), FY(sizes[2] / ts, 0.0);
+    if (s.dim == 2) {
+      for (int v = 0; v < 4; ++v)
         for (int j = 0; j < s.ny; ++j)
-          for (int fi = 0; fi <= s.nx; ++fi)
-            FX[x.fx(g, v, j, fi)] = face_x[n][(((size_t)g * 4 + v) * s.ny + j) * (s.nx + 1) + fi];
-        for (int fj = 0; fj <= s.ny; ++fj)
-          for (int i = 0; i < s.nx; ++i)
-            FY[x.fy(g, v, fj, i)] = face_y[n][(((size_t)g * 4 + v) * (s.ny + 1) + fj) * s.nx + i];
+          for (int i = 0; i < s.nx; ++i) W[x.w(v, j, i)] = cell[n][((size_t)v * s.ny + j) * s.nx + i];
+      for (int g = 0; g < 2; ++g)
+        for (int v = 0; v < 4; ++v) {
+          for (int j = 0; j < s.ny; ++j)
+            for (int fi = 0; fi <= s.nx; ++fi)
+              FX[x.fx(g, v, j, fi)] = face_x[n][(((size_t)g * 4 + v) * s.ny + j) * (s.nx + 1) + fi];
+          for (int fj = 0; fj <= s.ny; ++fj)
+            for (int i = 0; i < s.nx; ++i)
+              FY[x.fy(g, v, fj, i)] = face_y[n][(((size_t)g * 4 + v) * (s.ny + 1) + fj) * s.nx + i];
+        }
+    } else {
+      for (int v = 0; v < 3; ++v) {
+        for (int i = 0; i < s.nx; ++i) W[x.w1(v, i)] = cell[n][(size_t)v * s.nx + i];
+        for (int fi = 0; fi <= s.nx; ++fi) FX[x.f1(v, fi)] = face_x[n][(size_t)v * (s.nx + 1) + fi];
       }
+    }
     const double scal0[4] = {s.t0, 0.0, 0.0, 0.0};
-    if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess) {
-      gks_destroy(h);
-      return GKS_EDEVICE;
-    }
-    if (hipMemcpy(p.W, W.data(), W.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-      gks_destroy(h);
-      return GKS_EDEVICE;
-    }
+    if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p.W, W.data(), W.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "upload failed");
+    bool up = true;
     if (p.mixed) {
       std::vector<float> fx(FX.begin(), FX.end()), fy(FY.begin(), FY.end());
-      if (hipMemcpy(p.FX, fx.data(), fx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(p.FY, fy.data(), fy.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-        gks_destroy(h);
-        return GKS_EDEVICE;
-      }
+      up = hipMemcpy(p.FX, fx.data(), fx.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+           (fy.empty() || hipMemcpy(p.FY, fy.data(), fy.size() * 4, hipMemcpyHostToDevice) == hipSuccess);
     } else {
-      if (hipMemcpy(p.FX, FX.data(), FX.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(p.FY, FY.data(), FY.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-        gks_destroy(h);
-        return GKS_EDEVICE;
-      }
+      up = hipMemcpy(p.FX, FX.data(), FX.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+           (FY.empty() || hipMemcpy(p.FY, FY.data(), FY.size() * 8, hipMemcpyHostToDevice) == hipSuccess);
     }
-  }
-  // CFL bound of the initial state
-  for (int n = 0; n < n_problems; ++n) {
-    Problem& p = h->probs[n];
+    if (!up) return init_fail(GKS_EDEVICE, "upload failed");
     const unsigned long long inf = (unsigned long long)0x7e37e43c8800759cull;  // bits of 1e300
-    if (hipMemcpy((char*)p.scal + 32, &inf, 8, hipMemcpyHostToDevice) != hipSuccess) {
-      gks_destroy(h);
-      return GKS_EDEVICE;
+    if (hipMemcpy((char*)p.scal + 32, &inf, 8, hipMemcpyHostToDevice) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "upload failed");
+  }
+  // groups: problems of one dimension and precision, in problem order
+  for (int n = 0; n < n_problems; ++n) {
+    const Problem& p = h->probs[n];
+    Group* G = nullptr;
+    for (Group& g : h->groups)
+      if (g.dim == p.spec.dim && g.mixed == p.mixed) G = &g;
+    if (!G) {
+      h->groups.emplace_back();
+      G = &h->groups.back();
+      G->dim = p.spec.dim;
+      G->mixed = p.mixed;
     }
-    const unsigned nb = cdiv((size_t)p.ix.nx * p.ix.ny, 256);
-    if (p.mixed)
-      k_dt_scan<float, float><<<nb, 256, 0, h->stream>>>(grid_of<float, float>(p), p.phys);
+    G->members.push_back(n);
+  }
+  for (Group& G : h->groups) {
+    const int rc = build_tables(h, G);
+    if (rc != GKS_OK) return init_fail(rc, h->msg);
+    if (hipMalloc(&G.ctl, 2 * G.members.size() * sizeof(double)) != hipSuccess)
+      return init_fail(GKS_ENOMEM, "device allocation failed");
+    G.ctl_host.assign(2 * G.members.size(), 0.0);
+    if (hipMemcpy(G.ctl, G.ctl_host.data(), G.ctl_host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "upload failed");
+    // CFL bound of the initial state
+    if (G.mixed)
+      enqueue_scan<float, float, float>(G, h->stream);
     else
-      k_dt_scan<double, double><<<nb, 256, 0, h->stream>>>(grid_of<double, double>(p), p.phys);
+      enqueue_scan<double, double, double>(G, h->stream);
   }
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
-    gks_destroy(h);
-    return GKS_EDEVICE;
-  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+    return init_fail(GKS_EDEVICE, "initial CFL scan failed");
   *out = h;
   return GKS_OK;
 }
@@ -939,15 +1361,17 @@ int gks_step(gks_handle* h, int32_t nsteps, const double* dt_fixed, const double
       return fail(h, GKS_EINVAL, "dt_fixed must be positive and finite");
     if (t_end && !std::isfinite(t_end[n])) return fail(h, GKS_EINVAL, "t_end must be finite");
   }
-  for (int s = 0; s < nsteps; ++s)
-    for (size_t n = 0; n < h->probs.size(); ++n) {
-      Problem& p = h->probs[n];
-      const double* dtf = dt_fixed ? &dt_fixed[n] : nullptr;
-      const double te = t_end ? t_end[n] : 0.0;
-      int rc = p.mixed ? step_problem<float, float, float>(h, p, dtf, te)
-                       : step_problem<double, double, double>(h, p, dtf, te);
-      if (rc != GKS_OK) return rc;
-    }
+  if (nsteps == 0) return GKS_OK;
+  int rc = set_controls(h, dt_fixed, t_end);
+  if (rc != GKS_OK) return rc;
+  if (h->profiling == 1) {
+    for (int s = 0; s < nsteps; ++s) enqueue_step(h, h->stream);
+  } else {
+    rc = ensure_graph(h);
+    if (rc != GKS_OK) return rc;
+    for (int s = 0; s < nsteps; ++s) HIP_OR(h, hipGraphLaunch(h->exec, h->stream));
+  }
+  HIP_OR(h, hipGetLastError());
   return GKS_OK;
 }
 
@@ -964,57 +1388,193 @@ int gks_fetch(gks_handle* h, int32_t problem, double* cell, double* face_x, doub
   if (t) *t = scal[0];
   if (steps) *steps = *(long long*)&scal[2];
   unsigned long long err = *(unsigned long long*)&scal[3];
-  if (cell) {
-    std::vector<double> W(x.nW());
-    HIP_OR(h, hipMemcpy(W.data(), p.W, W.size() * 8, hipMemcpyDeviceToHost));
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < s.ny; ++j)
-        for (int i = 0; i < s.nx; ++i) cell[((size_t)v * s.ny + j) * s.nx + i] = W[x.w(v, j, i)];
-  }
-  if (face_x || face_y) {
-    std::vector<double> FX(x.nFX()), FY(x.nFY());
+  const size_t ts = p.mixed ? 4 : 8;
+  auto fetch_ts = [&](const void* src, size_t count, std::vector<double>& dst) -> hipError_t {
+    dst.resize(count);
     if (p.mixed) {
-      std::vector<float> fx(x.nFX()), fy(x.nFY());
-      HIP_OR(h, hipMemcpy(fx.data(), p.FX, fx.size() * 4, hipMemcpyDeviceToHost));
-      HIP_OR(h, hipMemcpy(fy.data(), p.FY, fy.size() * 4, hipMemcpyDeviceToHost));
-      FX.assign(fx.begin(), fx.end());
-      FY.assign(fy.begin(), fy.end());
-    } else {
-      HIP_OR(h, hipMemcpy(FX.data(), p.FX, FX.size() * 8, hipMemcpyDeviceToHost));
-      HIP_OR(h, hipMemcpy(FY.data(), p.FY, FY.size() * 8, hipMemcpyDeviceToHost));
+      std::vector<float> f(count);
+      hipError_t e = hipMemcpy(f.data(), src, count * 4, hipMemcpyDeviceToHost);
+      dst.assign(f.begin(), f.end());
+      return e;
     }
-    for (int g = 0; g < 2; ++g)
-      for (int v = 0; v < 4; ++v) {
-        if (face_x)
-          for (int j = 0; j < s.ny; ++j)
-            for (int fi = 0; fi <= s.nx; ++fi)
-              face_x[(((size_t)g * 4 + v) * s.ny + j) * (s.nx + 1) + fi] = FX[x.fx(g, v, j, fi)];
-        if (face_y)
-          for (int fj = 0; fj <= s.ny; ++fj)
-            for (int i = 0; i < s.nx; ++i)
-              face_y[(((size_t)g * 4 + v) * (s.ny + 1) + fj) * s.nx + i] = FY[x.fy(g, v, fj, i)];
-      }
+    return hipMemcpy(dst.data(), src, count * 8, hipMemcpyDeviceToHost);
+  };
+  if (s.dim == 2) {
+    if (cell) {
+      std::vector<double> W((size_t)4 * (s.ny + 4) * (s.nx + 4));
+      HIP_OR(h, hipMemcpy(W.data(), p.W, W.size() * 8, hipMemcpyDeviceToHost));
+      for (int v = 0; v < 4; ++v)
+        for (int j = 0; j < s.ny; ++j)
+          for (int i = 0; i < s.nx; ++i) cell[((size_t)v * s.ny + j) * s.nx + i] = W[x.w(v, j, i)];
+    }
+    if (face_x || face_y) {
+      std::vector<double> FX, FY;
+      HIP_OR(h, fetch_ts(p.FX, (size_t)2 * 4 * (s.ny + 2) * (s.nx + 3), FX));
+      HIP_OR(h, fetch_ts(p.FY, (size_t)2 * 4 * (s.ny + 3) * (s.nx + 2), FY));
+      for (int g = 0; g < 2; ++g)
+        for (int v = 0; v < 4; ++v) {
+          if (face_x)
+            for (int j = 0; j < s.ny; ++j)
+              for (int fi = 0; fi <= s.nx; ++fi)
+                face_x[(((size_t)g * 4 + v) * s.ny + j) * (s.nx + 1) + fi] = FX[x.fx(g, v, j, fi)];
+          if (face_y)
+            for (int fj = 0; fj <= s.ny; ++fj)
+              for (int i = 0; i < s.nx; ++i)
+                face_y[(((size_t)g * 4 + v) * (s.ny + 1) + fj) * s.nx + i] = FY[x.fy(g, v, fj, i)];
+        }
+    }
+  } else {
+    if (cell) {
+      std::vector<double> W((size_t)3 * (s.nx + 4));
+      HIP_OR(h, hipMemcpy(W.data(), p.W, W.size() * 8, hipMemcpyDeviceToHost));
+      for (int v = 0; v < 3; ++v)
+        for (int i = 0; i < s.nx; ++i) cell[(size_t)v * s.nx + i] = W[x.w1(v, i)];
+    }
+    if (face_x) {
+      std::vector<double> F;
+      HIP_OR(h, fetch_ts(p.FX, (size_t)3 * (s.nx + 3), F));
+      for (int v = 0; v < 3; ++v)
+        for (int fi = 0; fi <= s.nx; ++fi) face_x[(size_t)v * (s.nx + 1) + fi] = F[x.f1(v, fi)];
+    }
   }
+  (void)ts;
   if (err) {
     const int kind = (int)(err >> 62);
     const long long a = (long long)((err >> 32) & 0x3fffffff) - 1, b = (long long)(err & 0xffffffff) - 2;
-    const char* where = kind == 2 ? "cell (i, j) = (" : kind == 1 ? "y interface (i, j) = (" : "x interface (i, j) = (";
+    const char* where = kind == 2 ? "cell" : kind == 1 ? "y interface" : "x interface";
     h->sticky = GKS_ENONPHYS;
     return fail(h, GKS_ENONPHYS, "problem " + std::to_string(problem) + ": nonphysical state at " + where +
-                                     std::to_string(b) + ", " + std::to_string(a) + ")");
+                                     " (i, j) = (" + std::to_string(b) + ", " + std::to_string(a) + ")");
   }
   return h->sticky;
+}
+
+int gks_tune(gks_handle* h, int32_t steps) {
+  if (!h) return GKS_EINVAL;
+  if (h->sticky != GKS_OK) return fail(h, GKS_ESTATE, "handle in error state: " + h->msg);
+  if (steps < 1 || steps > 1000) return fail(h, GKS_EINVAL, "steps must lie in [1, 1000]");
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  // save the state that a step changes (averages, point values, scalars)
+  struct Saved {
+    void* dst;
+    void* copy;
+    size_t bytes;
+  };
+  std::vector<Saved> saved;
+  int rc = GKS_OK;
+  for (Problem& p : h->probs) {
+    const size_t ts = p.mixed ? 4 : 8;
+    const size_t nx = p.ix.nx, ny = p.ix.ny;
+    const bool two = p.spec.dim == 2;
+    const Saved s[4] = {{p.W, nullptr, (two ? 4 * (ny + 4) : 3) * (nx + 4) * 8},
+                        {p.FX, nullptr, (two ? 2 * 4 * (ny + 2) : 3) * (nx + 3) * ts},
+                        {p.FY, nullptr, two ? 2 * 4 * (ny + 3) * (nx + 2) * ts : 0},
+                        {p.scal, nullptr, 64}};
+    for (const Saved& x : s) {
+      if (!x.bytes) continue;
+      Saved y = x;
+      if (hipMalloc(&y.copy, y.bytes) != hipSuccess) {
+        rc = fail(h, GKS_ENOMEM, "device allocation failed");
+        break;
+      }
+      saved.push_back(y);
+      if (hipMemcpy(y.copy, y.dst, y.bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+        rc = fail(h, GKS_EDEVICE, "state copy failed");
+        break;
+      }
+    }
+    if (rc != GKS_OK) break;
+  }
+  auto restore = [&]() -> int {
+    for (const Saved& y : saved)
+      if (hipMemcpy(y.dst, y.copy, y.bytes, hipMemcpyDeviceToDevice) != hipSuccess)
+        return fail(h, GKS_EDEVICE, "state restore failed");
+    return GKS_OK;
+  };
+  // time every candidate block size for all kernel classes at once and
+  // keep the fastest per class
+  static const int cand[3] = {64, 128, 256};
+  static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE};
+  double best_t[GKS_K_COUNT];
+  int best_bs[GKS_K_COUNT];
+  for (int k = 0; k < GKS_K_COUNT; ++k) {
+    best_t[k] = 1e300;
+    best_bs[k] = 256;
+  }
+  const int saved_prof = h->profiling;
+  double saved_time[GKS_K_COUNT];
+  long long saved_launch[GKS_K_COUNT];
+  collect(h);
+  memcpy(saved_time, h->ktime, sizeof(saved_time));
+  memcpy(saved_launch, h->klaunch, sizeof(saved_launch));
+  for (int c = 0; c < 3 && rc == GKS_OK; ++c) {
+    for (Group& G : h->groups) {
+      for (int k = 0; k < KK_COUNT; ++k) G.bs[k] = cand[c];
+      if ((rc = build_tables(h, G)) != GKS_OK) break;
+    }
+    if (rc != GKS_OK) break;
+    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
+    h->profiling = 1;
+    enqueue_step(h, h->stream);  // warm-up
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+      rc = fail(h, GKS_EDEVICE, "tuning step failed");
+      break;
+    }
+    collect(h);
+    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
+    for (int s = 0; s < steps; ++s) enqueue_step(h, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+      rc = fail(h, GKS_EDEVICE, "tuning step failed");
+      break;
+    }
+    collect(h);
+    for (int k = 0; k < GKS_K_COUNT; ++k)
+      if (k != GKS_K_DT && h->ktime[k] < best_t[k]) {
+        best_t[k] = h->ktime[k];
+        best_bs[k] = cand[c];
+      }
+    if ((rc = restore()) != GKS_OK) break;
+  }
+  h->profiling = saved_prof;
+  memcpy(h->ktime, saved_time, sizeof(saved_time));
+  memcpy(h->klaunch, saved_launch, sizeof(saved_launch));
+  if (rc == GKS_OK) {
+    for (Group& G : h->groups) {
+      for (int k = 0; k < KK_COUNT; ++k) G.bs[k] = best_bs[cls[k]];
+      if ((rc = build_tables(h, G)) != GKS_OK) break;
+    }
+  }
+  drop_graph(h);
+  if (rc == GKS_OK) rc = restore();
+  for (const Saved& y : saved) (void)hipFree(y.copy);
+  if (rc != GKS_OK) h->sticky = rc;
+  return rc;
+}
+
+int gks_block_size(gks_handle* h, int32_t kernel, int32_t* threads) {
+  if (!h || !threads || kernel < 0 || kernel >= GKS_K_COUNT) return GKS_EINVAL;
+  static const int kind_of[GKS_K_COUNT] = {KK_GA, -1, KK_RECON, KK_FACE, KK_CELL};
+  *threads = kind_of[kernel] < 0 ? 64 : h->groups[0].bs[kind_of[kernel]];
+  return GKS_OK;
 }
 
 int gks_destroy(gks_handle* h) {
   if (!h) return GKS_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   collect(h);
+  drop_graph(h);
+  for (Group& G : h->groups) {
+    if (G.dprobs) (void)hipFree(G.dprobs);
+    if (G.ctl) (void)hipFree(G.ctl);
+    for (int k = 0; k < KK_COUNT; ++k)
+      if (G.owner[k]) (void)hipFree(G.owner[k]);
+  }
   for (Problem& p : h->probs) {
     void* bufs[9] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal, p.recd, p.rect};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return GKS_OK;

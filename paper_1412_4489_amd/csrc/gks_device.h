@@ -603,4 +603,244 @@ __device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const
   return ok;
 }
 
+
+// ---------------------------------------------------------------------------
+// 1D (Sec. 3.1): compact reconstruction of one scalar and the fused
+// interface evaluation
+// ---------------------------------------------------------------------------
+
+// c = cell average, e, w = neighbour averages, Fp, Fm = point values at the
+// right and left interfaces.  p = (p2, p4): U = c + p2 x + p4 (x^2/2 - h^2/24).
+// Branch-deciding quantities in the order of the printed formulas, no FMA.
+__device__ __forceinline__ void recon_1d(double c, double e, double w, double Fp, double Fm, double h, double eps,
+                                         double Cw, double* p) {
+#pragma clang fp contract(off)
+  // one-sided stencils {U_{i-1}, U_{i-1/2}, U_i} and {U_i, U_{i+1/2}, U_{i+1}}
+  const double a3W = 3.0 * (c + w - 2.0 * Fm) / (h * h), a3E = 3.0 * (c + e - 2.0 * Fp) / (h * h);
+  const double s2W = 2.0 * (Fm - c) / h, s2E = 2.0 * (Fp - c) / h;
+  // eq. limiter
+  const double a3 = mm2(a3W, a3E);
+  const double a2 = mm2(-s2W + a3 * h / 6.0, s2E - a3 * h / 6.0);
+  // central stencil: averages of U2 over the three cells
+  const double c2 = (e - w) / (2.0 * h), c4 = (e - 2.0 * c + w) / (h * h);
+  // weights: I(U1) = C h^2, I(U2) = h^2 c2^2 + 13/12 h^4 c4^2
+  const double I1 = Cw * h * h;
+  const double I2 = h * h * c2 * c2 + 13.0 / 12.0 * h * h * h * h * c4 * c4;
+  const double b1 = 1.0 / ((eps + I1) * (eps + I1)), b2 = 1.0 / ((eps + I2) * (eps + I2));
+  const double w1 = b1 / (b1 + b2), w2 = b2 / (b1 + b2);
+  p[0] = w1 * a2 + w2 * c2;
+  p[1] = w1 * a3 + w2 * c4;
+}
+
+// Eigenvectors of the 1D Euler flux Jacobian at the state W (columns of R:
+// waves u - c, u, u + c) and the rows of L = R^-1 in closed form.  False for a
+// nonphysical state.
+__device__ __forceinline__ bool euler_eigen_1d(double gamma, const double* W, double (&R)[3][3], double (&L)[3][3]) {
+  const double rho = W[0], u = W[1] / rho, p = (gamma - 1.0) * (W[2] - 0.5 * rho * u * u);
+  if (!(rho > 0.0) || !(p > 0.0)) return false;
+  const double c = sqrt(gamma * p / rho), H = (W[2] + p) / rho;
+  R[0][0] = 1.0;
+  R[0][1] = 1.0;
+  R[0][2] = 1.0;
+  R[1][0] = u - c;
+  R[1][1] = u;
+  R[1][2] = u + c;
+  R[2][0] = H - u * c;
+  R[2][1] = 0.5 * u * u;
+  R[2][2] = H + u * c;
+  const double b1 = (gamma - 1.0) / (c * c), b2 = 0.5 * u * u * b1, ic = 1.0 / c;
+  L[0][0] = 0.5 * (b2 + u * ic);
+  L[0][1] = -0.5 * (b1 * u + ic);
+  L[0][2] = 0.5 * b1;
+  L[1][0] = 1.0 - b2;
+  L[1][1] = b1 * u;
+  L[1][2] = -b1;
+  L[2][0] = 0.5 * (b2 - u * ic);
+  L[2][1] = -0.5 * (b1 * u - ic);
+  L[2][2] = 0.5 * b1;
+  return true;
+}
+
+// moment target of a derivative vector d for the Maxwellian of density
+// 1/ir moving with U, in its frame (1D)
+template <typename T>
+__device__ __forceinline__ void frame_rhs_1d(const double* d, double ir, double U, T* o) {
+  double b[3], f[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) b[v] = d[v] * ir;
+  to_frame_1d(b, U, f);
+#pragma unroll
+  for (int v = 0; v < 3; ++v) o[v] = (T)f[v];
+}
+
+// One 1D interface.  Wc[s][v], pc[s][v] = (p2, p4): averages and
+// reconstruction of the left (s = 0) and right (s = 1) cells; h = dx.
+// Returns the time-integrated flux (eq. finite) and the interface value at
+// t + dt (eq. point); false if an interface state is nonphysical.  Leading
+// terms, U0, the equilibrium slopes, tau and the time integrals in double;
+// coefficients and correction moments in TC.
+template <typename TC>
+__device__ __forceinline__ bool iface_1d(const Phys& P, double dt, double h, const double (&Wc)[2][3],
+                                         const double (&pc)[2][3][2], double (&flux)[3], double (&pv)[3]) {
+  const double g1 = P.gamma - 1.0;
+  double W[2][3], Dn[2][3], Dnn[2][3], rho[2], U[2], pr[2], lam[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double xn = s == 0 ? 0.5 * h : -0.5 * h;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      W[s][v] = Wc[s][v] + pc[s][v][0] * xn + pc[s][v][1] * (h * h * (1.0 / 12.0));
+      Dn[s][v] = pc[s][v][0] + pc[s][v][1] * xn;
+      Dnn[s][v] = pc[s][v][1];
+    }
+    rho[s] = W[s][0];
+    U[s] = W[s][1] / rho[s];
+    pr[s] = g1 * (W[s][2] - 0.5 * rho[s] * U[s] * U[s]);
+    lam[s] = 0.5 * rho[s] / pr[s];
+  }
+  if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !(pr[0] > 0.0) || !(pr[1] > 0.0)) return false;
+  Half hm[2];
+  double W0[3] = {0, 0, 0}, Fk[3] = {0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    hm[s] = half_moments(U[s], lam[s], s == 0 ? 1.0 : -1.0);
+    const double e2 = P.K * (0.5 / lam[s]);  // <xi^2>
+    W0[0] += rho[s] * hm[s].M0;
+    W0[1] += rho[s] * hm[s].M1;
+    W0[2] += rho[s] * 0.5 * (hm[s].M2 + e2 * hm[s].M0);
+    Fk[0] += rho[s] * hm[s].M1;
+    Fk[1] += rho[s] * hm[s].M2;
+    Fk[2] += rho[s] * 0.5 * (hm[s].M3 + e2 * hm[s].M1);
+  }
+  const double rho0 = W0[0], U0 = W0[1] / rho0;
+  const double p0 = g1 * (W0[2] - 0.5 * rho0 * U0 * U0);
+  if (!(p0 > 0.0)) return false;
+  const double lam0 = 0.5 * rho0 / p0;
+  // equilibrium slopes of the two cells sharing the interface (Sec. 3.3 in 1D)
+  double q2[3], q4[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    q2[v] = (Wc[1][v] - Wc[0][v]) / h;
+    q4[v] = 3.0 * (Wc[0][v] + Wc[1][v] - 2.0 * W0[v]) / (h * h);
+  }
+  const double jump = fabs((pr[0] - pr[1]) / (pr[0] + pr[1]));
+  const double tau = P.viscous ? P.mu / p0 + P.tau_c * jump * dt : (P.tau_eps + P.tau_c * jump) * dt;
+  TimeWeights w;
+  time_weights(tau, dt, w);
+  const double tv = P.viscous ? tau : 0.0;
+  TC kp[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
+  const TC zero[3] = {0, 0, 0};
+  double E[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    flux[v] = w.I[1] * (v == 0 ? W0[1] : v == 1 ? W0[1] * U0 + p0 : U0 * (W0[2] + p0)) + w.I[7] * Fk[v];
+    pv[v] = W0[v];
+    E[v] = dt * W0[v];
+  }
+  // accumulate the correction moments of one Maxwellian (peculiar frame) in
+  // the lab frame
+  auto add = [&](const TC* AF, const TC* BF, const TC* V0, double Us, double rs) {
+    TC fl[3];
+    const TC us = (TC)Us;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) fl[v] = BF[v] + us * AF[v];
+    double a[3];
+    from_frame_1d(fl, Us, a);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) flux[v] += rs * a[v];
+    from_frame_1d(V0, Us, a);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) pv[v] += rs * a[v];
+    from_frame_1d(AF, Us, a);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) E[v] += rs * a[v];
+  };
+  // hydrodynamic part (eq. dis1, g0 over the whole space)
+  {
+    TC th[5];
+    theta_powers(0.5 / lam0, th);
+    TC bx[3], bxx[3];
+    frame_rhs_1d(q2, 1.0 / rho0, U0, bx);
+    frame_rhs_1d(q4, 1.0 / rho0, U0, bxx);
+    TC ax[3], ay[3] = {0, 0, 0}, At[3], dxx[3], dxy[3] = {0, 0, 0}, dyy[3] = {0, 0, 0}, bxt[3], byt[3] = {0, 0, 0},
+                                                                                           Bt[3];
+    const TC u0 = (TC)U0;
+    coef_g0_1d<TC>(th, kp, (TC)P.nth, u0, TC(0), bx, zero, bxx, zero, zero, ax, ay, At, dxx, dxy, dyy, bxt, byt, Bt);
+    TC AF[3] = {0, 0, 0}, BF[3] = {0, 0, 0}, V0[3] = {0, 0, 0}, m0[3], m1[3];
+    auto acc = [&](TC wi, TC wc) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        AF[v] += wi * m0[v];
+        BF[v] += wi * m1[v];
+        V0[v] += wc * m0[v];
+      }
+    };
+    mom_full_conv_1d<TC>(th, kp, u0, TC(0), ax, ay, m0, m1);  // C2 g0 a1 u
+    acc((TC)w.I[2], (TC)w.C[2]);
+    mom_full_A_1d<TC>(th, kp, u0, TC(0), At, m0, m1);  // C3 g0 A
+    acc((TC)w.I[3], (TC)w.C[3]);
+    mom_full_quad_1d<TC>(th, kp, u0, TC(0), ax, ay, dxx, dxy, dyy, m0, m1);  // 1/2 C4 g0 (a1^2 + d11) u^2
+    acc((TC)(0.5 * w.I[4]), (TC)(0.5 * w.C[4]));
+    mom_full_ttt_1d<TC>(th, kp, u0, TC(0), At, Bt, m0, m1);  // 1/2 C5 g0 (A^2 + B)
+    acc((TC)(0.5 * w.I[5]), (TC)(0.5 * w.C[5]));
+    mom_full_tlin_1d<TC>(th, kp, u0, TC(0), ax, ay, At, bxt, byt, m0, m1);  // C6 g0 (A a1 + b1) u
+    acc((TC)w.I[6], (TC)w.C[6]);
+    add(AF, BF, V0, U0, rho0);
+  }
+  // kinetic part (eq. dis2) of each side over its half space
+#pragma unroll 1
+  for (int s = 0; s < 2; ++s) {
+    TC th[5], ht[10];
+    theta_powers(0.5 / lam[s], th);
+    half_table(hm[s], U[s], lam[s], ht);
+    TC bx[3], bxx[3];
+    const double ir = 1.0 / rho[s];
+    frame_rhs_1d(Dn[s], ir, U[s], bx);
+    frame_rhs_1d(Dnn[s], ir, U[s], bxx);
+    TC ax[3], ay[3] = {0, 0, 0}, At[3] = {0, 0, 0}, dxx[3], dxy[3] = {0, 0, 0}, dyy[3] = {0, 0, 0},
+                                 bxt[3] = {0, 0, 0}, byt[3] = {0, 0, 0}, Bt[3] = {0, 0, 0};
+    const TC us = (TC)U[s];
+    if (P.viscous)
+      coef_side_ns_1d<TC>(th, kp, (TC)P.nth, us, TC(0), bx, zero, bxx, zero, zero, ax, ay, At, dxx, dxy, dyy, bxt,
+                          byt, Bt);
+    else
+      coef_side_euler_1d<TC>(th, kp, (TC)P.nth, us, TC(0), bx, zero, bxx, zero, zero, ax, ay, At, dxx, dxy, dyy,
+                             bxt, byt, Bt);
+    TC AF[3] = {0, 0, 0}, BF[3] = {0, 0, 0}, V0[3] = {0, 0, 0}, m0[3], m1[3];
+    auto acc = [&](double wi, double wc) {
+      const TC a = (TC)wi, b = (TC)wc;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        AF[v] += a * m0[v];
+        BF[v] += a * m1[v];
+        V0[v] += b * m0[v];
+      }
+    };
+    // C8 g a1 u  [and -tau C7 g a1 u]
+    mom_half_conv_1d<TC>(th, kp, ht, us, TC(0), ax, ay, m0, m1);
+    acc(w.I[8] - tv * w.I[7], w.C[8] - tv * w.C[7]);
+    // 1/2 C7 t^2 g (a1^2 + d11) u^2  [and -tau C8 g (a1^2 + d11) u^2]
+    mom_half_quad_1d<TC>(th, kp, ht, us, TC(0), ax, ay, dxx, dxy, dyy, m0, m1);
+    acc(0.5 * w.I[10] - tv * w.I[8], 0.5 * w.C[10] - tv * w.C[8]);
+    if (P.viscous) {
+      // -tau C7 g A, -tau C8 g (A a1 + b1) u
+      mom_half_A_1d<TC>(th, kp, ht, us, TC(0), At, m0, m1);
+      acc(-tau * w.I[7], -tau * w.C[7]);
+      mom_half_tlin_1d<TC>(th, kp, ht, us, TC(0), ax, ay, At, bxt, byt, m0, m1);
+      acc(-tau * w.I[8], -tau * w.C[8]);
+    }
+    add(AF, BF, V0, U[s], rho[s]);
+  }
+  if (P.viscous) {
+    // Prandtl-number fix: energy flux += (1/Pr - 1) q, q the heat flux
+    // relative to the velocity of g0
+    const double k2 = 0.5 * U0 * U0;
+    const double qh = flux[2] - U0 * flux[1] + k2 * flux[0] - U0 * (E[2] - U0 * E[1] + k2 * E[0]);
+    flux[2] += P.prfix * qh;
+  }
+  return true;
+}
+
 }  // namespace gks

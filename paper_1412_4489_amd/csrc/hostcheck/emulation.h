@@ -5,13 +5,15 @@
 // function-static, warp shuffles return the lane's own value.  The arithmetic
 // and every memory access of the kernels are those of the device code, so
 // AddressSanitizer on this build checks each access of each launch against
-// the exact size of its allocation.  Reductions across threads are not
-// emulated (block minima see only the thread's own value).
+// the exact size of its allocation.  Warp shuffles return the lane's own
+// value; make_hostcheck.py lets every lane reach the wave minimum's atomic.
 #pragma once
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <vector>
 
 using std::erfc;
 using std::exp;
@@ -64,10 +66,14 @@ inline double __longlong_as_double(long long l) {
 typedef int hipError_t;
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
-enum { hipSuccess = 0, hipStreamNonBlocking = 1, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
+enum { hipSuccess = 0, hipStreamNonBlocking = 1, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
 inline hipError_t hipMalloc(void** p, size_t n) {
   *p = std::calloc(1, n ? n : 1);
   return *p ? hipSuccess : 2;
+}
+template <typename T>
+inline hipError_t hipMalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, n);
 }
 inline hipError_t hipFree(void* p) {
   std::free(p);
@@ -102,9 +108,40 @@ inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
 }
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 
-// a launch: every block, every thread, in order
+// a launch: every block, every thread, in order (recorded instead while a
+// stream capture is open, and run by hipGraphLaunch)
+struct EmuGraph {
+  std::vector<std::function<void()>> ops;
+};
+typedef EmuGraph* hipGraph_t;
+typedef EmuGraph* hipGraphExec_t;
+enum { hipStreamCaptureModeThreadLocal = 2 };
+inline thread_local EmuGraph* g_emu_capture = nullptr;
+inline hipError_t hipStreamBeginCapture(hipStream_t, int) {
+  g_emu_capture = new EmuGraph;
+  return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+  *g = g_emu_capture;
+  g_emu_capture = nullptr;
+  return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void*, void*, size_t) {
+  *e = g;
+  return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  for (auto& op : e->ops) op();
+  return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+inline hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete g;
+  return hipSuccess;
+}
+
 template <class F>
-inline void gks_emulated_launch(dim3 grid, dim3 block, F&& body) {
+inline void gks_emulated_run(dim3 grid, dim3 block, const F& body) {
   gridDim = grid;
   blockDim = block;
   for (unsigned bz = 0; bz < grid.z; ++bz)
@@ -118,4 +155,13 @@ inline void gks_emulated_launch(dim3 grid, dim3 block, F&& body) {
               body();
             }
       }
+}
+
+template <class F>
+inline void gks_emulated_launch(dim3 grid, dim3 block, F body) {
+  if (g_emu_capture) {
+    g_emu_capture->ops.push_back([=]() { gks_emulated_run(grid, block, body); });
+    return;
+  }
+  gks_emulated_run(grid, block, body);
 }

@@ -46,7 +46,7 @@ def rewrite_launches(src):
             q += 1
         args = src[e + 4:q]
         out.append(src[pos:start])
-        out.append(f"gks_emulated_launch(dim3({cfg[0]}), dim3({cfg[1]}), [&]() {{ {kernel}({args}); }})")
+        out.append(f"gks_emulated_launch(dim3({cfg[0]}), dim3({cfg[1]}), [=]() {{ {kernel}({args}); }})")
         pos = q + 1
 
 
@@ -76,6 +76,10 @@ def main(outdir=None):
     s = open(os.path.join(CSRC, "gks.hip")).read()
     s = s.replace("#include <hip/hip_runtime.h>", '#include "emulation.h"')
     s = re.sub(r"__attribute__\(\(amdgpu_waves_per_eu\([^)]*\)\)\)", "", s)
+    # the serial emulation has no cross-lane shuffles: every lane takes part
+    # in the wave minimum's atomic directly, which gives the same minimum
+    s, n = re.subn(r"if \(\(threadIdx\.x & 63\) == 0\) (atomicMin\()", r"\1", s)
+    assert n == 1, "wave-minimum pattern not found"
     s = rewrite_launches(s)
     open(os.path.join(outdir, "gks_hostcheck.cpp"), "w").write(s)
     open(os.path.join(outdir, "emulation.h"), "w").write(open(os.path.join(HERE, "emulation.h")).read())

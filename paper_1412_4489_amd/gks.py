@@ -69,12 +69,14 @@ def lib():
         L.gks_last_error.restype = C.c_char_p
         L.gks_profile.argtypes = [_P, C.c_int32]
         L.gks_kernel_time.argtypes = [_P, C.c_int32, _D, C.POINTER(C.c_int64)]
+        L.gks_tune.argtypes = [_P, C.c_int32]
+        L.gks_block_size.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
 
 EXPORTED = ("gks_init", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error", "gks_profile",
-            "gks_kernel_time")
+            "gks_kernel_time", "gks_tune", "gks_block_size")
 
 
 def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
@@ -101,10 +103,12 @@ def _ptr(a):
 
 def gks_init(probs, states, precision=GKS_FP64, stream=None, t0=None):
     """probs: list of workloads.Problem; states: list of workloads.State;
-    t0: initial times (default 0).  Returns an opaque handle (c_void_p)."""
+    precision: one value or one per problem; t0: initial times (default 0).
+    Returns an opaque handle (c_void_p)."""
     n = len(probs)
     t0 = [0.0] * n if t0 is None else list(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
-    cp = (gks_problem * n)(*[to_c_problem(p, precision, t) for p, t in zip(probs, t0)])
+    prec = [int(x) for x in np.broadcast_to(np.asarray(precision, dtype=np.int64), (n,))]
+    cp = (gks_problem * n)(*[to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)])
     keep = []
     cells, fxs, fys = (_D * n)(), (_D * n)(), (_D * n)()
     for k, (p, st) in enumerate(zip(probs, states)):
@@ -128,8 +132,10 @@ def gks_step(h, nsteps, dt_fixed=None, t_end=None):
         raise GKSError(rc, gks_last_error(h))
 
 
-def gks_fetch(h, problem, prob):
-    """Returns (State, t, steps) of one problem."""
+def gks_fetch(h, problem, prob, check=True):
+    """Returns (State, t, steps) of one problem.  check=False: also return the
+    state of a handle that reported a nonphysical state, as (State, t, steps,
+    status)."""
     from .workloads import State
     nv = prob.nvar
     cell = np.zeros((nv, prob.ny, prob.nx))
@@ -140,6 +146,8 @@ def gks_fetch(h, problem, prob):
     steps = C.c_int64()
     rc = lib().gks_fetch(h, int(problem), _ptr(cell), _ptr(fx), _ptr(fy) if prob.dim == 2 else None,
                          C.byref(t), C.byref(steps))
+    if not check and rc in (GKS_OK, GKS_ENONPHYS):
+        return State(cell, fx, fy), t.value, steps.value, rc
     if rc != GKS_OK:
         raise GKSError(rc, gks_last_error(h))
     return State(cell, fx, fy), t.value, steps.value
@@ -169,6 +177,21 @@ def gks_kernel_time(h, kernel):
     return ms.value, n.value
 
 
+def gks_tune(h, steps=3):
+    rc = lib().gks_tune(h, int(steps))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+
+
+def gks_block_size(h, kernel):
+    n = C.c_int32()
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    rc = lib().gks_block_size(h, k, C.byref(n))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+    return n.value
+
+
 class Solver:
     """A handle over one or more problems (context manager)."""
 
@@ -185,8 +208,12 @@ class Solver:
         e = None if t_end is None else np.broadcast_to(np.asarray(t_end, dtype=np.float64), (n,)).copy()
         gks_step(self.h, nsteps, d, e)
 
-    def fetch(self, k=0):
-        return gks_fetch(self.h, k, self.probs[k])
+    def tune(self, steps=3):
+        gks_tune(self.h, steps)
+        return {k: gks_block_size(self.h, k) for k in KERNELS}
+
+    def fetch(self, k=0, check=True):
+        return gks_fetch(self.h, k, self.probs[k], check)
 
     def close(self):
         if self.h is not None:

@@ -360,6 +360,44 @@ def cavity(n=512, re=1000.0, mach=0.15, prandtl=0.72, gamma=5.0 / 3.0, lid_trans
     return prob, State(cell, fx, fy)
 
 
+BATCH_SIZES = (64, 96, 128, 192, 256, 384)
+
+
+def batch(n_problems=96, seed=14124489, sizes=BATCH_SIZES):
+    """Many independent 2D grids of uneven size advanced together: the
+    isentropic vortex of Sec. 4.1 (half of the problems, periodic [0, 10]^2)
+    and the quadrant Riemann problems 1 and 2 of Sec. 4.3 (a quarter each,
+    zero-gradient boundaries on [0, 1]^2), on n x n cells with n drawn
+    uniformly from `sizes`.  Every problem draws Euler or Navier-Stokes
+    (half each) and Re log-uniform in [100, 5000] (U_ref = 1, rho_ref = 1,
+    L = the vortex's unit core radius, constant mu, Pr 0.72); the draw makes
+    the vortex problems viscous, while the Riemann problems stay the
+    inviscid tests of Sec. 4.3: from their sharp initial jumps, tau |grad W|
+    of the Navier-Stokes distribution is of order one at Re of a few hundred
+    on 96^2 - 192^2 cells, outside its Chapman-Enskog range, and the scheme
+    leaves the physical states within the first steps (in the oracle as on
+    the GPU).  Collision time: Euler vortex tau_eps = 0 (smooth data),
+    Riemann tau_eps = 0.05, Navier-Stokes mu/p plus the jump term (Sec. 4).
+    Returns a list of (Problem, State)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_problems):
+        r = rng.uniform()
+        kind = "vortex" if r < 0.5 else ("riemann1" if r < 0.75 else "riemann2")
+        n = int(rng.choice(np.asarray(sizes)))
+        viscous = bool(rng.uniform() < 0.5)
+        re = float(math.exp(rng.uniform(math.log(100.0), math.log(5000.0))))
+        if kind == "vortex":
+            prob, st = vortex_2d(n)
+        else:
+            prob, st = riemann_2d(1 if kind == "riemann1" else 2, n=n)
+        if viscous and kind == "vortex":
+            prob = replace(prob, viscous=True, mu=1.0 / re, prandtl=0.72, tau_eps=0.0)
+        prob = replace(prob, name=f"batch{k}_{prob.name}_{'ns' if prob.viscous else 'euler'}")
+        out.append((prob, st))
+    return out
+
+
 def uniform_2d(nx=16, ny=12, state=(1.3, 0.4, -0.7, 2.1), gamma=1.4, bc="periodic", **kw):
     """Free stream: one uniform state everywhere."""
     prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=0.75, gamma=gamma,

@@ -25,6 +25,10 @@ CASES = {
                                               tau_eps=0.0),
     "dmr": lambda: W.dmr(32, 8),
     "cavity": lambda: W.cavity(12, re=100.0),
+    "advection_1d": lambda: W.advection_1d(20),
+    "sod_1d_char": lambda: W.sod_1d(24),
+    "sod_1d_cons": lambda: W.sod_1d(24, recon_vars=0),
+    "blast_1d": lambda: W.blast_1d(30),
 }
 bad = 0
 for name, mk in CASES.items():
@@ -33,22 +37,83 @@ for name, mk in CASES.items():
         dt = 0.8 * O.dt(prob, st)
         ref = st.copy()
         O.step(prob, ref, dt, 0.0)
+        # two more steps from the CFL condition; the oracle decides whether
+        # they stay physical (a coarse blast wave does not)
+        ref2, t2, ok2 = ref.copy(), dt, True
+        for n in range(2):
+            d = O.dt(prob, ref2)
+            try:
+                O.step(prob, ref2, d, t2)
+            except FloatingPointError:
+                ok2 = False
+                break
+            t2 += d
         with gks.Solver(prob, st, prec) as S:
             S.step(1, dt=dt)
             got, t, n = S.fetch()
-            S.step(2)  # CFL steps (block reductions are not emulated exactly)
-            S.fetch()
+            S.step(2)
+            try:
+                got2, _, _ = S.fetch()
+                gok2 = True
+            except gks.GKSError as e:
+                assert e.code == gks.GKS_ENONPHYS, e
+                gok2 = False
+        same = gok2 == ok2
+        if ok2 and gok2 and not any(k in name for k in ("rough", "riemann", "dmr", "sod", "blast")):
+            # free-running on smooth data (discontinuous data may flip a
+            # limiter branch on rounding-level differences)
+            e2 = np.abs(got2.cell - ref2.cell).max() / np.abs(ref2.cell).max()
+            same = e2 < (1e-11 if prec == gks.GKS_FP64 else 1e-5)
+        bad += not same
+        if not same:
+            print(f"{name} CFL steps differ from the oracle (physical: gpu {gok2}, oracle {ok2})", flush=True)
         err = np.abs(got.cell - ref.cell).max() / np.abs(ref.cell).max()
         tol = 1e-12 if prec == gks.GKS_FP64 else 1e-6
         ok = err < tol
         bad += not ok
         print(f"{name} {'fp64' if prec == gks.GKS_FP64 else 'fp32_mixed'} rel_diff {err:.2e} {'ok' if ok else 'FAIL'}",
               flush=True)
-# a batch of uneven grids in one handle
-probs, states = zip(*[W.smooth_periodic_2d(nx=n, ny=n + 2, seed=n) for n in (5, 9, 7)])
-with gks.Solver(list(probs), list(states)) as S:
-    S.step(2, dt=[1e-3, 1e-3, 1e-3])
-    for k in range(3):
-        S.fetch(k)
+# a batch of uneven grids of both dimensions and precisions in one handle,
+# each problem compared with the oracle run alone
+mixed = [W.smooth_periodic_2d(nx=n, ny=n + 2, seed=n) for n in (5, 9, 7)] + [W.sod_1d(12), W.advection_1d(9)]
+mixed += W.batch(4, seed=3, sizes=(6, 8))
+precs = [gks.GKS_FP64, gks.GKS_FP32_MIXED] * 5
+probs, states = [m[0] for m in mixed], [m[1] for m in mixed]
+dts = [0.7 * O.dt(p, s) for p, s in mixed]
+# one step each (a second one for the smooth problems: on discontinuous data
+# a rounding-level difference may legitimately flip a limiter branch)
+smooth = [not any(k in p.name for k in ("riemann", "sod")) for p in probs]
+refs1, refs2 = [], []
+for p, s, dt in zip(probs, states, dts):
+    r = s.copy()
+    O.step(p, r, dt, 0.0)
+    refs1.append(r.copy())
+    O.step(p, r, dt, dt)
+    refs2.append(r)
+with gks.Solver(probs, states, precision=precs[:len(probs)]) as S:
+    for nstep, refs in ((1, refs1), (2, refs2)):
+        S.step(1, dt=dts)
+        for k in range(len(probs)):
+            if nstep == 2 and not smooth[k]:
+                continue
+            got, t, n = S.fetch(k)
+            err = np.abs(got.cell - refs[k].cell).max() / np.abs(refs[k].cell).max()
+            tol = 1e-12 if precs[k] == gks.GKS_FP64 else 1e-6
+            bad += not err < tol
+            print(f"batch step {nstep} {k} {probs[k].name} rel_diff {err:.2e} {'ok' if err < tol else 'FAIL'}",
+                  flush=True)
 print("batch ok", flush=True)
+# autotuned launch shapes: bitwise the same results, the state not advanced
+pair = [W.smooth_periodic_2d(nx=13, ny=11, seed=5), W.sod_1d(20)]
+outs = []
+for tune in (False, True):
+    with gks.Solver([q[0] for q in pair], [q[1] for q in pair], precision=[gks.GKS_FP64, gks.GKS_FP32_MIXED]) as S:
+        if tune:
+            sizes = S.tune(2)
+            assert all(S.fetch(k)[2] == 0 for k in range(2)), "tuning advanced the state"
+        S.step(2, dt=[1e-3, 1e-3])
+        outs.append([S.fetch(k)[0].cell for k in range(2)])
+same = all(np.array_equal(a, b) for a, b in zip(*outs))
+bad += not same
+print(f"tuned block sizes {sizes}: results {'identical' if same else 'DIFFER'}", flush=True)
 sys.exit(1 if bad else 0)
