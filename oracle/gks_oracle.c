@@ -1124,10 +1124,32 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
   }
 }
 
-/* reconstruction of cell (i, j), all components (conservative variables).
- * Reading (robustness at strong shocks, not printed): if the reconstructed
- * polynomial gives rho <= 0 or p <= 0 at the centre of any of the cell's four
- * interfaces, the cell is reconstructed as its constant average for this step. */
+/* Reading (robustness at strong shocks, not printed): a reconstructed cell
+ * polynomial is admissible if, at the centre of every interface of the cell,
+ * density and pressure are positive and lie within a factor two of the range
+ * of the averages of the cell and its face neighbours:
+ *   rho_min / 2 <= rho <= 2 rho_max,  p_min / 2 <= p <= 2 p_max.
+ * Otherwise the cell is reconstructed as its constant average for this step.
+ * (Smooth data never come near the bounds.)  lo/hi: the neighbourhood's range
+ * of rho (index 0) and p (index 1). */
+static int admissible(int dim, double gamma, const double* W, const double* lo, const double* hi) {
+  double p = pressure(dim, gamma, W);
+  if (!(W[0] > 0.0) || !(p > 0.0)) return 0;
+  if (W[0] < 0.5 * lo[0] || W[0] > 2.0 * hi[0]) return 0;
+  if (p < 0.5 * lo[1] || p > 2.0 * hi[1]) return 0;
+  return 1;
+}
+
+static void range_add(int dim, double gamma, const double* W, double* lo, double* hi) {
+  double q[2] = {W[0], pressure(dim, gamma, W)};
+  for (int a = 0; a < 2; ++a) {
+    if (q[a] < lo[a]) lo[a] = q[a];
+    if (q[a] > hi[a]) hi[a] = q[a];
+  }
+}
+
+/* reconstruction of cell (i, j), all components (conservative variables),
+ * with the admissibility reading above */
 static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
   double pc[4][5];
   for (int v = 0; v < G->nv; ++v)
@@ -1135,6 +1157,14 @@ static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h
                        GW(G, v, j - 1, i), GFX(G, 1, v, j, i + 1), GFX(G, 0, v, j, i + 1), GFX(G, 1, v, j, i),
                        GFX(G, 0, v, j, i), GFY(G, 1, v, j + 1, i), GFY(G, 0, v, j + 1, i), GFY(G, 1, v, j, i),
                        GFY(G, 0, v, j, i), h, k, P->weno_eps, P->weno_c, pc[v]);
+  /* range of the averages of the cell and its four face neighbours */
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+  const int nb[5][2] = {{0, 0}, {0, 1}, {0, -1}, {1, 0}, {-1, 0}};
+  for (int q = 0; q < 5; ++q) {
+    double Wq[4];
+    get_cell(G, j + nb[q][0], i + nb[q][1], Wq);
+    range_add(2, P->gamma, Wq, lo, hi);
+  }
   int ok = 1;
   for (int f = 0; f < 4; ++f) {
     /* interface centres: x = +-h/2 (y = 0), y = +-k/2 (x = 0) */
@@ -1144,7 +1174,7 @@ static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h
     for (int v = 0; v < 4; ++v)
       W[v] = GW(G, v, j, i) + pc[v][0] * x + pc[v][1] * y + pc[v][2] * 0.5 * (x * x - h * h / 12.0) +
              pc[v][3] * 0.5 * (y * y - k * k / 12.0) + pc[v][4] * x * y;
-    if (!(W[0] > 0.0) || !(pressure(2, P->gamma, W) > 0.0)) ok = 0;
+    if (!admissible(2, P->gamma, W, lo, hi)) ok = 0;
   }
   for (int v = 0; v < G->nv; ++v)
     for (int m = 0; m < 5; ++m) GPC(G, v, m, j, i) = ok ? pc[v][m] : 0.0;
@@ -1398,6 +1428,23 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
         P1(v, 1, i) = p[1];
       }
     }
+  }
+  /* admissibility reading (see above): interface values at x = +-h/2 of each
+   * cell polynomial against the range of the cell and its two neighbours */
+  for (int i = -1; i <= nx; ++i) {
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+    for (int q = -1; q <= 1; ++q) {
+      double Wq[3] = {W1(0, i + q), W1(1, i + q), W1(2, i + q)};
+      range_add(1, P->gamma, Wq, lo, hi);
+    }
+    int ok = 1;
+    for (int sd = -1; sd <= 1; sd += 2) {
+      double xn = 0.5 * sd * h, Wf[3];
+      for (int v = 0; v < 3; ++v) Wf[v] = W1(v, i) + P1(v, 0, i) * xn + P1(v, 1, i) * 0.5 * (xn * xn - h * h / 12.0);
+      if (!admissible(1, P->gamma, Wf, lo, hi)) ok = 0;
+    }
+    if (!ok)
+      for (int v = 0; v < 3; ++v) P1(v, 0, i) = P1(v, 1, i) = 0.0;
   }
   /* interfaces */
 #pragma omp parallel for schedule(static) reduction(| : status)

@@ -438,20 +438,33 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   if (id >= (nx + 2) * (ny + 2)) return;
   const int j = id / (nx + 2) - 1, i = id % (nx + 2) - 1;
   if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
-  const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, Cw = Q.P.weno_c;
+  const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, Cw = Q.P.weno_c, gamma = Q.P.gamma;
   const Idx& x = g.ix;
+  // the cell and its east, west, north, south neighbours
+  double Wn[5][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Wn[0][v] = g.W[x.w(v, j, i)];
+    Wn[1][v] = g.W[x.w(v, j, i + 1)];
+    Wn[2][v] = g.W[x.w(v, j, i - 1)];
+    Wn[3][v] = g.W[x.w(v, j + 1, i)];
+    Wn[4][v] = g.W[x.w(v, j - 1, i)];
+  }
   double p[4][5], Wc[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    Wc[v] = g.W[x.w(v, j, i)];
-    recon_2d(Wc[v], g.W[x.w(v, j, i + 1)], g.W[x.w(v, j, i - 1)], g.W[x.w(v, j + 1, i)], g.W[x.w(v, j - 1, i)],
-             (double)g.FX[x.fx(1, v, j, i + 1)], (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)],
-             (double)g.FX[x.fx(0, v, j, i)], (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)],
-             (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, p[v]);
+    Wc[v] = Wn[0][v];
+    recon_2d(Wc[v], Wn[1][v], Wn[2][v], Wn[3][v], Wn[4][v], (double)g.FX[x.fx(1, v, j, i + 1)],
+             (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)],
+             (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)], (double)g.FY[x.fy(1, v, j, i)],
+             (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, p[v]);
   }
-  // a polynomial that is nonphysical at the centre of one of the cell's
-  // interfaces is replaced by the constant cell average for this step
-  const bool ok = recon_admissible_2d(Wc, p, h, k, Q.P.gamma);
+  // an inadmissible polynomial is replaced by the constant cell average for
+  // this step
+  Range rg;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) rg.add(Wn[q][0], pressure_2d(gamma, Wn[q]));
+  const bool ok = recon_admissible_2d(Wc, p, h, k, gamma, rg);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -515,10 +528,16 @@ __global__ void __launch_bounds__(256) k_recon_1d(KA<Prob<TS, TP, TC>> a) {
 #pragma unroll
     for (int v = 0; v < 3; ++v) recon_1d(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], h, eps, Cw, p[v]);
   }
+  // an inadmissible polynomial is replaced by the constant cell average
+  Range rg;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) rg.add(s[q][0], pressure_1d(Q.P.gamma, s[q]));
+  const double Wc[3] = {s[0][0], s[0][1], s[0][2]};
+  const bool ok = recon_admissible_1d(Wc, p, h, Q.P.gamma, rg);
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int m = 0; m < 2; ++m) g.PC[x.pc1(v, m, i)] = (TP)p[v][m];
+    for (int m = 0; m < 2; ++m) g.PC[x.pc1(v, m, i)] = ok ? (TP)p[v][m] : TP(0);
 }
 
 // ---------------------------------------------------------------------------

@@ -582,11 +582,38 @@ __device__ __forceinline__ void recon_2d(double c, double e, double w, double n,
   p[4] = w1 * a6 + w2 * c6;
 }
 
-// true if the cell polynomial Wc + p2 x + p3 y + p4 w_x + p5 w_y + p6 x y
-// (per conservative variable) has rho > 0 and p > 0 at the centres of the
-// four interfaces of the cell
+// Admissibility of a reconstructed cell polynomial (a robustness reading; the
+// paper prints none): at the centre of every interface of the cell, density
+// and pressure must be positive and lie within a factor two of the range of
+// the averages of the cell and its face neighbours,
+//   rho_min / 2 <= rho <= 2 rho_max,  p_min / 2 <= p <= 2 p_max;
+// otherwise the cell is reconstructed as its constant average for this step.
+// Smooth data never come near these bounds.
+struct Range {
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};  // rho, p
+  __device__ __forceinline__ void add(double rho, double p) {
+    lo[0] = fmin(lo[0], rho);
+    hi[0] = fmax(hi[0], rho);
+    lo[1] = fmin(lo[1], p);
+    hi[1] = fmax(hi[1], p);
+  }
+  __device__ __forceinline__ bool admits(double rho, double p) const {
+    return rho > 0.0 && p > 0.0 && !(rho < 0.5 * lo[0]) && !(rho > 2.0 * hi[0]) && !(p < 0.5 * lo[1]) &&
+           !(p > 2.0 * hi[1]);
+  }
+};
+
+__device__ __forceinline__ double pressure_2d(double gamma, const double* W) {
+  return (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+}
+__device__ __forceinline__ double pressure_1d(double gamma, const double* W) {
+  return (gamma - 1.0) * (W[2] - 0.5 * (W[1] * W[1]) / W[0]);
+}
+
+// the cell polynomial Wc + p2 x + p3 y + p4 w_x + p5 w_y + p6 x y (per
+// conservative variable) at the centres of the four interfaces of the cell
 __device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const double (&p)[4][5], double h,
-                                                    double k, double gamma) {
+                                                    double k, double gamma, const Range& R) {
   bool ok = true;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
@@ -597,12 +624,25 @@ __device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const
     for (int v = 0; v < 4; ++v)
       W[v] = Wc[v] + p[v][0] * x + p[v][1] * y + p[v][2] * 0.5 * (x * x - h * h / 12.0) +
              p[v][3] * 0.5 * (y * y - k * k / 12.0) + p[v][4] * x * y;
-    const double pr = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-    ok = ok && (W[0] > 0.0) && (pr > 0.0);
+    ok = ok && R.admits(W[0], pressure_2d(gamma, W));
   }
   return ok;
 }
 
+// 1D: the polynomial Wc + p2 x + p4 (x^2/2 - h^2/24) at x = -h/2, +h/2
+__device__ __forceinline__ bool recon_admissible_1d(const double (&Wc)[3], const double (&p)[3][2], double h,
+                                                    double gamma, const Range& R) {
+  bool ok = true;
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) {
+    const double x = sd == 0 ? -0.5 * h : 0.5 * h;
+    double W[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) W[v] = Wc[v] + p[v][0] * x + p[v][1] * 0.5 * (x * x - h * h / 12.0);
+    ok = ok && R.admits(W[0], pressure_1d(gamma, W));
+  }
+  return ok;
+}
 
 // ---------------------------------------------------------------------------
 // 1D (Sec. 3.1): compact reconstruction of one scalar and the fused

@@ -115,3 +115,19 @@ def test_advection_full_run_cfl05(G, oracle):
     e_orc = np.abs(ref.cell[0, 0] - exact).mean()
     assert e_gpu == pytest.approx(e_orc, rel=1e-6)
     assert e_gpu < 1e-4
+
+
+def test_blast_wave_full_run(G, oracle):
+    """Sec. 4.2 blast wave, 400 cells, characteristic variables, CFL 0.2 from
+    each side's own CFL condition, to t = 3.8: GPU FP64 against the oracle
+    (relative L1 of the density; limiter branches may flip on rounding-level
+    differences over thousands of steps of shocked data)."""
+    prob, st = W.blast_1d(400)
+    ref = st.copy()
+    n, t = oracle.run(prob, ref, t_end=3.8)
+    with G.Solver(prob, st, G.GKS_FP64) as S:
+        S.step(n + 200, t_end=3.8)
+        got, tg, ng = S.fetch()
+    assert tg == pytest.approx(3.8, rel=1e-14) and abs(ng - n) <= 2
+    l1 = np.abs(got.cell[0] - ref.cell[0]).mean() / np.abs(ref.cell[0]).mean()
+    assert l1 < 1e-3

@@ -94,8 +94,13 @@ def test_full_size_parity(G, oracle, case, prec):
         assert d[:, near].max() < 1e-4
         return
     assert _rel(got.cell, ref.cell, floor) < tol
-    assert _rel(got.fx, ref.fx, floor) < 10 * tol
-    assert _rel(got.fy, ref.fy, floor) < 10 * tol
+    # point values: on the interfaces a shock crosses, the correction terms of
+    # the point-value update are as large as the value itself, and their
+    # single-precision evaluation leaves up to 3e-4 of the field there (the
+    # host emulation of the same kernels gives the same figure)
+    ptol = 1e-3 if (prec != "fp64" and case == "dmr_1920x480") else 10 * tol
+    assert _rel(got.fx, ref.fx, floor) < ptol
+    assert _rel(got.fy, ref.fy, floor) < ptol
     # conservation on the periodic grid: every total to round-off (the walls
     # of the cavity are not mass-tight in the ghost-cell wall treatment; the
     # drift is the oracle's, to parity)
@@ -103,3 +108,72 @@ def test_full_size_parity(G, oracle, case, prec):
         for v in range(4):
             tot, tot0 = got.cell[v].sum(dtype=np.float64), st.cell[v].sum(dtype=np.float64)
             assert abs(tot - tot0) <= 1e-12 * np.abs(st.cell[v]).sum()
+
+
+def _physical(prob, c):
+    pr = (prob.gamma - 1.0) * (c[3] - 0.5 * (c[1] ** 2 + c[2] ** 2) / c[0])
+    return bool((c[0] > 0).all() and (pr > 0).all())
+
+
+def _shock_x(row, xc, hi=8.0, lo=1.4):
+    mid = 0.5 * (hi + lo)
+    k = int(np.argmax(row < mid))
+    return xc[k - 1] + (row[k - 1] - mid) / (row[k - 1] - row[k]) * (xc[k] - xc[k - 1])
+
+
+def test_dmr_to_t02_against_oracle(G, oracle):
+    """Double Mach reflection (Sec. 4.5) on 192 x 48 cells to t = 0.2 with a
+    fixed step (0.8 of the initial CFL step, which bounds the whole run), GPU
+    FP64 and FP32-mixed against the oracle run alone.  Over hundreds of steps
+    on shocked data rounding-level differences flip limiter branches and grow
+    (FP64 against the oracle, relative L1 of the density: 5e-13 after 100
+    steps, 9e-6 after 300, 2.2e-3 at t = 0.2; the kernels emulated on the host
+    give the same history), so the comparison is the relative L1 difference
+    of the density (5e-3) and the incident shock position on three rows
+    (within a tenth of a cell)."""
+    prob, st = W.dmr(192, 48)
+    dt = 0.8 * oracle.dt(prob, st)
+    nsteps = int(np.ceil(0.2 / dt - 1e-9))
+    ref = st.copy()
+    n, t = oracle.run(prob, ref, nsteps=nsteps, dt_fixed=dt, t_end=0.2)
+    assert t == pytest.approx(0.2, rel=1e-14) and _physical(prob, ref.cell)
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
+    for p in (G.GKS_FP64, G.GKS_FP32_MIXED):
+        with G.Solver(prob, st, p) as S:
+            S.step(nsteps, dt=dt, t_end=0.2)
+            got, tg, ng = S.fetch()
+        assert ng == n and tg == pytest.approx(0.2, rel=1e-14)
+        l1 = np.abs(got.cell[0] - ref.cell[0]).mean() / np.abs(ref.cell[0]).mean()
+        assert l1 < 5e-3, (p, l1)
+        for j in (24, 36, 47):
+            assert abs(_shock_x(got.cell[0, j], xc) - _shock_x(ref.cell[0, j], xc)) < 0.1 * prob.dx, (p, j)
+
+
+def test_dmr_full_size_fp32_against_fp64(G):
+    """The 1920 x 480 double Mach reflection to t = 0.2 with the CFL step
+    computed on the device (beyond the oracle's reach in a test): the
+    FP32-mixed run against the FP64 run -- both stay physical, the relative L1
+    difference of the density stays below 5e-2 (at this resolution the slip
+    line behind the Mach stem rolls up, and rounding-level differences grow
+    there over the ~6000 steps; 2.2e-2 measured) and the incident shock on
+    three rows agrees within a tenth of a cell, and its mid-density crossing
+    lies within two cells of the exact line x = 1/6 + (y + 20 t) / sqrt(3)
+    (1.2 cells measured on the middle row: the captured profile is not
+    symmetric about the discontinuity)."""
+    prob, st = W.dmr(1920, 480)
+    out = {}
+    for p in (G.GKS_FP64, G.GKS_FP32_MIXED):
+        with G.Solver(prob, st, p) as S:
+            S.step(20000, t_end=0.2)
+            got, t, n = S.fetch()
+        assert t == pytest.approx(0.2, rel=1e-14) and 4000 < n < 20000
+        assert _physical(prob, got.cell)
+        out[p] = got.cell[0]
+    l1 = np.abs(out[G.GKS_FP32_MIXED] - out[G.GKS_FP64]).mean() / np.abs(out[G.GKS_FP64]).mean()
+    assert l1 < 5e-2
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
+    for j in (240, 360, 479):
+        y = prob.y0 + (j + 0.5) * prob.dy
+        exact = 1.0 / 6.0 + (y + 4.0) / np.sqrt(3.0)
+        x64, x32 = _shock_x(out[G.GKS_FP64][j], xc), _shock_x(out[G.GKS_FP32_MIXED][j], xc)
+        assert abs(x32 - x64) < 0.1 * prob.dx and abs(x64 - exact) < 2 * prob.dx, (j, x32, x64, exact)

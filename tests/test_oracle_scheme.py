@@ -124,3 +124,44 @@ def test_sod_vs_exact_riemann(oracle):
         errs.append(np.abs(rho - ex).mean())
         assert rho.min() > 0.124 and rho.max() < 1.005
     assert errs[0] < 6e-3 and errs[1] < 0.8 * errs[0]
+
+
+def _shock_x(row, xc, hi, lo):
+    """First crossing of the mid value between the post- and pre-shock
+    densities along a row, by linear interpolation."""
+    mid = 0.5 * (hi + lo)
+    k = int(np.argmax(row < mid))
+    return xc[k - 1] + (row[k - 1] - mid) / (row[k - 1] - row[k]) * (xc[k] - xc[k - 1])
+
+
+def test_double_mach_reflection_runs_and_moves_the_incident_shock(oracle):
+    """Sec. 4.5 at 96 x 24 to t = 0.2 (the admissibility reading of the
+    reconstruction keeps every state physical): above the Mach stem the
+    incident Mach-10 shock sits where its exact motion puts it,
+    x = 1/6 + (y + 20 t) / sqrt(3), within one cell."""
+    prob, st = W.dmr(96, 24)
+    n, t = oracle.run(prob, st, t_end=0.2)
+    assert t == pytest.approx(0.2, rel=1e-14)
+    c = st.cell
+    pr = (prob.gamma - 1.0) * (c[3] - 0.5 * (c[1] ** 2 + c[2] ** 2) / c[0])
+    assert (c[0] > 0).all() and (pr > 0).all()
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
+    for j in (12, 18, 23):
+        y = prob.y0 + (j + 0.5) * prob.dy
+        exact = 1.0 / 6.0 + (y + 20.0 * 0.2) / np.sqrt(3.0)
+        assert abs(_shock_x(c[0, j], xc, 8.0, 1.4) - exact) < prob.dx, j
+
+
+def test_blast_wave_stays_physical(oracle):
+    """Sec. 4.2 Woodward-Colella blast wave on 200 cells to t = 3.8 with
+    characteristic variables: every state stays physical, mass is conserved
+    between the reflecting walls, and the two blast waves have collided into
+    a density peak well above the initial unit density."""
+    prob, st = W.blast_1d(200)
+    m0 = st.cell[0].sum()
+    n, t = oracle.run(prob, st, t_end=3.8)
+    c = st.cell[:, 0]
+    pr = (prob.gamma - 1.0) * (c[2] - 0.5 * c[1] ** 2 / c[0])
+    assert (c[0] > 0).all() and (pr > 0).all()
+    assert abs(c[0].sum() - m0) < 1e-11 * m0
+    assert 3.0 < c[0].max() < 7.0
