@@ -96,8 +96,13 @@ struct Grid {
   double* dt;                 // step of the current step
   long long* steps;
   unsigned long long* err;    // 0, or the location of the first nonphysical state (see gks_fetch)
-  unsigned long long* dtmin;  // running minimum of the CFL bound (bits of a positive double)
+  unsigned long long* dtmin;  // kDtSlots running minima of the CFL bound (bits of positive doubles)
 };
+
+// The CFL bound is reduced into kDtSlots slots per problem (one atomic per
+// wave into slot wave % kDtSlots), which keeps the atomics on one address few.
+constexpr int kDtSlots = 64;
+constexpr size_t kScalBytes = 64 + kDtSlots * 8;  // t, dt, steps, err (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
 enum Kind { KK_GA = 0, KK_GB, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };
@@ -380,9 +385,10 @@ __global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a) {
 
 // ---------------------------------------------------------------------------
 // time step: dt = cfl * min over cells of min(h/(|u|+c+2nu/h), k/(|v|+c+2nu/k))
-// The per-cell bound is reduced into g.dtmin (bits of a positive double,
-// ordered like unsigned integers) by the update kernel for the next step (and
-// by its scan form for the initial state); k_dt turns it into the step.
+// The per-cell bound is reduced into the slots g.dtmin (bits of positive
+// doubles, ordered like unsigned integers) by the update kernel for the next
+// step (and by its scan form for the initial state); k_dt takes the minimum
+// of the slots, turns it into the step and resets them.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, double h, double k) {
   const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
@@ -400,13 +406,13 @@ __device__ __forceinline__ double cell_dt_bound_1d(const double* W, const Phys& 
   return h / (fabs(u) + cs + 2.0 * nu / h);
 }
 
-// wave minimum of a positive bound, one atomic per wave (NaN bounds of a
-// nonphysical cell are skipped; the update flags that cell).  Every lane of
-// the wave takes part.
-__device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slot) {
+// wave minimum of a positive bound, one atomic per wave into slot
+// (wave index) % kDtSlots (NaN bounds of a nonphysical cell are skipped; the
+// update flags that cell).  Every lane of the wave takes part.
+__device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slots, unsigned wave) {
   if (!(b > 0.0) || !isfinite(b)) b = 1e300;
   for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(slot, (unsigned long long)__double_as_longlong(b));
+  if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave % kDtSlots), (unsigned long long)__double_as_longlong(b));
 }
 
 // one thread per problem: ctl[2p] = fixed step (0: CFL), ctl[2p+1] = end
@@ -418,10 +424,15 @@ __global__ void __launch_bounds__(256) k_dt(const Prob<TS, TP, TC>* __restrict__
   if (p >= n) return;
   const Grid<TS, TP> g = probs[p].g;
   const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1];
-  double dt = fixed > 0.0 ? fixed : probs[p].P.cfl * __longlong_as_double((long long)*g.dtmin);
+  unsigned long long m = g.dtmin[0];
+  for (int q = 1; q < kDtSlots; ++q) {
+    const unsigned long long b = g.dtmin[q];
+    m = b < m ? b : m;
+  }
+  double dt = fixed > 0.0 ? fixed : probs[p].P.cfl * __longlong_as_double((long long)m);
   if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
   *g.dt = dt;
-  *g.dtmin = (unsigned long long)__double_as_longlong(1e300);
+  for (int q = 0; q < kDtSlots; ++q) g.dtmin[q] = (unsigned long long)__double_as_longlong(1e300);
 }
 
 // ---------------------------------------------------------------------------
@@ -683,12 +694,13 @@ __global__ void __launch_bounds__(256) k_iface_hydro_2d(KA<Prob<TS, TP, TC>> a) 
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
-  if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const double dt = *g.dt;
+  if (!(dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
-  iface_hydro_2d<TC>(P, hs, R, (size_t)id, flux, pvm, pvp, E);
+  iface_hydro_2d<TC>(P, dt, hs, R, (size_t)id, flux, pvm, pvp, E);
   add_corrections(g, F, flux, pvm, pvp);
   if (P.viscous)
 #pragma unroll
@@ -702,12 +714,13 @@ __global__ void __launch_bounds__(256) k_iface_kin_2d(KA<Prob<TS, TP, TC>> a, in
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
-  if (!(*g.dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  const double dt = *g.dt;
+  if (!(dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
-  iface_kinetic_2d<TC>(P, hs, side, R, (size_t)id, flux, pvm, pvp, E);
+  iface_kinetic_2d<TC>(P, dt, hs, side, R, (size_t)id, flux, pvm, pvp, E);
   add_corrections(g, F, flux, pvm, pvp);
   if (P.viscous) {
 #pragma unroll
@@ -803,7 +816,7 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
     }
     bound = cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
   }
-  reduce_dt_bound(bound, g.dtmin);
+  reduce_dt_bound(bound, g.dtmin, (blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 template <typename TS, typename TP, typename TC, bool kScan>
@@ -837,7 +850,7 @@ __global__ void __launch_bounds__(256) k_update_1d(KA<Prob<TS, TP, TC>> a) {
     }
     bound = cell_dt_bound_1d(W, Q.P, g.geo.h);
   }
-  reduce_dt_bound(bound, g.dtmin);
+  reduce_dt_bound(bound, g.dtmin, (blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 // ---------------------------------------------------------------------------
@@ -857,7 +870,7 @@ struct Problem {
   void* PC = nullptr;
   void* FLX = nullptr;
   void* FLY = nullptr;
-  void* scal = nullptr;  // t, dt, steps, err, dtmin
+  void* scal = nullptr;  // t, dt, steps, err, CFL slots (kScalBytes)
   void* recd = nullptr;  // interface frame record, double fields (2D)
   void* rect = nullptr;  // interface frame record, compute-type fields (2D)
 };
@@ -998,7 +1011,7 @@ Grid<TS, TP> grid_of(Problem& p) {
   g.dt = s + 1;
   g.steps = (long long*)(s + 2);
   g.err = (unsigned long long*)(s + 3);
-  g.dtmin = (unsigned long long*)(s + 4);
+  g.dtmin = (unsigned long long*)(s + 8);
   return g;
 }
 
@@ -1280,11 +1293,11 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,        2 * 4 * (ny + 2) * (nx + 3) * ts,
                             2 * 4 * (ny + 3) * (nx + 2) * ts,   4 * 5 * (ny + 2) * (nx + 2) * ts,
                             4 * ny * (nx + 1) * 8,              4 * (ny + 1) * nx * 8,
-                            64,                                 (size_t)ND_REC * nf * 8,
+                            kScalBytes,                         (size_t)ND_REC * nf * 8,
                             (size_t)NT_REC * nf * ts};
       memcpy(sizes, sz, sizeof(sz));
     } else {
-      const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, 64, 0, 0};
+      const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes, 0, 0};
       memcpy(sizes, sz, sizeof(sz));
     }
     for (int b = 0; b < 9; ++b) {
@@ -1333,8 +1346,8 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
            (FY.empty() || hipMemcpy(p.FY, FY.data(), FY.size() * 8, hipMemcpyHostToDevice) == hipSuccess);
     }
     if (!up) return init_fail(GKS_EDEVICE, "upload failed");
-    const unsigned long long inf = (unsigned long long)0x7e37e43c8800759cull;  // bits of 1e300
-    if (hipMemcpy((char*)p.scal + 32, &inf, 8, hipMemcpyHostToDevice) != hipSuccess)
+    const std::vector<unsigned long long> inf(kDtSlots, 0x7e37e43c8800759cull);  // bits of 1e300
+    if (hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * 8, hipMemcpyHostToDevice) != hipSuccess)
       return init_fail(GKS_EDEVICE, "upload failed");
   }
   // groups: problems of one dimension and precision, in problem order
@@ -1488,7 +1501,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
     const Saved s[4] = {{p.W, nullptr, (two ? 4 * (ny + 4) : 3) * (nx + 4) * 8},
                         {p.FX, nullptr, (two ? 2 * 4 * (ny + 2) : 3) * (nx + 3) * ts},
                         {p.FY, nullptr, two ? 2 * 4 * (ny + 3) * (nx + 2) * ts : 0},
-                        {p.scal, nullptr, 64}};
+                        {p.scal, nullptr, kScalBytes}};
     for (const Saved& x : s) {
       if (!x.bytes) continue;
       Saved y = x;

@@ -233,22 +233,56 @@ struct Acc {
 //                       per side).
 // The frame record is a structure of arrays indexed by the interface.
 // ---------------------------------------------------------------------------
+enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
+enum KinW { KW_ICONV, KW_CCONV, KW_IQUAD, KW_CQUAD, KW_IY, KW_C7H, KW_C7, KW_CINNER, KW_AI, KW_AC, KW_TI, KW_TC };
 enum RecD {  // double fields
   D_RHO0, D_U0, D_V0, D_LAM0,
   D_RHOL, D_UL, D_VL, D_LAML, D_H0L, D_H1L,
   D_RHOR, D_UR, D_VR, D_LAMR, D_H0R, D_H1R,
-  D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux)
+  D_TAU,                    // collision time (the phases rebuild the time weights)
+  D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
   ND_REC
 };
 enum RecT {  // compute-type fields
   T_B0 = 0,                 // g0 targets bx, by, bxx, bxy, byy (5 x 4), peculiar frame
-  T_WH = 20,                // hydro weights (13)
-  T_BL = 33, T_BR = 53,     // side targets (5 x 4 each)
-  T_WK = 73,                // kinetic weights (12)
-  NT_REC = 85
+  T_BL = 20, T_BR = 40,     // side targets (5 x 4 each)
+  NT_REC = 60
 };
-enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
-enum KinW { KW_ICONV, KW_CCONV, KW_IQUAD, KW_CQUAD, KW_IY, KW_C7H, KW_C7, KW_CINNER, KW_AI, KW_AC, KW_TI, KW_TC };
+
+// weights of the terms of eq. dis1 (hydro) and eq. dis2 (kinetic) from the
+// time integrals (flux) and values at dt (point values) of C1..C8
+__device__ __forceinline__ void hydro_weights(const TimeWeights& w, double hs, double (&hw)[13]) {
+  const double hs2 = hs * hs * (1.0 / 24.0);
+  hw[HW_I2] = w.I[2];
+  hw[HW_I3] = w.I[3];
+  hw[HW_I4H] = 0.5 * w.I[4];
+  hw[HW_I5H] = 0.5 * w.I[5];
+  hw[HW_I6] = w.I[6];
+  hw[HW_I1Y] = w.I[1] * hs2;
+  hw[HW_C2] = w.C[2];
+  hw[HW_C3] = w.C[3];
+  hw[HW_C4H] = 0.5 * w.C[4];
+  hw[HW_C5H] = 0.5 * w.C[5];
+  hw[HW_C6] = w.C[6];
+  hw[HW_C1] = w.C[1];
+  hw[HW_C1H] = 0.5 * w.C[1];
+}
+__device__ __forceinline__ void kinetic_weights(const TimeWeights& w, double tau, double tv, double hs,
+                                                double (&kw)[12]) {
+  const double hs2 = hs * hs * (1.0 / 24.0);
+  kw[KW_ICONV] = w.I[8] - tv * w.I[7];
+  kw[KW_CCONV] = w.C[8] - tv * w.C[7];
+  kw[KW_IQUAD] = 0.5 * w.I[10] - tv * w.I[8];
+  kw[KW_CQUAD] = 0.5 * w.C[10] - tv * w.C[8];
+  kw[KW_IY] = w.I[7] * hs2;
+  kw[KW_C7H] = 0.5 * w.C[7];
+  kw[KW_C7] = w.C[7];
+  kw[KW_CINNER] = -w.C[9] - tv * w.C[7];
+  kw[KW_AI] = -tau * w.I[7];
+  kw[KW_AC] = -tau * w.C[7];
+  kw[KW_TI] = -tau * w.I[8];
+  kw[KW_TC] = -tau * w.C[8];
+}
 
 template <typename TC>
 struct Rec {
@@ -359,27 +393,17 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   // collision time (Sec. 4) and the time weights
   const double jump = fabs((pr[0] - pr[1]) / (pr[0] + pr[1]));
   const double tau = P.viscous ? P.mu / p0 + P.tau_c * jump * dt : (P.tau_eps + P.tau_c * jump) * dt;
-  TimeWeights w;
-  time_weights(tau, dt, w);
-  const double hs2 = hs * hs * (1.0 / 24.0);
-  const double hw[13] = {w.I[2], w.I[3], 0.5 * w.I[4], 0.5 * w.I[5], w.I[6], w.I[1] * hs2, w.C[2],
-                         w.C[3], 0.5 * w.C[4], 0.5 * w.C[5], w.C[6], w.C[1], 0.5 * w.C[1]};
-#pragma unroll
-  for (int k = 0; k < 13; ++k) R.T(T_WH + k, f) = (TC)hw[k];
-  const double tv = P.viscous ? tau : 0.0;  // Euler: f_G = g_k
-  const double kw[12] = {w.I[8] - tv * w.I[7],       w.C[8] - tv * w.C[7],       0.5 * w.I[10] - tv * w.I[8],
-                         0.5 * w.C[10] - tv * w.C[8], w.I[7] * hs2,               0.5 * w.C[7],
-                         w.C[7],                      -w.C[9] - tv * w.C[7],      -tau * w.I[7],
-                         -tau * w.C[7],               -tau * w.I[8],              -tau * w.C[8]};
-#pragma unroll
-  for (int k = 0; k < 12; ++k) R.T(T_WK + k, f) = (TC)kw[k];
-  // leading terms: Euler flux of U0 (C1 g0) and free transport of the sides (C7 g_k)
+  R.D(D_TAU, f) = tau;
+  // leading terms: Euler flux of U0 (C1 g0) and free transport of the sides
+  // (C7 g_k); only the two time integrals of the leading terms are needed here
+  const double E = tau > 0.0 ? exp(-dt / tau) : 0.0;
+  const double I7 = tau * (1.0 - E), I1 = dt - I7;
   const double FE[4] = {W0[1], W0[1] * U0 + p0, W0[1] * V0, U0 * (W0[3] + p0)};
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    flux[v] = hs * (w.I[1] * FE[v] + w.I[7] * Fk[v]);
+    flux[v] = hs * (I1 * FE[v] + I7 * Fk[v]);
     pv[v] = W0[v];  // C1 + C7 = 1
-    R.D(D_E0 + v, f) = hs * dt * W0[v];
+    if (P.viscous) R.D(D_E0 + v, f) = hs * dt * W0[v];
   }
   return true;
 }
@@ -393,7 +417,7 @@ struct Coefs {
 // Hydrodynamic phase of interface f: corrections to flux, point values and
 // the integrated density (lab frame, interface frame components).
 template <typename TC>
-__device__ __forceinline__ void iface_hydro_2d(const Phys& P, double hs, const Rec<TC>& R, size_t f,
+__device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double hs, const Rec<TC>& R, size_t f,
                                                double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                double (&E)[4]) {
   const double rho0 = R.D(D_RHO0, f), U0 = R.D(D_U0, f), V0 = R.D(D_V0, f), lam0 = R.D(D_LAM0, f);
@@ -413,8 +437,14 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double hs, const R
                    c.bxt, c.byt, c.Bt);
   }
   TC w[13];
+  {
+    TimeWeights tw;
+    time_weights(R.D(D_TAU, f), dt, tw);
+    double hw[13];
+    hydro_weights(tw, hs, hw);
 #pragma unroll
-  for (int k = 0; k < 13; ++k) w[k] = R.T(T_WH + k, f);
+    for (int k = 0; k < 13; ++k) w[k] = (TC)hw[k];
+  }
   Acc<TC> A;
   TC m0[4], m1[4];
   // C2 g0 (a1 u + a2 v)
@@ -456,8 +486,8 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double hs, const R
 
 // Kinetic phase of interface f, side s (0: g_l on u > 0, 1: g_r on u < 0).
 template <typename TC>
-__device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double hs, int s, const Rec<TC>& R, size_t f,
-                                                 double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
+__device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, double hs, int s, const Rec<TC>& R,
+                                                 size_t f, double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                  double (&E)[4]) {
   const int o = s == 0 ? D_RHOL : D_RHOR;
   const double rho = R.D(o, f), U = R.D(o + 1, f), V = R.D(o + 2, f), lam = R.D(o + 3, f);
@@ -486,8 +516,15 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double hs, int s
                              c.dxy, c.dyy, c.bxt, c.byt, c.Bt);
   }
   TC w[12];
+  {
+    const double tau = R.D(D_TAU, f);
+    TimeWeights tw;
+    time_weights(tau, dt, tw);
+    double kw[12];
+    kinetic_weights(tw, tau, P.viscous ? tau : 0.0, hs, kw);  // Euler: f_G = g_k
 #pragma unroll
-  for (int k = 0; k < 12; ++k) w[k] = R.T(T_WK + k, f);
+    for (int k = 0; k < 12; ++k) w[k] = (TC)kw[k];
+  }
   Acc<TC> A;
   TC m0[4], m1[4];
   // C8 g (a1 u + a2 v)  [and -tau C7 g (a1 u + a2 v)]
