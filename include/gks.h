@@ -10,13 +10,22 @@
  *   3. compact reconstruction of every cell from its average, its face
  *      neighbours' averages and the tracked interface Gauss-point values
  *      (Sec. 3.1, 3.2: one-sided stencils, limiter eq. limiter, central
- *      stencil, nonlinear weights eq. average);
+ *      stencil, nonlinear weights eq. average; in 1D optionally in
+ *      characteristic variables, Sec. 4);
  *   4. at every interface: the equilibrium state U0 (eq. compatibility2), its
  *      quadratic (Sec. 3.3), the collision time (Sec. 4), the expansion
  *      coefficients (system after eq. dis3), the time- and interface-integrated
  *      flux (eq. finite with eq. dis1 + eq. dis2) and the point values at the
  *      next time level (eq. point);
  *   5. the conservative update (eq. finite).
+ *
+ * A handle advances any number of independent problems (1D and 2D, both
+ * precisions, uneven sizes) together: every step is one launch per phase for
+ * all problems of a dimension and precision, replayed from one captured HIP
+ * graph.  Where the paper leaves the reconstruction's robustness open, a
+ * reconstructed cell polynomial whose density or pressure at an interface
+ * centre is nonpositive or more than a factor two outside the range of the
+ * neighbouring averages is replaced by the constant average for the step.
  *
  * Every call returns an int status (GKS_OK or a negative GKS_E* code); no C++
  * exception crosses the ABI.  All arrays are plain memory with the layouts
@@ -96,8 +105,8 @@ typedef struct {
 
 typedef struct gks_handle gks_handle; /* opaque, owned by the library */
 
-/* Create a handle for n_problems independent grids (n_problems > 1: a batch,
- * advanced together by gks_step) and upload their initial state.
+/* Create a handle for n_problems (1..65535) independent grids (more than one:
+ * a batch, advanced together by gks_step) and upload their initial state.
  *   cell[p]   : host, [nvar][ny][nx] cell averages, nvar = dim + 2
  *   face_x[p] : host, [ng][nvar][ny][nx+1] point values on the x interfaces,
  *               ng = 2 (2D: Gauss points y_j -/+ sqrt(3)/6 dy, in that order) or 1 (1D)
@@ -113,7 +122,7 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs,
              const double* const* face_y, void* stream);
 
 /* Enqueue nsteps time steps of every problem (asynchronous; returns after the
- * launches).  dt_fixed: NULL to take each step from the CFL condition on the
+ * launches: nsteps replays of the step graph, captured at the first call).  dt_fixed: NULL to take each step from the CFL condition on the
  * device, else dt_fixed[p] for every step of problem p.  t_end: NULL for no
  * limit, else the last step of problem p is shortened to end at t_end[p] and
  * later steps leave it unchanged.  Arguments are validated before anything
