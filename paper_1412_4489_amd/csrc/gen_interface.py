@@ -18,6 +18,11 @@ the interface point values need (Pan & Xu, arXiv:1412.4489, Sec. 2.2):
                 velocity space (g0) or over the half space of one side (g_l on
                 u > 0, g_r on u < 0).  The time weights are applied by the caller.
 
+The moment functions are emitted in two stages: first the monomial
+coefficients of the term's velocity polynomial (with shared subexpressions),
+then the accumulation of every monomial's moments into the outputs, which
+keeps only the coefficients live between the stages.
+
 Whole-space central moments are closed forms in theta = 1/(2 lambda) and K;
 half-space moments enter as the runtime table h[n] = <c^n>_half.  Products of
 coefficient polynomials are formed symbolically, every moment that vanishes
@@ -347,6 +352,35 @@ def gen_term(dim, name, half):
     return ins, flux, out
 
 
+def gen_term_two_stage(dim, name, half):
+    """The same moments as gen_term in two stages with separate common
+    subexpressions: (1) the monomial coefficients p_abe of the term's velocity
+    polynomial X = sum p_abe c^a w^b z^e from the expansion coefficients;
+    (2) m0_i = sum p_abe <psi'_i c^a w^b z^e>, m1_i = sum p_abe <c psi'_i ...>.
+    Only the coefficients are live between the stages (a smaller register
+    peak than one expanded expression per output)."""
+    TH, KP = theta_syms()
+    H = [sp.Symbol(f"h[{n}]") for n in range(12)] if half else None
+    M = Moments(dim, half, TH, KP, H)
+    P, ins, flux = term_polys(dim)[name]
+    keys = sorted(P.t)
+    psyms = {k: sp.Symbol(f"p_{k[0]}_{k[1]}_{k[2]}") for k in keys}
+    stage1 = [(str(psyms[k]), P.t[k]) for k in keys]
+    # stage 2 as accumulation, monomial by monomial: out += p_k * <psi' mono_k>
+    outs = [f"m0[{i}]" for i in range(len(psi(dim)))]
+    if flux:
+        outs += [f"m1[{i}]" for i in range(len(psi(dim)))]
+    acc = []
+    for k in keys:
+        mono = VP({k: 1})
+        vals = M.psi(mono) + (M.psi(mono, C) if flux else [])
+        for o, v in zip(outs, vals):
+            v = sp.expand(v)
+            if v != 0:
+                acc.append((o, psyms[k], v))
+    return ins, flux, stage1, (outs, acc)
+
+
 HEADER = """// interface_gen.h -- GENERATED by gen_interface.py; do not edit by hand.
 //
 // Straight-line velocity-moment arithmetic of one Maxwellian in its peculiar
@@ -360,9 +394,14 @@ HEADER = """// interface_gen.h -- GENERATED by gen_interface.py; do not edit by 
 """
 
 
+# terms generated in two stages (see gen_term_two_stage)
+TWO_STAGE = ("conv", "A", "quad", "ttt", "tlin", "dyy", "ay", "inner", "ty")
+
+
 def main():
     body = [HEADER]
     report = []
+    emitted = []
     for dim in (2, 1):
         nv = dim + 2
         for which, tag in ((0, "g0"), (1, "side_euler"), (2, "side_ns")):
@@ -382,10 +421,26 @@ def main():
             report.append((f"coef_{tag}_{dim}d", total))
         for half, tag in ((False, "full"), (True, "half")):
             for name in term_polys(dim):
-                ins, flux, outs = gen_term(dim, name, half)
                 if half and name in ("ttt",):
                     continue  # B is not part of the kinetic part
-                l, n = emit(None, outs)
+                if name in TWO_STAGE:
+                    ins, flux, stage1, (onames, acc) = gen_term_two_stage(dim, name, half)
+                    l1, n1 = emit(None, stage1, indent="    ")
+                    decl = "  T " + ", ".join(n for n, _ in stage1) + ";"
+                    l2 = [f"  {o} = T(0);" for o in onames]
+                    n2 = 0
+                    for o, pk, v in acc:
+                        l2.append(f"  {o} += {pk} * ({PR.doprint(v)});")
+                        n2 += 2 + sp.count_ops(v)
+                    l = [decl, "  {"] + l1 + ["  }"] + l2
+                    # the algorithmic count: the same moments as one expanded
+                    # expression per output with shared subexpressions
+                    _, _, outs_cse = gen_term(dim, name, half)
+                    _, n = emit(None, outs_cse)
+                    emitted.append((f"mom_{tag}_{name}_{dim}d", n1 + n2))
+                else:
+                    ins, flux, outs = gen_term(dim, name, half)
+                    l, n = emit(None, outs)
                 args = ", ".join(f"const T* {a}" for a in ins)
                 hh = "const T* __restrict__ h, " if half else ""
                 res = "T* m0, T* m1" if flux else "T* m0"
@@ -398,10 +453,13 @@ def main():
     out = os.path.join(HERE, "interface_gen.h")
     with open(out, "w") as f:
         f.write("\n".join(body))
+    em = dict(emitted)
     for name, n in report:
-        print(f"{name:24s} ~{n} ops")
+        print(f"{name:24s} ~{n} ops" + (f"   (emitted form ~{em[name]})" if name in em else ""))
     # floating-point operations (sympy count_ops: one per +, -, *, /) of the
-    # generated functions, used as the algorithmic count of an interface
+    # generated functions in the form with shared subexpressions (the emitted
+    # two-stage form trades some of them for a lower register peak), used as
+    # the algorithmic count of an interface
     import json
     with open(os.path.join(HERE, "interface_ops.json"), "w") as f:
         json.dump({name: int(n) for name, n in report}, f, indent=1)
