@@ -5,7 +5,7 @@
 // the same dimension and precision form a group; one time step of a group is
 // a fixed sequence of launches, each covering every problem of the group
 // (a block-owner table maps each block to its problem and tile):
-//   2D: k_ghost_we, k_ghost_sn   boundary images (cells: two layers incl.
+//   2D: k_ghost_2d               boundary images (cells: two layers incl.
 //                                corners; interface values of edge ghosts)
 //       k_dt                     CFL time step or the fixed step, per problem
 //       k_recon_2d               compact reconstruction (Sec. 3.2)
@@ -105,7 +105,7 @@ constexpr int kDtSlots = 64;
 constexpr size_t kScalBytes = 64 + kDtSlots * 8;  // t, dt, steps, err (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
-enum Kind { KK_GA = 0, KK_GB, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };
+enum Kind { KK_GA = 0, KK_GB, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };  // KK_GB: unused (no work)
 
 // device descriptor of one problem, read by every kernel
 template <typename TS, typename TP, typename TC>
@@ -203,12 +203,27 @@ __device__ void bc_mirror_1d(const BCDev& b, double gamma, const double* s, doub
   }
 }
 
+// image of ghost cell (j, ig), ig < 0 or ig >= nx, of an interior row j under
+// the west (ig < 0) or east boundary
+template <typename TS, typename TP, typename TC>
+__device__ void ghost_x_cell(const Prob<TS, TP, TC>& Q, const Grid<TS, TP>& g, double t, int j, int ig, double* out) {
+  const int nx = g.ix.nx, side = ig < 0 ? 0 : 1;
+  const BCDev& b = Q.bc[side];
+  const double xc = g.geo.x0 + (ig + 0.5) * g.geo.h, yc = g.geo.y0 + (j + 0.5) * g.geo.k;
+  if (bc_fixed(b, 4, xc, yc, t, out)) return;
+  double src[4];
+  const int is = b.kind == GKS_BC_PERIODIC ? (side == 0 ? ig + nx : ig - nx) : (side == 0 ? -1 - ig : 2 * nx - 1 - ig);
+  for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, j, is)];
+  if (b.kind == GKS_BC_PERIODIC)
+    for (int v = 0; v < 4; ++v) out[v] = src[v];
+  else
+    bc_mirror(b, 0, Q.P.gamma, src, out);
+}
+
 // West (side 0) / east (side 1): ghost cells of rows 0..ny-1, ghost x
 // interfaces -1 / nx+1, and the y interfaces of the ghost columns -1 / nx.
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_ghost_we(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+__device__ void ghost_we_item(const Prob<TS, TP, TC>& Q, int id) {
   const Grid<TS, TP> g = Q.g;
   const double gamma = Q.P.gamma;
   const int nx = g.ix.nx, ny = g.ix.ny;
@@ -218,21 +233,8 @@ __global__ void __launch_bounds__(256) k_ghost_we(KA<Prob<TS, TP, TC>> a) {
   double src[4], out[4];
   if (id < ncell) {
     const int side = id / (2 * ny), r = id % (2 * ny), j = r / 2, m = r % 2;
-    const BCDev& b = Q.bc[side];
     const int ig = side == 0 ? -1 - m : nx + m;
-    const double xc = g.geo.x0 + (ig + 0.5) * h, yc = g.geo.y0 + (j + 0.5) * k;
-    if (!bc_fixed(b, 4, xc, yc, t, out)) {
-      int is;
-      if (b.kind == GKS_BC_PERIODIC)
-        is = side == 0 ? ig + nx : ig - nx;
-      else
-        is = side == 0 ? -1 - ig : 2 * nx - 1 - ig;
-      for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, j, is)];
-      if (b.kind == GKS_BC_PERIODIC)
-        for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 0, gamma, src, out);
-    }
+    ghost_x_cell(Q, g, t, j, ig, out);
     for (int v = 0; v < 4; ++v) g.W[g.ix.w(v, j, ig)] = out[v];
     return;
   }
@@ -273,13 +275,12 @@ __global__ void __launch_bounds__(256) k_ghost_we(KA<Prob<TS, TP, TC>> a) {
   }
 }
 
-// South (side 2) / north (side 3): ghost cells of columns -2..nx+1 (corners
-// from the west/east images), ghost y interfaces -1 / ny+1, and the x
-// interfaces of the ghost rows -1 / ny.
+// South (side 2) / north (side 3): ghost cells of columns -2..nx+1 (the
+// corners are the south/north images of the west/east images, composed here
+// so that this part does not wait for the west/east part), ghost y interfaces
+// -1 / ny+1, and the x interfaces of the ghost rows -1 / ny.
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_ghost_sn(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_GB, id);
+__device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
   const Grid<TS, TP> g = Q.g;
   const double gamma = Q.P.gamma;
   const int nx = g.ix.nx, ny = g.ix.ny;
@@ -298,7 +299,10 @@ __global__ void __launch_bounds__(256) k_ghost_sn(KA<Prob<TS, TP, TC>> a) {
         js = side == 0 ? jg + ny : jg - ny;
       else
         js = side == 0 ? -1 - jg : 2 * ny - 1 - jg;
-      for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, js, i)];
+      if (i < 0 || i >= nx)
+        ghost_x_cell(Q, g, t, js, i, src);
+      else
+        for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, js, i)];
       if (b.kind == GKS_BC_PERIODIC)
         for (int v = 0; v < 4; ++v) out[v] = src[v];
       else
@@ -342,6 +346,19 @@ __global__ void __launch_bounds__(256) k_ghost_sn(KA<Prob<TS, TP, TC>> a) {
     }
     for (int v = 0; v < 4; ++v) g.FX[g.ix.fx(gp, v, jg, fi)] = (TS)out[v];
   }
+}
+
+// all 2D boundary images of a problem in one launch
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+  const int nx = Q.g.ix.nx, ny = Q.g.ix.ny;
+  const int nwe = 4 * ny + 4 * ny + 4 * (ny + 1), nsn = 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
+  if (id < nwe)
+    ghost_we_item(Q, id);
+  else if (id < nwe + nsn)
+    ghost_sn_item(Q, id - nwe);
 }
 
 // 1D: tasks (side, m), m = 0, 1 ghost cells -1-m / nx+m, m = 2 the ghost
@@ -979,8 +996,8 @@ size_t work_items(const Problem& p, int dim, int k) {
   const size_t nx = p.ix.nx, ny = p.ix.ny;
   if (dim == 2) {
     switch (k) {
-      case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1);
-      case KK_GB: return 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
+      case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1) + 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
+      case KK_GB: return 0;
       case KK_RECON: return (nx + 2) * (ny + 2);
       case KK_FACE: return n_interfaces(p.ix);
       default: return nx * ny;
@@ -1106,8 +1123,7 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   const int n = (int)G.members.size();
   record_begin(h, st);
   if (G.dim == 2) {
-    k_ghost_we<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
-    k_ghost_sn<TS, TP, TC><<<G.nblk[KK_GB], G.bs[KK_GB], 0, st>>>(A[KK_GB]);
+    k_ghost_2d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
   } else {
     k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
   }

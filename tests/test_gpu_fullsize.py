@@ -66,8 +66,6 @@ def test_full_size_parity(G, oracle, case, prec):
         got, t, n, rc = S.fetch(check=False)
     assert n == nsteps
     # the GPU flags a nonphysical state exactly when the oracle's has one
-    # (the double Mach reflection at this resolution has a few such cells
-    # after the first step in both implementations)
     c = ref.cell
     pr = (prob.gamma - 1.0) * (c[3] - 0.5 * (c[1] ** 2 + c[2] ** 2) / c[0])
     bad = (c[0] <= 0) | (pr <= 0)
