@@ -114,6 +114,9 @@ typedef struct gks_handle gks_handle; /* opaque, owned by the library */
  *               (Gauss points x_i -/+ sqrt(3)/6 dx); NULL when dim == 1
  *   stream    : a hipStream_t the library launches on (borrowed; it must
  *               outlive the handle), or NULL for a stream of the library's own.
+ * On a periodic axis the last interface is the first one: its point values
+ * are taken from the first interface (face_x[..][0], face_y[..][0][..]) and it
+ * is computed once per step.
  * Host arrays are read during the call only.  Returns GKS_EINVAL for an
  * inconsistent problem (sizes, gamma, unknown boundary kind, nonphysical
  * initial state), GKS_ENOMEM / GKS_EDEVICE on device failures. */

@@ -50,6 +50,10 @@ namespace {
 // ---------------------------------------------------------------------------
 struct Idx {
   int nx, ny;
+  // computed interfaces: fxr x interfaces per row, fyr rows of y interfaces.
+  // On a periodic axis the last interface is the first one and is not
+  // computed again (fxr = nx, fyr = ny; else nx + 1, ny + 1).
+  int fxr, fyr;
   __device__ __host__ size_t w(int v, int j, int i) const {
     return ((size_t)v * (ny + 4) + (size_t)(j + 2)) * (nx + 4) + (size_t)(i + 2);
   }
@@ -579,12 +583,12 @@ struct Face {
 };
 
 __device__ __forceinline__ Face face_of(const Idx& x, int id) {
-  const int nfx = (x.nx + 1) * x.ny;
+  const int nfx = x.fxr * x.ny;
   Face F;
   F.isx = id < nfx;
   if (F.isx) {
-    F.a = id / (x.nx + 1);
-    F.b = id % (x.nx + 1);
+    F.a = id / x.fxr;
+    F.b = id % x.fxr;
   } else {
     const int r = id - nfx;
     F.a = r / x.nx;
@@ -597,7 +601,39 @@ __device__ __forceinline__ Face face_of(const Idx& x, int id) {
 // two momentum components
 __device__ __forceinline__ int loc(bool isx, int v) { return isx ? v : (v == 1 ? 2 : v == 2 ? 1 : v); }
 
-__device__ __forceinline__ int n_faces(const Idx& x) { return (x.nx + 1) * x.ny + x.nx * (x.ny + 1); }
+__device__ __forceinline__ int n_faces(const Idx& x) { return x.fxr * x.ny + x.nx * x.fyr; }
+
+// average and reconstruction of side s's cell of interface F in the interface
+// frame (y interfaces swap the momentum components and the two directions)
+template <typename TS, typename TP>
+__device__ __forceinline__ void load_face_cell(const Grid<TS, TP>& g, const Face& F, int s, double (&Wc)[4],
+                                               double (&pc)[4][5]) {
+  const Idx& x = g.ix;
+  if (F.isx) {
+    const int j = F.a, ic = F.b - 1 + s;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wc[v] = g.W[x.w(v, j, ic)];
+      pc[v][0] = (double)g.PC[x.pc(v, 0, j, ic)];  // p_n  = p2
+      pc[v][1] = (double)g.PC[x.pc(v, 1, j, ic)];  // p_s  = p3
+      pc[v][2] = (double)g.PC[x.pc(v, 2, j, ic)];  // p_nn = p4
+      pc[v][3] = (double)g.PC[x.pc(v, 3, j, ic)];  // p_ss = p5
+      pc[v][4] = (double)g.PC[x.pc(v, 4, j, ic)];  // p_ns = p6
+    }
+  } else {
+    const int jc = F.a - 1 + s, i = F.b;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int vl = loc(false, v);
+      Wc[vl] = g.W[x.w(v, jc, i)];
+      pc[vl][0] = (double)g.PC[x.pc(v, 1, jc, i)];  // p_n  = p3
+      pc[vl][1] = (double)g.PC[x.pc(v, 0, jc, i)];  // p_s  = p2
+      pc[vl][2] = (double)g.PC[x.pc(v, 3, jc, i)];  // p_nn = p5
+      pc[vl][3] = (double)g.PC[x.pc(v, 2, jc, i)];  // p_ss = p4
+      pc[vl][4] = (double)g.PC[x.pc(v, 4, jc, i)];  // p_ns = p6
+    }
+  }
+}
 
 template <typename TS, typename TP, typename TC>
 __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
@@ -612,21 +648,10 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
   double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
+  load_face_cell(g, F, 0, Wc[0], pc[0]);
+  load_face_cell(g, F, 1, Wc[1], pc[1]);
   if (F.isx) {
     const int j = F.a, fi = F.b;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int ic = fi - 1 + s;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Wc[s][v] = g.W[x.w(v, j, ic)];
-        pc[s][v][0] = (double)g.PC[x.pc(v, 0, j, ic)];  // p_n  = p2
-        pc[s][v][1] = (double)g.PC[x.pc(v, 1, j, ic)];  // p_s  = p3
-        pc[s][v][2] = (double)g.PC[x.pc(v, 2, j, ic)];  // p_nn = p4
-        pc[s][v][3] = (double)g.PC[x.pc(v, 3, j, ic)];  // p_ss = p5
-        pc[s][v][4] = (double)g.PC[x.pc(v, 4, j, ic)];  // p_ns = p6
-      }
-    }
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -635,20 +660,6 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
         for (int v = 0; v < 4; ++v) Ueq[m][n][v] = g.W[x.w(v, j - 1 + n, fi - 1 + m)];
   } else {
     const int fj = F.a, i = F.b;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int jc = fj - 1 + s;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int vl = loc(false, v);
-        Wc[s][vl] = g.W[x.w(v, jc, i)];
-        pc[s][vl][0] = (double)g.PC[x.pc(v, 1, jc, i)];  // p_n  = p3
-        pc[s][vl][1] = (double)g.PC[x.pc(v, 0, jc, i)];  // p_s  = p2
-        pc[s][vl][2] = (double)g.PC[x.pc(v, 3, jc, i)];  // p_nn = p5
-        pc[s][vl][3] = (double)g.PC[x.pc(v, 2, jc, i)];  // p_ss = p4
-        pc[s][vl][4] = (double)g.PC[x.pc(v, 4, jc, i)];  // p_ns = p6
-      }
-    }
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -735,9 +746,11 @@ __global__ void __launch_bounds__(256) k_iface_kin_2d(KA<Prob<TS, TP, TC>> a, in
   if (!(dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
-  const double hs = F.isx ? g.geo.k : g.geo.h;
+  const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
+  double Wc[4], pc[4][5];
+  load_face_cell(g, F, side, Wc, pc);
   double flux[4], pvm[4], pvp[4], E[4];
-  iface_kinetic_2d<TC>(P, dt, hs, side, R, (size_t)id, flux, pvm, pvp, E);
+  iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, (size_t)id, flux, pvm, pvp, E);
   add_corrections(g, F, flux, pvm, pvp);
   if (P.viscous) {
 #pragma unroll
@@ -815,13 +828,23 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
     const double dt = kScan ? 0.0 : *g.dt;
     if (dt > 0.0) {
       const double ia = 1.0 / (g.geo.h * g.geo.k);
+      // periodic seams: the last interface is the first one
+      const int ie = (i + 1 == nx && x.fxr == nx) ? 0 : i + 1;
+      const int je = (j + 1 == ny && x.fyr == ny) ? 0 : j + 1;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double d = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, i + 1)] + g.FLY[x.fly(v, j, i)] -
-                         g.FLY[x.fly(v, j + 1, i)];
+        const double d = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, ie)] + g.FLY[x.fly(v, j, i)] -
+                         g.FLY[x.fly(v, je, i)];
         W[v] += d * ia;
         g.W[x.w(v, j, i)] = W[v];
       }
+      // and gets its new point values (read by the next reconstruction)
+      if (i == 0 && x.fxr == nx)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g.FX[x.fx(q >> 2, q & 3, j, nx)] = g.FX[x.fx(q >> 2, q & 3, j, 0)];
+      if (j == 0 && x.fyr == ny)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g.FY[x.fy(q >> 2, q & 3, ny, i)] = g.FY[x.fy(q >> 2, q & 3, 0, i)];
       const double p = (Q.P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
       if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
         atomicCAS(g.err, 0ull,
@@ -987,7 +1010,7 @@ std::string validate(const gks_problem& p) {
   return "";
 }
 
-size_t n_interfaces(const Idx& x) { return (size_t)(x.nx + 1) * x.ny + (size_t)x.nx * (x.ny + 1); }
+size_t n_interfaces(const Idx& x) { return (size_t)x.fxr * x.ny + (size_t)x.nx * x.fyr; }
 
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -1249,7 +1272,12 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
     Problem& p = h->probs[n];
     p.spec = s;
     p.mixed = s.precision == GKS_FP32_MIXED;
-    p.ix = Idx{s.nx, s.dim == 2 ? s.ny : 1};
+    {
+      const int ny = s.dim == 2 ? s.ny : 1;
+      const bool px = s.dim == 2 && s.bc[0].kind == GKS_BC_PERIODIC;
+      const bool py = s.dim == 2 && s.bc[2].kind == GKS_BC_PERIODIC;
+      p.ix = Idx{s.nx, ny, px ? s.nx : s.nx + 1, py ? ny : ny + 1};
+    }
     p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, s.dim == 2 ? (s.y1 - s.y0) / s.ny : 1.0};
     Phys& P = p.phys;
     memset(&P, 0, sizeof(P));
@@ -1341,6 +1369,11 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
           for (int fj = 0; fj <= s.ny; ++fj)
             for (int i = 0; i < s.nx; ++i)
               FY[x.fy(g, v, fj, i)] = face_y[n][(((size_t)g * 4 + v) * (s.ny + 1) + fj) * s.nx + i];
+          // a periodic seam is one interface: its values are those of the first
+          if (x.fxr == s.nx)
+            for (int j = 0; j < s.ny; ++j) FX[x.fx(g, v, j, s.nx)] = FX[x.fx(g, v, j, 0)];
+          if (x.fyr == s.ny)
+            for (int i = 0; i < s.nx; ++i) FY[x.fy(g, v, s.ny, i)] = FY[x.fy(g, v, 0, i)];
         }
     } else {
       for (int v = 0; v < 3; ++v) {

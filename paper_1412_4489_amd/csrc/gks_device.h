@@ -165,11 +165,14 @@ __device__ __forceinline__ void theta_powers(double th, T* t) {
 }
 
 // Accumulators of the correction moments of one Maxwellian in its frame:
-// flux moments AF = <psi' P_F>, BF = <c psi' P_F> and point-value moments
-// V0, V1, V2 of the y^0, y^1, y^2 parts.
+// flux moments AF = <psi' P_F>, BF = <c psi' P_F>, and the point values at the
+// two Gauss points y = -delta (PM) and +delta (PP) of the interface, to which
+// the y^0, y^1, y^2 parts contribute with weights 1, -+delta, delta^2.
 template <typename TC>
 struct Acc {
-  TC AF[4] = {0, 0, 0, 0}, BF[4] = {0, 0, 0, 0}, V0[4] = {0, 0, 0, 0}, V1[4] = {0, 0, 0, 0}, V2[4] = {0, 0, 0, 0};
+  TC AF[4] = {0, 0, 0, 0}, BF[4] = {0, 0, 0, 0}, PM[4] = {0, 0, 0, 0}, PP[4] = {0, 0, 0, 0};
+  TC d, d2;
+  __device__ __forceinline__ explicit Acc(double delta) : d((TC)delta), d2((TC)(delta * delta)) {}
   __device__ __forceinline__ void flux(const TC* m0, const TC* m1, TC w) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -179,37 +182,46 @@ struct Acc {
   }
   __device__ __forceinline__ void pv0(const TC* m0, TC w) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) V0[v] += w * m0[v];
+    for (int v = 0; v < 4; ++v) {
+      const TC a = w * m0[v];
+      PM[v] += a;
+      PP[v] += a;
+    }
   }
   __device__ __forceinline__ void pv1(const TC* m0, TC w) {
+    const TC wd = w * d;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) V1[v] += w * m0[v];
+    for (int v = 0; v < 4; ++v) {
+      const TC a = wd * m0[v];
+      PM[v] -= a;
+      PP[v] += a;
+    }
   }
   __device__ __forceinline__ void pv2(const TC* m0, TC w) {
+    const TC wd = w * d2;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) V2[v] += w * m0[v];
+    for (int v = 0; v < 4; ++v) {
+      const TC a = wd * m0[v];
+      PM[v] += a;
+      PP[v] += a;
+    }
   }
   // back to lab-frame moments, times rho (and the interface length for the
   // integrated flux), added to the double-precision totals
-  template <int NV>
-  __device__ __forceinline__ void add_to(double U, double V, double rho, double hs, double delta, double* flux,
-                                         double* pvm, double* pvp, double* Edens) const {
-    TC fl[4], pm[4], pp[4];
-    const TC d = (TC)delta, d2 = (TC)(delta * delta), u = (TC)U;
+  __device__ __forceinline__ void add_to(double U, double V, double rho, double hs, double* flux, double* pvm,
+                                         double* pvp, double* Edens) const {
+    TC fl[4];
+    const TC u = (TC)U;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      fl[v] = BF[v] + u * AF[v];
-      pm[v] = V0[v] - d * V1[v] + d2 * V2[v];
-      pp[v] = V0[v] + d * V1[v] + d2 * V2[v];
-    }
+    for (int v = 0; v < 4; ++v) fl[v] = BF[v] + u * AF[v];
     double a[4];
     from_frame_2d(fl, U, V, a);
 #pragma unroll
     for (int v = 0; v < 4; ++v) flux[v] += hs * rho * a[v];
-    from_frame_2d(pm, U, V, a);
+    from_frame_2d(PM, U, V, a);
 #pragma unroll
     for (int v = 0; v < 4; ++v) pvm[v] += rho * a[v];
-    from_frame_2d(pp, U, V, a);
+    from_frame_2d(PP, U, V, a);
 #pragma unroll
     for (int v = 0; v < 4; ++v) pvp[v] += rho * a[v];
     if (Edens) {
@@ -225,29 +237,38 @@ struct Acc {
 // each phase holds only its own working set in registers:
 //   prologue  (double)  interface values of the two cell polynomials, their
 //                       half-space moments, U0 (eq. compatibility2), the
-//                       equilibrium quadratic (Sec. 3.3), tau (Sec. 4), the
-//                       time integrals; leading flux and point values; the
-//                       frame record of the three Maxwellians;
-//   hydro     (TC)      coefficients of g0 and the terms of eq. dis1;
-//   kinetic   (TC)      coefficients of g_k and the terms of eq. dis2 (once
-//                       per side).
-// The frame record is a structure of arrays indexed by the interface.
+//                       equilibrium quadratic (Sec. 3.3), tau (Sec. 4); the
+//                       leading flux and point values; (TC) the expansion
+//                       coefficients of g0; the record of g0;
+//   hydro     (TC)      the terms of eq. dis1;
+//   kinetic   (double)  the side's interface state, half-space moments and
+//                       targets again (from its cell, same arithmetic as in
+//                       the prologue), (TC) the coefficients of g_k and the
+//                       terms of eq. dis2 (once per side).
+// The record is a structure of arrays indexed by the interface.
 // ---------------------------------------------------------------------------
 enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
 enum KinW { KW_ICONV, KW_CCONV, KW_IQUAD, KW_CQUAD, KW_IY, KW_C7H, KW_C7, KW_CINNER, KW_AI, KW_AC, KW_TI, KW_TC };
 enum RecD {  // double fields
   D_RHO0, D_U0, D_V0, D_LAM0,
-  D_RHOL, D_UL, D_VL, D_LAML, D_H0L, D_H1L,
-  D_RHOR, D_UR, D_VR, D_LAMR, D_H0R, D_H1R,
   D_TAU,                    // collision time (the phases rebuild the time weights)
   D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
   ND_REC
 };
 enum RecT {  // compute-type fields
-  T_B0 = 0,                 // g0 targets bx, by, bxx, bxy, byy (5 x 4), peculiar frame
-  T_BL = 20, T_BR = 40,     // side targets (5 x 4 each)
-  NT_REC = 60
+  T_CG = 0,                 // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar
+                            // frame; in double precision its targets bx, by, bxx, bxy, byy (5 x 4)
+  NT_REC = 36
 };
+
+// Where the coefficient systems of g0 are solved: in the prologue for a
+// single-precision compute type (it then leaves the hydrodynamic phase within
+// two waves per SIMD), in the hydrodynamic phase for double precision (where
+// the prologue would lose its second wave).
+template <typename TC>
+constexpr bool g0_solved_in_prologue() {
+  return sizeof(TC) == 4;
+}
 
 // weights of the terms of eq. dis1 (hydro) and eq. dis2 (kinetic) from the
 // time integrals (flux) and values at dt (point values) of C1..C8
@@ -293,72 +314,86 @@ struct Rec {
   __device__ __forceinline__ TC& T(int k, size_t f) const { return t[(size_t)k * nf + f]; }
 };
 
+// coefficient-set arrays of one Maxwellian (peculiar frame)
+template <typename TC>
+struct Coefs {
+  TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
+};
+
+// State of side s (0: left cell, 1: right cell) at the interface centre from
+// its cell average Wc and reconstruction pc = (p_n, p_s, p_nn, p_ss, p_ns) in
+// the interface frame; false if nonphysical.
+struct Side {
+  double rho, U, V, pr, lam;
+};
+__device__ __forceinline__ bool side_state_2d(const Phys& P, int s, double hn, double hs, const double (&Wc)[4],
+                                              const double (&pc)[4][5], Side& o) {
+  const double xn = s == 0 ? 0.5 * hn : -0.5 * hn;
+  double W[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* p = pc[v];
+    W[v] = Wc[v] + p[0] * xn + p[2] * (hn * hn * (1.0 / 12.0)) - p[3] * (hs * hs * (1.0 / 24.0));
+  }
+  o.rho = W[0];
+  o.U = W[1] / o.rho;
+  o.V = W[2] / o.rho;
+  o.pr = (P.gamma - 1.0) * (W[3] - 0.5 * o.rho * (o.U * o.U + o.V * o.V));
+  o.lam = 0.5 * o.rho / o.pr;
+  return o.rho > 0.0 && o.pr > 0.0;
+}
+
+// targets of side s's coefficient systems (dU/dn, dU/ds, d2U/dn2, d2U/dnds,
+// d2U/ds2 of the cell polynomial at the interface, divided by rho, in the
+// frame of the side's Maxwellian)
+template <typename TC>
+__device__ __forceinline__ void side_targets_2d(int s, double hn, const Side& S, const double (&pc)[4][5],
+                                                TC (&b)[5][4]) {
+  const double ir = 1.0 / S.rho, xn = s == 0 ? 0.5 * hn : -0.5 * hn;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double d[4], f[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double* p = pc[v];
+      d[v] = (k == 0 ? p[0] + p[2] * xn : k == 1 ? p[1] + p[4] * xn : k == 2 ? p[2] : k == 3 ? p[4] : p[3]) * ir;
+    }
+    to_frame_2d(d, S.U, S.V, f);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[k][v] = (TC)f[v];
+  }
+}
+
 // Prologue of interface f.  Wc[s][v], pc[s][v][0..4] = (p_n, p_s, p_nn, p_ss,
 // p_ns): averages and reconstruction coefficients of the left (s = 0) and
 // right (s = 1) cells in the interface frame; Ueq[m][n][v]: the six averages
-// around the interface.  Writes the frame record and returns the leading
-// flux (C1 g0 and C7 g_k terms) and the leading point value U0.
+// around the interface.  Writes the record of g0 (state, tau, expansion
+// coefficients) and returns the leading flux (C1 g0 and C7 g_k terms) and the
+// leading point value U0.
 template <typename TC>
 __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, double hn, double hs,
                                                   const double (&Wc)[2][4], const double (&pc)[2][4][5],
                                                   const double (&Ueq)[2][3][4], const Rec<TC>& R, size_t f,
                                                   double (&flux)[4], double (&pv)[4]) {
   const double g1 = P.gamma - 1.0;
-  double W[2][4];
-  double rho[2], U[2], V[2], pr[2], lam[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const double xn = s == 0 ? 0.5 * hn : -0.5 * hn;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double* p = pc[s][v];
-      W[s][v] = Wc[s][v] + p[0] * xn + p[2] * (hn * hn * (1.0 / 12.0)) - p[3] * (hs * hs * (1.0 / 24.0));
-    }
-    rho[s] = W[s][0];
-    U[s] = W[s][1] / rho[s];
-    V[s] = W[s][2] / rho[s];
-    pr[s] = g1 * (W[s][3] - 0.5 * rho[s] * (U[s] * U[s] + V[s] * V[s]));
-    lam[s] = 0.5 * rho[s] / pr[s];
-  }
-  if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !(pr[0] > 0.0) || !(pr[1] > 0.0)) return false;
+  Side S[2];
+  const bool okl = side_state_2d(P, 0, hn, hs, Wc[0], pc[0], S[0]);
+  const bool okr = side_state_2d(P, 1, hn, hs, Wc[1], pc[1], S[1]);
+  if (!okl || !okr) return false;
   double W0[4] = {0, 0, 0, 0}, Fk[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const Half m = half_moments(U[s], lam[s], s == 0 ? 1.0 : -1.0);
-    const double th = 0.5 / lam[s];
-    const double e2 = V[s] * V[s] + (1.0 + P.K) * th;  // <v^2> + <xi^2>
-    W0[0] += rho[s] * m.M0;
-    W0[1] += rho[s] * m.M1;
-    W0[2] += rho[s] * V[s] * m.M0;
-    W0[3] += rho[s] * 0.5 * (m.M2 + e2 * m.M0);
-    Fk[0] += rho[s] * m.M1;
-    Fk[1] += rho[s] * m.M2;
-    Fk[2] += rho[s] * V[s] * m.M1;
-    Fk[3] += rho[s] * 0.5 * (m.M3 + e2 * m.M1);
-    const int o = s == 0 ? D_RHOL : D_RHOR;
-    R.D(o + 0, f) = rho[s];
-    R.D(o + 1, f) = U[s];
-    R.D(o + 2, f) = V[s];
-    R.D(o + 3, f) = lam[s];
-    R.D(o + 4, f) = m.M0;
-    R.D(o + 5, f) = m.h1;
-    // targets of the side's coefficient systems, divided by rho, in its frame
-    const double ir = 1.0 / rho[s];
-    const int tb = s == 0 ? T_BL : T_BR;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double d[4], b[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double* p = pc[s][v];
-        const double xn = s == 0 ? 0.5 * hn : -0.5 * hn;
-        // dU/dn, dU/ds, d2U/dn2, d2U/dnds, d2U/ds2 of the cell polynomial at the interface
-        d[v] = (k == 0 ? p[0] + p[2] * xn : k == 1 ? p[1] + p[4] * xn : k == 2 ? p[2] : k == 3 ? p[4] : p[3]) * ir;
-      }
-      to_frame_2d(d, U[s], V[s], b);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) R.T(tb + 4 * k + v, f) = (TC)b[v];
-    }
+    const Half m = half_moments(S[s].U, S[s].lam, s == 0 ? 1.0 : -1.0);
+    const double th = 0.5 / S[s].lam, rho = S[s].rho, V = S[s].V;
+    const double e2 = V * V + (1.0 + P.K) * th;  // <v^2> + <xi^2>
+    W0[0] += rho * m.M0;
+    W0[1] += rho * m.M1;
+    W0[2] += rho * V * m.M0;
+    W0[3] += rho * 0.5 * (m.M2 + e2 * m.M0);
+    Fk[0] += rho * m.M1;
+    Fk[1] += rho * m.M2;
+    Fk[2] += rho * V * m.M1;
+    Fk[3] += rho * 0.5 * (m.M3 + e2 * m.M1);
   }
   const double rho0 = W0[0], U0 = W0[1] / rho0, V0 = W0[2] / rho0;
   const double p0 = g1 * (W0[3] - 0.5 * rho0 * (U0 * U0 + V0 * V0));
@@ -368,30 +403,51 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   R.D(D_U0, f) = U0;
   R.D(D_V0, f) = V0;
   R.D(D_LAM0, f) = lam0;
-  // equilibrium quadratic (Sec. 3.3) -> targets of the g0 systems
+  // equilibrium quadratic (Sec. 3.3) -> targets and coefficients of g0
   {
     const double ir = 1.0 / rho0;
-    double qd[5][4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
-      const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
-      qd[0][v] = ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)) / (4.0 * hn) * ir;                          // b2: U_x
-      qd[1][v] = (R2 - R0 + L2 - L0) / (4.0 * hs) * ir;                                                // b3: U_y
-      qd[2][v] = (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]) / (8.0 * hn * hn) * ir;     // b4: U_xx
-      qd[3][v] = (R2 - L2 - R0 + L0) / (2.0 * hn * hs) * ir;                                           // b6: U_xy
-      qd[4][v] = (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0) / (2.0 * hs * hs) * ir;                     // b5: U_yy
-    }
+    TC b[5][4];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      double b[4];
-      to_frame_2d(qd[k], U0, V0, b);
+      double qd[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) R.T(T_B0 + 4 * k + v, f) = (TC)b[v];
+      for (int v = 0; v < 4; ++v) {
+        const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
+        const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
+        qd[v] = (k == 0   ? ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)) / (4.0 * hn)                      // U_x
+                 : k == 1 ? (R2 - R0 + L2 - L0) / (4.0 * hs)                                            // U_y
+                 : k == 2 ? (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]) / (8.0 * hn * hn)  // U_xx
+                 : k == 3 ? (R2 - L2 - R0 + L0) / (2.0 * hn * hs)                                       // U_xy
+                          : (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0) / (2.0 * hs * hs)) *              // U_yy
+                ir;
+      }
+      double bf[4];
+      to_frame_2d(qd, U0, V0, bf);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[k][v] = (TC)bf[v];
+    }
+    if constexpr (g0_solved_in_prologue<TC>()) {
+      TC th[5], kp[4];
+      theta_powers(0.5 / lam0, th);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
+      Coefs<TC> c;
+      coef_g0_2d<TC>(th, kp, (TC)P.nth, (TC)U0, (TC)V0, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx,
+                     c.dxy, c.dyy, c.bxt, c.byt, c.Bt);
+      const TC* sets[9] = {c.ax, c.ay, c.At, c.dxx, c.dxy, c.dyy, c.bxt, c.byt, c.Bt};
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R.T(T_CG + 4 * k + v, f) = sets[k][v];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R.T(T_CG + 4 * k + v, f) = b[k][v];
     }
   }
-  // collision time (Sec. 4) and the time weights
-  const double jump = fabs((pr[0] - pr[1]) / (pr[0] + pr[1]));
+  // collision time (Sec. 4)
+  const double jump = fabs((S[0].pr - S[1].pr) / (S[0].pr + S[1].pr));
   const double tau = P.viscous ? P.mu / p0 + P.tau_c * jump * dt : (P.tau_eps + P.tau_c * jump) * dt;
   R.D(D_TAU, f) = tau;
   // leading terms: Euler flux of U0 (C1 g0) and free transport of the sides
@@ -408,12 +464,6 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   return true;
 }
 
-// coefficient-set arrays of one Maxwellian (peculiar frame)
-template <typename TC>
-struct Coefs {
-  TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
-};
-
 // Hydrodynamic phase of interface f: corrections to flux, point values and
 // the integrated density (lab frame, interface frame components).
 template <typename TC>
@@ -427,12 +477,18 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double 
   for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
   const TC u0 = (TC)U0, v0 = (TC)V0;
   Coefs<TC> c;
-  {
+  if constexpr (g0_solved_in_prologue<TC>()) {
+    TC* sets[9] = {c.ax, c.ay, c.At, c.dxx, c.dxy, c.dyy, c.bxt, c.byt, c.Bt};
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sets[k][v] = R.T(T_CG + 4 * k + v, f);
+  } else {
     TC b[5][4];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b[k][v] = R.T(T_B0 + 4 * k + v, f);
+      for (int v = 0; v < 4; ++v) b[k][v] = R.T(T_CG + 4 * k + v, f);
     coef_g0_2d<TC>(th, kp, (TC)P.nth, u0, v0, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy, c.dyy,
                    c.bxt, c.byt, c.Bt);
   }
@@ -445,7 +501,7 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double 
 #pragma unroll
     for (int k = 0; k < 13; ++k) w[k] = (TC)hw[k];
   }
-  Acc<TC> A;
+  Acc<TC> A(kGaussOffset * hs);
   TC m0[4], m1[4];
   // C2 g0 (a1 u + a2 v)
   mom_full_conv_2d<TC>(th, kp, u0, v0, c.ax, c.ay, m0, m1);
@@ -481,19 +537,20 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double 
   A.pv1(m0, w[HW_C3]);
 #pragma unroll
   for (int v = 0; v < 4; ++v) flux[v] = pvm[v] = pvp[v] = E[v] = 0.0;
-  A.template add_to<4>(U0, V0, rho0, hs, kGaussOffset * hs, flux, pvm, pvp, P.viscous ? E : nullptr);
+  A.add_to(U0, V0, rho0, hs, flux, pvm, pvp, P.viscous ? E : nullptr);
 }
 
-// Kinetic phase of interface f, side s (0: g_l on u > 0, 1: g_r on u < 0).
+// Kinetic phase of interface f, side s (0: g_l on u > 0, 1: g_r on u < 0);
+// Wc, pc: average and reconstruction of the side's cell in the interface frame.
 template <typename TC>
-__device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, double hs, int s, const Rec<TC>& R,
+__device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, double hn, double hs, int s,
+                                                 const double (&Wc)[4], const double (&pc)[4][5], const Rec<TC>& R,
                                                  size_t f, double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                  double (&E)[4]) {
-  const int o = s == 0 ? D_RHOL : D_RHOR;
-  const double rho = R.D(o, f), U = R.D(o + 1, f), V = R.D(o + 2, f), lam = R.D(o + 3, f);
-  Half hm;
-  hm.M0 = R.D(o + 4, f);
-  hm.h1 = R.D(o + 5, f);
+  Side S;
+  side_state_2d(P, s, hn, hs, Wc, pc, S);  // physical: the prologue checked it
+  const double rho = S.rho, U = S.U, V = S.V, lam = S.lam;
+  const Half hm = half_moments(U, lam, s == 0 ? 1.0 : -1.0);
   TC th[5], kp[4], h[10];
   theta_powers(0.5 / lam, th);
   half_table(hm, U, lam, h);
@@ -502,12 +559,8 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
   const TC us = (TC)U, vs = (TC)V;
   Coefs<TC> c;
   {
-    const int tb = s == 0 ? T_BL : T_BR;
     TC b[5][4];
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[k][v] = R.T(tb + 4 * k + v, f);
+    side_targets_2d(s, hn, S, pc, b);
     if (P.viscous)
       coef_side_ns_2d<TC>(th, kp, (TC)P.nth, us, vs, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy,
                           c.dyy, c.bxt, c.byt, c.Bt);
@@ -525,7 +578,7 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
 #pragma unroll
     for (int k = 0; k < 12; ++k) w[k] = (TC)kw[k];
   }
-  Acc<TC> A;
+  Acc<TC> A(kGaussOffset * hs);
   TC m0[4], m1[4];
   // C8 g (a1 u + a2 v)  [and -tau C7 g (a1 u + a2 v)]
   mom_half_conv_2d<TC>(th, kp, h, us, vs, c.ax, c.ay, m0, m1);
@@ -558,7 +611,7 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) flux[v] = pvm[v] = pvp[v] = E[v] = 0.0;
-  A.template add_to<4>(U, V, rho, hs, kGaussOffset * hs, flux, pvm, pvp, P.viscous ? E : nullptr);
+  A.add_to(U, V, rho, hs, flux, pvm, pvp, P.viscous ? E : nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -136,6 +136,11 @@ def _face_values_2d(fun, prob: Problem):
         fx[g] = fun(X, Y)
         X, Y = np.broadcast_arrays((xc + s * h)[None, :], yf[:, None])
         fy[g] = fun(X, Y)
+    # on a periodic axis the last interface is the first one: one value
+    if prob.bc[0].kind == "periodic":
+        fx[..., prob.nx] = fx[..., 0]
+    if prob.bc[2].kind == "periodic":
+        fy[..., prob.ny, :] = fy[..., 0, :]
     return fx, fy
 
 
