@@ -154,8 +154,9 @@ const char* gks_last_error(const gks_handle* h);
  * accumulated time (ms) and launch count of kernel k (GKS_K_*) since the last
  * reset are returned by gks_kernel_time (which synchronises the stream).
  * gks_profile(h, 0) stops recording; gks_profile(h, 2) resets the sums. */
-enum { GKS_K_GHOST = 0, GKS_K_DT = 1, GKS_K_RECON = 2, GKS_K_INTERFACE = 3, GKS_K_UPDATE = 4,
-       GKS_K_COUNT = 5 };
+enum { GKS_K_GHOST = 0,  /* boundary images, with the time step */
+       GKS_K_DT = 1,     /* (kept for the ABI: the step is taken in the boundary kernel; no launches) */
+       GKS_K_RECON = 2, GKS_K_INTERFACE = 3, GKS_K_UPDATE = 4, GKS_K_COUNT = 5 };
 int gks_profile(gks_handle* h, int32_t mode);
 int gks_kernel_time(gks_handle* h, int32_t kernel, double* ms, int64_t* launches);
 

@@ -7,7 +7,8 @@
 // (a block-owner table maps each block to its problem and tile):
 //   2D: k_ghost_2d               boundary images (cells: two layers incl.
 //                                corners; interface values of edge ghosts)
-//       k_dt                     CFL time step or the fixed step, per problem
+//                                and, in one thread per problem, the CFL
+//                                time step or the fixed step
 //       k_recon_2d               compact reconstruction (Sec. 3.2)
 //       k_iface_pro_2d           interface prologue: U0, equilibrium quadratic,
 //                                tau, time integrals, leading terms (double)
@@ -15,7 +16,7 @@
 //       k_iface_kin_2d (x2)      eq. dis2 corrections (g_l on u > 0, g_r on u < 0)
 //       k_update_2d              conservative update (eq. finite), nonphysical
 //                                flag, CFL bound of the new state
-//   1D: k_ghost_1d, k_dt, k_recon_1d, k_face_1d (fused interface), k_update_1d
+//   1D: k_ghost_1d (+ time step), k_recon_1d, k_face_1d (fused interface), k_update_1d
 // The step of all groups is captured once in a hipGraph and replayed.
 //
 // Memory per 2D problem (structure of arrays, x fastest):
@@ -140,10 +141,12 @@ __device__ __forceinline__ unsigned logical_block(unsigned nblk) {
 }
 
 template <class PR>
-__device__ __forceinline__ const PR& locate(const KA<PR>& a, int kind, int& local) {
+__device__ __forceinline__ const PR& locate(const KA<PR>& a, int kind, int& local, int* problem = nullptr) {
   const unsigned L = logical_block(a.nblk);
-  const PR& Q = a.probs[a.owner[L]];
+  const int p = a.owner[L];
+  const PR& Q = a.probs[p];
   local = (int)((L - Q.first[kind]) * blockDim.x + threadIdx.x);
+  if (problem) *problem = p;
   return Q;
 }
 
@@ -352,11 +355,31 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
   }
 }
 
-// all 2D boundary images of a problem in one launch
+// the step of problem p, by one thread of the boundary kernel (which reads
+// neither the step nor the CFL slots): ctl[2p] = fixed step (0: CFL),
+// ctl[2p+1] = end time (0: none; the step is shortened to reach it, later
+// steps are empty); the slots are reset for the update of this step
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+__device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ctl, int p) {
+  const Grid<TS, TP> g = Q.g;
+  const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1];
+  unsigned long long m = g.dtmin[0];
+  for (int q = 1; q < kDtSlots; ++q) {
+    const unsigned long long b = g.dtmin[q];
+    m = b < m ? b : m;
+  }
+  double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
+  if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
+  *g.dt = dt;
+  for (int q = 0; q < kDtSlots; ++q) g.dtmin[q] = (unsigned long long)__double_as_longlong(1e300);
+}
+
+// all 2D boundary images of a problem in one launch, and its time step
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a, const double* __restrict__ ctl) {
+  int id, p;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id, &p);
+  if (id == 0) step_dt(Q, ctl, p);
   const int nx = Q.g.ix.nx, ny = Q.g.ix.ny;
   const int nwe = 4 * ny + 4 * ny + 4 * (ny + 1), nsn = 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
   if (id < nwe)
@@ -368,9 +391,10 @@ __global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a) {
 // 1D: tasks (side, m), m = 0, 1 ghost cells -1-m / nx+m, m = 2 the ghost
 // interface -1 / nx+1
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id);
+__global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a, const double* __restrict__ ctl) {
+  int id, p;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id, &p);
+  if (id == 0) step_dt(Q, ctl, p);
   if (id >= 6) return;
   const Grid<TS, TP> g = Q.g;
   const double gamma = Q.P.gamma;
@@ -408,7 +432,7 @@ __global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a) {
 // time step: dt = cfl * min over cells of min(h/(|u|+c+2nu/h), k/(|v|+c+2nu/k))
 // The per-cell bound is reduced into the slots g.dtmin (bits of positive
 // doubles, ordered like unsigned integers) by the update kernel for the next
-// step (and by its scan form for the initial state); k_dt takes the minimum
+// step (and by its scan form for the initial state); step_dt takes the minimum
 // of the slots, turns it into the step and resets them.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, double h, double k) {
@@ -434,26 +458,6 @@ __device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* sl
   if (!(b > 0.0) || !isfinite(b)) b = 1e300;
   for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave % kDtSlots), (unsigned long long)__double_as_longlong(b));
-}
-
-// one thread per problem: ctl[2p] = fixed step (0: CFL), ctl[2p+1] = end
-// time (0: none; the step is shortened to reach it, later steps are empty)
-template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_dt(const Prob<TS, TP, TC>* __restrict__ probs, const double* __restrict__ ctl,
-                                            int n) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const Grid<TS, TP> g = probs[p].g;
-  const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1];
-  unsigned long long m = g.dtmin[0];
-  for (int q = 1; q < kDtSlots; ++q) {
-    const unsigned long long b = g.dtmin[q];
-    m = b < m ? b : m;
-  }
-  double dt = fixed > 0.0 ? fixed : probs[p].P.cfl * __longlong_as_double((long long)m);
-  if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
-  *g.dt = dt;
-  for (int q = 0; q < kDtSlots; ++q) g.dtmin[q] = (unsigned long long)__double_as_longlong(1e300);
 }
 
 // ---------------------------------------------------------------------------
@@ -1143,17 +1147,13 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   KA<PR> A[KK_COUNT];
   for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k]};
   double* ctl = G.ctl;
-  const int n = (int)G.members.size();
   record_begin(h, st);
   if (G.dim == 2) {
-    k_ghost_2d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
+    k_ghost_2d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
   } else {
-    k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA]);
+    k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
   }
-  record_end(h, st, GKS_K_GHOST);
-  record_begin(h, st);
-  k_dt<TS, TP, TC><<<cdiv(n, 64), 64, 0, st>>>(probs, ctl, n);
-  record_end(h, st, GKS_K_DT);
+  record_end(h, st, GKS_K_GHOST);  // includes the time step
   record_begin(h, st);
   if (G.dim == 2)
     k_recon_2d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
