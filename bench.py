@@ -11,13 +11,21 @@ conservative update.  The state stays resident in HBM; W untimed warm-up
 steps, then K timed steps bracketed by device synchronisation.
 
 Printed: one JSON line.  value = Mcell-updates/s of the GKS_FP32_MIXED form
-(the headline form); the GKS_FP64 form is reported beside it.  The dominant
-kernel (the interface kernel) is timed live with HIP events on the stream it
-runs on; `roofline` prices its algorithmic floating-point operations (the
+(the headline form), replayed as one hipGraph per step after the launch
+shapes are tuned (gks_tune); the GKS_FP64 form and the batched form (96
+grids of mixed sizes and flows, one launch per phase for all of them) are
+reported beside it.  The interface phases (the dominant kernels) are timed
+live with HIP events on the stream they run on, in an eager run of the same
+steps; `roofline` prices their algorithmic floating-point operations (the
 straight-line operation count of the generated interface arithmetic plus the
-double-precision prologue) against the vector ALU peak.  `cpu_baseline` times
-the FP64 oracle on this host for a bounded number of steps of the same
-workload; the same steps on the GPU give the L1 difference to the oracle.
+double-precision prologue) against the vector ALU peak, and `traffic` gives
+their HBM bytes from the committed counter record while the kernel sources
+still match it.  `cpu_baseline` times the FP64 oracle on this host for a
+bounded number of steps of the same workload; the same steps on the GPU give
+the L1 difference to the oracle.
+
+`--pmc-probe` runs the counter-collection workload (a 256 MiB calibration
+copy, then a few eager steps of the tuned FP32-mixed vortex).
 """
 import argparse
 import json
@@ -45,17 +53,6 @@ KIN_TERMS_NS = KIN_TERMS_EULER + ("A", "tlin", "ty")
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_iface_vortex256_fp32mixed.json")
-KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
-
-
-def source_hash():
-    """Hash of the kernel sources: a stored counter record is valid only for them."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1412_4489_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def traffic_record():
@@ -67,6 +64,7 @@ def traffic_record():
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
+    from paper_1412_4489_amd.profiling import source_hash
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch_set")
@@ -204,7 +202,9 @@ def main():
     value = cells * a.steps / wall / 1e6
     wall64, kt64, _, _ = res["fp64"]
     value64 = cells * a.steps / wall64 / 1e6
-    n_if = (prob.nx + 1) * prob.ny + prob.nx * (prob.ny + 1)
+    # distinct interfaces (on a periodic axis the last interface is the first)
+    n_if = ((prob.nx if prob.bc[0].kind == "periodic" else prob.nx + 1) * prob.ny
+            + prob.nx * (prob.ny if prob.bc[2].kind == "periodic" else prob.ny + 1))
     fl = interface_flops(False) * n_if
     ms_if, nl = kt["interface"]
     t_if = ms_if / 1e3 / max(nl, 1)

@@ -173,3 +173,24 @@ def test_nonphysical_state_is_reported(G):
         with pytest.raises(G.GKSError) as e2:
             S.step(1, dt=0.01)
         assert e2.value.code == G.GKS_ESTATE
+
+
+def test_periodic_seam_is_one_interface(G, oracle):
+    """On a periodic axis the last interface is the first one: gks_init takes
+    the seam's point values from the first interface, the seam is computed
+    once, and the fetched state keeps the two equal; the result equals the
+    oracle's from the same (consistent) data."""
+    prob, st = W.smooth_periodic_2d(nx=14, ny=11, seed=4)
+    bad = st.copy()
+    bad.fx[..., prob.nx] += 0.01   # inconsistent seam values are overridden
+    bad.fy[..., prob.ny, :] -= 0.01
+    dt = 0.8 * oracle.dt(prob, st)
+    ref = st.copy()
+    oracle.step(prob, ref, dt, 0.0)
+    with G.Solver(prob, bad) as S:
+        S.step(1, dt=dt)
+        got, _, _ = S.fetch()
+    assert np.array_equal(got.fx[..., prob.nx], got.fx[..., 0])
+    assert np.array_equal(got.fy[..., prob.ny, :], got.fy[..., 0, :])
+    _compare(got.cell, ref.cell, 1e-11, "cell")
+    _compare(got.fx, ref.fx, 1e-10, "x point values")
