@@ -83,7 +83,8 @@ def pmc_probe():
         y.copy_(x)
     torch.cuda.synchronize()
     prob, st = W.vortex_2d(N)
-    with gks.Solver(prob, st, gks.GKS_FP32_MIXED, stream=torch.cuda.current_stream().cuda_stream) as S:
+    side = torch.cuda.Stream()  # a torch stream the library borrows (handle 0 would mean its own)
+    with gks.Solver(prob, st, gks.GKS_FP32_MIXED, stream=side.cuda_stream) as S:
         S.tune(3)
         gks.gks_profile(S.h, 1)
         S.step(5)
@@ -114,8 +115,8 @@ def run_gpu(precision, steps, warmup, items=None):
     if items is None:
         items = [W.vortex_2d(N)]
     probs, states = [p for p, _ in items], [s for _, s in items]
-    stream = torch.cuda.current_stream().cuda_stream
-    S = gks.Solver(probs, states, precision, stream=stream)
+    side = torch.cuda.Stream()  # a torch stream the library borrows (handle 0 would mean its own)
+    S = gks.Solver(probs, states, precision, stream=side.cuda_stream)
     sizes = S.tune(3)
     S.step(warmup)
     torch.cuda.synchronize()

@@ -124,6 +124,44 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs,
              const double* const* cell, const double* const* face_x,
              const double* const* face_y, void* stream);
 
+/* Device-borrow form of gks_init, for callers that keep the state in device
+ * memory of their own (e.g. PyTorch tensors): the library steps these buffers
+ * in place and allocates only its scratch arrays (reconstruction coefficients,
+ * fluxes, the interface frame record, scalars).  The scheme's state, as in
+ * gks_init, is the cell averages plus the interface point values (Sec. 3.2:
+ * the point values at t^{n+1} come from the interface distribution and feed
+ * the next reconstruction).  The layouts carry the library's ghost regions;
+ * x runs fastest:
+ *   d_cell[p]   : double, 2D [4][ny+4][nx+4], cell (i, j) at [v][j+2][i+2];
+ *                 1D [3][nx+4], cell i at [v][i+2]
+ *   d_face_x[p] : TS, 2D [2][4][ny+2][nx+3], interface i-1/2 (i = 0..nx) of
+ *                 row j at [g][v][j+1][i+1]; 1D [3][nx+3], interface i at [v][i+1]
+ *   d_face_y[p] : TS, 2D [2][4][ny+3][nx+2], interface j-1/2 (j = 0..ny) of
+ *                 column i at [g][v][j+1][i+1]; NULL when dim == 1
+ * TS = double for GKS_FP64, float for GKS_FP32_MIXED; g and v as in gks_init.
+ * Ghost entries are ignored on entry and overwritten by every step; on a
+ * periodic axis the seam interface is overwritten with the first interface's
+ * values, as in gks_init.  The buffers must hold the initial state when the
+ * call is made (work that wrote them on another stream must be complete),
+ * must not overlap, must be aligned to their element size and must outlive
+ * the handle; the caller owns them.  Between gks_step and a read of them by
+ * the caller, synchronise `stream`, or call gks_fetch (which waits for the
+ * library's stream; all its arrays may be NULL).  With stream == NULL the
+ * library launches on a non-blocking stream of its own, which the legacy
+ * default stream does not wait for.  Errors as gks_init;
+ * a nonphysical initial cell is found on the device and reported as
+ * GKS_EINVAL. */
+int gks_init_device(gks_handle** out, int32_t n_problems, const gks_problem* probs,
+                    void* const* d_cell, void* const* d_face_x, void* const* d_face_y,
+                    void* stream);
+
+/* Element counts of the three device buffers of gks_init_device for one
+ * problem, and the size in bytes of a face element (8 or 4).  Host-only: no
+ * device call.  Any output pointer may be NULL.  GKS_EINVAL for an
+ * inconsistent problem (gks_last_error(NULL) says why). */
+int gks_state_extent(const gks_problem* prob, int64_t* cell_elems, int64_t* face_x_elems,
+                     int64_t* face_y_elems, int32_t* face_elem_bytes);
+
 /* Enqueue nsteps time steps of every problem (asynchronous; returns after the
  * launches: nsteps replays of the step graph, captured at the first call).  dt_fixed: NULL to take each step from the CFL condition on the
  * device, else dt_fixed[p] for every step of problem p.  t_end: NULL for no
@@ -170,7 +208,7 @@ int gks_kernel_time(gks_handle* h, int32_t kernel, double* ms, int64_t* launches
  * GKS_EINVAL, GKS_ESTATE, GKS_ENOMEM or GKS_EDEVICE (the latter two leave the
  * handle in its error state).
  * gks_block_size reports the present block size of kernel class `kernel`
- * (GKS_K_*; the CFL kernel always uses 64). */
+ * (GKS_K_*; GKS_K_DT, which has no launches of its own, reports 64). */
 int gks_tune(gks_handle* h, int32_t steps);
 int gks_block_size(gks_handle* h, int32_t kernel, int32_t* threads);
 

@@ -849,14 +849,17 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
       if (j == 0 && x.fyr == ny)
 #pragma unroll
         for (int q = 0; q < 8; ++q) g.FY[x.fy(q >> 2, q & 3, ny, i)] = g.FY[x.fy(q >> 2, q & 3, 0, i)];
-      const double p = (Q.P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
-        atomicCAS(g.err, 0ull,
-                  1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
       if (id == 0) {
         *g.t += dt;
         *g.steps += 1;
       }
+    }
+    // (the scan checks the state it is given: a caller's initial state)
+    if (kScan || dt > 0.0) {
+      const double p = (Q.P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
+        atomicCAS(g.err, 0ull,
+                  1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
     }
     bound = cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
   }
@@ -884,13 +887,15 @@ __global__ void __launch_bounds__(256) k_update_1d(KA<Prob<TS, TP, TC>> a) {
         W[v] += (g.FLX[x.fl1(v, i)] - g.FLX[x.fl1(v, i + 1)]) * ih;
         g.W[x.w1(v, i)] = W[v];
       }
-      const double p = (Q.P.gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
-      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
-        atomicCAS(g.err, 0ull, 1ull + (1ull << 32) + (unsigned long long)(i + 1) + (1ull << 63));
       if (id == 0) {
         *g.t += dt;
         *g.steps += 1;
       }
+    }
+    if (kScan || dt > 0.0) {
+      const double p = (Q.P.gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
+      if (!(W[0] > 0.0) || !(p > 0.0) || !isfinite(p))
+        atomicCAS(g.err, 0ull, 1ull + (1ull << 32) + (unsigned long long)(i + 1) + (1ull << 63));
     }
     bound = cell_dt_bound_1d(W, Q.P, g.geo.h);
   }
@@ -917,6 +922,7 @@ struct Problem {
   void* scal = nullptr;  // t, dt, steps, err, CFL slots (kScalBytes)
   void* recd = nullptr;  // interface frame record, double fields (2D)
   void* rect = nullptr;  // interface frame record, compute-type fields (2D)
+  bool borrowed = false;  // W, FX, FY belong to the caller (gks_init_device)
 };
 
 // problems of one dimension and precision, advanced by one launch sequence
@@ -1015,6 +1021,43 @@ std::string validate(const gks_problem& p) {
 }
 
 size_t n_interfaces(const Idx& x) { return (size_t)x.fxr * x.ny + (size_t)x.nx * x.fyr; }
+
+// a caller's buffer must be device memory of the current device with at
+// least `bytes` left in its allocation from p (else "" is not returned)
+std::string check_device_buffer(const char* name, const void* p, size_t bytes) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return std::string(name) + " is not device memory";
+  }
+  if (a.type != hipMemoryTypeDevice) return std::string(name) + " is not device memory";
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || a.device != dev)
+    return std::string(name) + " is not memory of the current device";
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (void*)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return std::string(name) + ": allocation range unknown";
+  }
+  if ((const char*)p < (const char*)base || (size_t)((const char*)p - (const char*)base) + bytes > size)
+    return std::string(name) + " is smaller than the state extent (gks_state_extent)";
+  return "";
+}
+
+// element counts of the ghosted state arrays W, FX, FY of a validated problem
+void state_elems(const gks_problem& s, size_t e[3]) {
+  const size_t nx = s.nx, ny = s.dim == 2 ? s.ny : 1;
+  if (s.dim == 2) {
+    e[0] = 4 * (ny + 4) * (nx + 4);
+    e[1] = 2 * 4 * (ny + 2) * (nx + 3);
+    e[2] = 2 * 4 * (ny + 3) * (nx + 2);
+  } else {
+    e[0] = 3 * (nx + 4);
+    e[1] = 3 * (nx + 3);
+    e[2] = 0;
+  }
+}
 
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -1242,16 +1285,16 @@ int set_controls(gks_handle* h, const double* dt_fixed, const double* t_end) {
   return GKS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, const double* const* cell,
-             const double* const* face_x, const double* const* face_y, void* stream) {
+// gks_init (host arrays cell / face_x / face_y, copied in) and
+// gks_init_device (device buffers dcell / dfx / dfy, borrowed) share this body
+int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, const double* const* cell,
+                const double* const* face_x, const double* const* face_y, void* const* dcell, void* const* dfx,
+                void* const* dfy, void* stream) {
   if (!out) return GKS_EINVAL;
   *out = nullptr;
   g_init_msg.clear();
-  if (n_problems < 1 || n_problems > kMaxProblems || !probs || !cell || !face_x) {
+  const bool dev = dcell != nullptr;
+  if (n_problems < 1 || n_problems > kMaxProblems || !probs || !(dev ? (bool)dfx : (cell && face_x))) {
     g_init_msg = "n_problems must lie in [1, 65535] and probs, cell, face_x must be given";
     return GKS_EINVAL;
   }
@@ -1267,8 +1310,20 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
   for (int n = 0; n < n_problems; ++n) {
     const gks_problem& s = probs[n];
     std::string why = validate(s);
-    if (!why.empty() || !cell[n] || !face_x[n] || (s.dim == 2 && (!face_y || !face_y[n])))
-      return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": " + (why.empty() ? "null array" : why));
+    const bool given = dev ? dcell[n] && dfx[n] && (s.dim == 1 || (dfy && dfy[n]))
+                           : cell[n] && face_x[n] && (s.dim == 1 || (face_y && face_y[n]));
+    if (why.empty() && !given) why = "null array";
+    if (why.empty() && dev) {
+      const size_t fe = s.precision == GKS_FP32_MIXED ? 4 : 8;
+      size_t e[3];
+      state_elems(s, e);
+      if ((uintptr_t)dcell[n] % 8 || (uintptr_t)dfx[n] % fe || (s.dim == 2 && (uintptr_t)dfy[n] % fe))
+        why = "device buffers must be aligned to their element size";
+      if (why.empty()) why = check_device_buffer("d_cell", dcell[n], e[0] * 8);
+      if (why.empty()) why = check_device_buffer("d_face_x", dfx[n], e[1] * fe);
+      if (why.empty() && s.dim == 2) why = check_device_buffer("d_face_y", dfy[n], e[2] * fe);
+    }
+    if (!why.empty()) return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": " + why);
     Problem& p = h->probs[n];
     p.spec = s;
     p.mixed = s.precision == GKS_FP32_MIXED;
@@ -1304,8 +1359,9 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       b.wv = s.bc[side].wall_v;
       b.wT = s.bc[side].wall_T;
     }
-    // the initial state must be physical
-    const size_t nc = (size_t)s.nx * p.ix.ny;
+    // the initial state must be physical (device buffers: checked by the
+    // initial CFL scan below)
+    const size_t nc = dev ? 0 : (size_t)s.nx * p.ix.ny;
     for (size_t c = 0; c < nc; ++c) {
       const double r = cell[n][c], mu_ = cell[n][nc + c];
       const double mv = s.dim == 2 ? cell[n][2 * nc + c] : 0.0, E = cell[n][(s.dim + 1) * nc + c];
@@ -1344,8 +1400,14 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes, 0, 0};
       memcpy(sizes, sz, sizeof(sz));
     }
+    if (dev) {
+      p.borrowed = true;
+      p.W = dcell[n];
+      p.FX = dfx[n];
+      p.FY = s.dim == 2 ? dfy[n] : nullptr;
+    }
     for (int b = 0; b < 9; ++b) {
-      if (!sizes[b]) continue;
+      if (!sizes[b] || (dev && b < 3)) continue;
       if (hipMalloc(bufs[b], sizes[b]) != hipSuccess) {
         *bufs[b] = nullptr;
         return init_fail(GKS_ENOMEM, "device allocation failed");
@@ -1353,8 +1415,27 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
       if (hipMemsetAsync(*bufs[b], 0, sizes[b], h->stream) != hipSuccess)
         return init_fail(GKS_EDEVICE, "hipMemsetAsync failed");
     }
+    // a periodic seam is one interface: its values are those of the first
+    if (dev && s.dim == 2) {
+      bool ok = true;
+      if (x.fxr == s.nx)
+        ok = ok && hipMemcpy2DAsync((char*)p.FX + (nx + 1) * ts, (nx + 3) * ts, (const char*)p.FX + ts,
+                                    (nx + 3) * ts, ts, 2 * 4 * (ny + 2), hipMemcpyDeviceToDevice,
+                                    h->stream) == hipSuccess;
+      if (x.fyr == s.ny)
+        ok = ok && hipMemcpy2DAsync((char*)p.FY + (ny + 1) * (nx + 2) * ts, (ny + 3) * (nx + 2) * ts,
+                                    (const char*)p.FY + (nx + 2) * ts, (ny + 3) * (nx + 2) * ts, (nx + 2) * ts,
+                                    2 * 4, hipMemcpyDeviceToDevice, h->stream) == hipSuccess;
+      if (!ok) return init_fail(GKS_EDEVICE, "seam copy failed");
+    }
     // the clears above must land before the blocking uploads below
     if (hipStreamSynchronize(h->stream) != hipSuccess) return init_fail(GKS_EDEVICE, "hipStreamSynchronize failed");
+    const double scal0[4] = {s.t0, 0.0, 0.0, 0.0};
+    const std::vector<unsigned long long> inf(kDtSlots, 0x7e37e43c8800759cull);  // bits of 1e300
+    if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "upload failed");
+    if (dev) continue;
     // upload: host layouts without ghosts -> ghosted device layouts
     std::vector<double> W(sizes[0] / 8, 0.0), FX(sizes[1] / ts, 0.0), FY(sizes[2] / ts, 0.0);
     if (s.dim == 2) {
@@ -1381,9 +1462,7 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
         for (int fi = 0; fi <= s.nx; ++fi) FX[x.f1(v, fi)] = face_x[n][(size_t)v * (s.nx + 1) + fi];
       }
     }
-    const double scal0[4] = {s.t0, 0.0, 0.0, 0.0};
-    if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p.W, W.data(), W.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(p.W, W.data(), W.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
       return init_fail(GKS_EDEVICE, "upload failed");
     bool up = true;
     if (p.mixed) {
@@ -1395,9 +1474,6 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
            (FY.empty() || hipMemcpy(p.FY, FY.data(), FY.size() * 8, hipMemcpyHostToDevice) == hipSuccess);
     }
     if (!up) return init_fail(GKS_EDEVICE, "upload failed");
-    const std::vector<unsigned long long> inf(kDtSlots, 0x7e37e43c8800759cull);  // bits of 1e300
-    if (hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * 8, hipMemcpyHostToDevice) != hipSuccess)
-      return init_fail(GKS_EDEVICE, "upload failed");
   }
   // groups: problems of one dimension and precision, in problem order
   for (int n = 0; n < n_problems; ++n) {
@@ -1429,7 +1505,57 @@ int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, con
   }
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
     return init_fail(GKS_EDEVICE, "initial CFL scan failed");
+  // the scan flags a nonphysical initial cell in the error word
+  for (int n = 0; n < n_problems; ++n) {
+    unsigned long long err = 0;
+    if (hipMemcpy(&err, (char*)h->probs[n].scal + 24, 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return init_fail(GKS_EDEVICE, "download failed");
+    if (err)
+      return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": nonphysical initial cell (i, j) = (" +
+                                       std::to_string((long long)(err & 0xffffffff) - 2) + ", " +
+                                       std::to_string((long long)((err >> 32) & 0x3fffffff) - 1) + ")");
+  }
   *out = h;
+  return GKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gks_init(gks_handle** out, int32_t n_problems, const gks_problem* probs, const double* const* cell,
+             const double* const* face_x, const double* const* face_y, void* stream) {
+  return init_handle(out, n_problems, probs, cell, face_x, face_y, nullptr, nullptr, nullptr, stream);
+}
+
+int gks_init_device(gks_handle** out, int32_t n_problems, const gks_problem* probs, void* const* d_cell,
+                    void* const* d_face_x, void* const* d_face_y, void* stream) {
+  if (!d_cell) {
+    if (out) *out = nullptr;
+    g_init_msg = "d_cell must be given";
+    return GKS_EINVAL;
+  }
+  return init_handle(out, n_problems, probs, nullptr, nullptr, nullptr, d_cell, d_face_x, d_face_y, stream);
+}
+
+int gks_state_extent(const gks_problem* prob, int64_t* cell_elems, int64_t* face_x_elems, int64_t* face_y_elems,
+                     int32_t* face_elem_bytes) {
+  g_init_msg.clear();
+  if (!prob) {
+    g_init_msg = "prob must be given";
+    return GKS_EINVAL;
+  }
+  const std::string why = validate(*prob);
+  if (!why.empty()) {
+    g_init_msg = why;
+    return GKS_EINVAL;
+  }
+  size_t e[3];
+  state_elems(*prob, e);
+  if (cell_elems) *cell_elems = (int64_t)e[0];
+  if (face_x_elems) *face_x_elems = (int64_t)e[1];
+  if (face_y_elems) *face_y_elems = (int64_t)e[2];
+  if (face_elem_bytes) *face_elem_bytes = prob->precision == GKS_FP32_MIXED ? 4 : 8;
   return GKS_OK;
 }
 
@@ -1652,8 +1778,8 @@ int gks_destroy(gks_handle* h) {
   }
   for (Problem& p : h->probs) {
     void* bufs[9] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal, p.recd, p.rect};
-    for (void* b : bufs)
-      if (b) (void)hipFree(b);
+    for (int b = p.borrowed ? 3 : 0; b < 9; ++b)
+      if (bufs[b]) (void)hipFree(bufs[b]);
   }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <functional>
 #include <vector>
 
@@ -67,20 +68,65 @@ typedef int hipError_t;
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
 enum { hipSuccess = 0, hipStreamNonBlocking = 1, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
+// allocations of the emulated device (for the pointer queries below)
+inline std::map<const char*, size_t>& emu_allocations() {
+  static std::map<const char*, size_t> m;
+  return m;
+}
 inline hipError_t hipMalloc(void** p, size_t n) {
   *p = std::calloc(1, n ? n : 1);
+  if (*p) emu_allocations()[(const char*)*p] = n;
   return *p ? hipSuccess : 2;
+}
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2 };
+struct hipPointerAttribute_t {
+  hipMemoryType type;
+  int device;
+};
+inline bool emu_find(const void* p, const char** base, size_t* size) {
+  auto& m = emu_allocations();
+  auto it = m.upper_bound((const char*)p);
+  if (it == m.begin()) return false;
+  --it;
+  if ((const char*)p >= it->first + it->second) return false;
+  *base = it->first;
+  *size = it->second;
+  return true;
+}
+inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
+  const char* b;
+  size_t n;
+  if (!emu_find(p, &b, &n)) return 1;
+  a->type = hipMemoryTypeDevice;
+  a->device = 0;
+  return hipSuccess;
+}
+inline hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+inline hipError_t hipMemGetAddressRange(void** base, size_t* size, void* p) {
+  const char* b;
+  if (!emu_find(p, &b, size)) return 1;
+  *base = (void*)b;
+  return hipSuccess;
 }
 template <typename T>
 inline hipError_t hipMalloc(T** p, size_t n) {
   return hipMalloc((void**)p, n);
 }
 inline hipError_t hipFree(void* p) {
+  emu_allocations().erase((const char*)p);
   std::free(p);
   return hipSuccess;
 }
 inline hipError_t hipMemcpy(void* d, const void* s, size_t n, int) {
   std::memcpy(d, s, n);
+  return hipSuccess;
+}
+inline hipError_t hipMemcpy2DAsync(void* d, size_t dp, const void* s, size_t sp, size_t w, size_t h, int,
+                                   hipStream_t) {
+  for (size_t r = 0; r < h; ++r) std::memmove((char*)d + r * dp, (const char*)s + r * sp, w);
   return hipSuccess;
 }
 inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {

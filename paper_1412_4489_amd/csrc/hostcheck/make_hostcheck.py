@@ -81,6 +81,10 @@ def main(outdir=None):
     s, n = re.subn(r"if \(\(threadIdx\.x & 63\) == 0\) (atomicMin\()", r"\1", s)
     assert n == 1, "wave-minimum pattern not found"
     s = rewrite_launches(s)
+    # emulated device memory for callers of gks_init_device
+    s += ('\nextern "C" void* gks_emu_alloc(size_t n) {\n  void* p = nullptr;\n'
+          '  return hipMalloc(&p, n) == hipSuccess ? p : nullptr;\n}\n'
+          'extern "C" void gks_emu_free(void* p) { (void)hipFree(p); }\n')
     open(os.path.join(outdir, "gks_hostcheck.cpp"), "w").write(s)
     open(os.path.join(outdir, "emulation.h"), "w").write(open(os.path.join(HERE, "emulation.h")).read())
     lib = os.path.join(outdir, "libgks_hostcheck.so")

@@ -1,7 +1,8 @@
 """Thin ctypes binding of the C ABI in include/gks.h (libgks.so, gfx950).
 
-The functions keep the C names (gks_init, gks_step, gks_fetch, gks_destroy,
-gks_last_error, gks_profile, gks_kernel_time) and only marshal arguments;
+The functions keep the C names (gks_init, gks_init_device, gks_state_extent,
+gks_step, gks_fetch, gks_destroy, gks_last_error, gks_profile, gks_kernel_time,
+gks_tune, gks_block_size) and only marshal arguments;
 every step of the scheme runs in the HIP kernels of the library.  `Solver`
 wraps a handle for numpy arrays laid out as in paper_1412_4489_amd.workloads.
 
@@ -62,6 +63,10 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.gks_init.argtypes = [C.POINTER(_P), C.c_int32, C.POINTER(gks_problem), C.POINTER(_D), C.POINTER(_D),
                                C.POINTER(_D), _P]
+        L.gks_init_device.argtypes = [C.POINTER(_P), C.c_int32, C.POINTER(gks_problem), C.POINTER(_P),
+                                      C.POINTER(_P), C.POINTER(_P), _P]
+        _I64 = C.POINTER(C.c_int64)
+        L.gks_state_extent.argtypes = [C.POINTER(gks_problem), _I64, _I64, _I64, C.POINTER(C.c_int32)]
         L.gks_step.argtypes = [_P, C.c_int32, _D, _D]
         L.gks_fetch.argtypes = [_P, C.c_int32, _D, _D, _D, _D, C.POINTER(C.c_int64)]
         L.gks_destroy.argtypes = [_P]
@@ -75,7 +80,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("gks_init", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error", "gks_profile",
+EXPORTED = ("gks_init", "gks_init_device", "gks_state_extent", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error", "gks_profile",
             "gks_kernel_time", "gks_tune", "gks_block_size")
 
 
@@ -121,6 +126,88 @@ def gks_init(probs, states, precision=GKS_FP64, stream=None, t0=None):
     rc = lib().gks_init(C.byref(h), n, cp, cells, fxs, fys, stream)
     if rc != GKS_OK:
         raise GKSError(rc, "gks_init: " + lib().gks_last_error(None).decode())
+    return h
+
+
+def gks_state_extent(prob, precision=GKS_FP64):
+    """Element counts (cell, face_x, face_y) of the device buffers that
+    gks_init_device takes for one problem, and the byte size of a face
+    element (8 for GKS_FP64, 4 for GKS_FP32_MIXED).  Host-only."""
+    cp = to_c_problem(prob, precision)
+    n = [C.c_int64() for _ in range(3)]
+    fb = C.c_int32()
+    rc = lib().gks_state_extent(C.byref(cp), *[C.byref(x) for x in n], C.byref(fb))
+    if rc != GKS_OK:
+        raise GKSError(rc, "gks_state_extent: " + lib().gks_last_error(None).decode())
+    return n[0].value, n[1].value, n[2].value, fb.value
+
+
+def ghosted(prob, state, precision=GKS_FP64, fill=np.nan):
+    """Host arrays in the ghosted device layouts of gks_init_device (cell
+    averages double; point values double or float by precision), holding
+    `state` (workloads.State layout) and `fill` in every ghost entry."""
+    nv, nx, ny = prob.nvar, prob.nx, prob.ny
+    ft = np.float32 if precision == GKS_FP32_MIXED else np.float64
+    if prob.dim == 2:
+        cell = np.full((4, ny + 4, nx + 4), fill)
+        cell[:, 2:ny + 2, 2:nx + 2] = state.cell
+        fx = np.full((2, 4, ny + 2, nx + 3), fill, dtype=ft)
+        fx[:, :, 1:ny + 1, 1:nx + 2] = state.fx
+        fy = np.full((2, 4, ny + 3, nx + 2), fill, dtype=ft)
+        fy[:, :, 1:ny + 2, 1:nx + 1] = state.fy
+        return cell, fx, fy
+    cell = np.full((nv, nx + 4), fill)
+    cell[:, 2:nx + 2] = state.cell.reshape(nv, nx)
+    fx = np.full((nv, nx + 3), fill, dtype=ft)
+    fx[:, 1:nx + 2] = state.fx.reshape(nv, nx + 1)
+    return cell, fx, None
+
+
+def unghosted(prob, cell, fx, fy=None):
+    """workloads.State (float64 copies) of arrays in the ghosted layouts."""
+    from .workloads import State
+    nv, nx, ny = prob.nvar, prob.nx, prob.ny
+    if prob.dim == 2:
+        return State(np.array(cell[:, 2:ny + 2, 2:nx + 2], dtype=np.float64),
+                     np.array(fx[:, :, 1:ny + 1, 1:nx + 2], dtype=np.float64),
+                     np.array(fy[:, :, 1:ny + 2, 1:nx + 1], dtype=np.float64))
+    return State(np.array(cell[:, 2:nx + 2], dtype=np.float64).reshape(nv, 1, nx),
+                 np.array(fx[:, 1:nx + 2], dtype=np.float64).reshape(1, nv, 1, nx + 1),
+                 np.zeros((2, nv, 2, nx)))
+
+
+def _addr(x):
+    """Device address of an int or of an object with data_ptr() (a tensor)."""
+    if x is None:
+        return None
+    return int(x) if isinstance(x, int) else int(x.data_ptr())
+
+
+def gks_init_device(probs, d_cell, d_face_x, d_face_y, precision=GKS_FP64, stream=None, t0=None):
+    """Device-borrow form of gks_init: d_cell, d_face_x, d_face_y are lists
+    (one entry per problem) of device buffers in the ghosted layouts of
+    include/gks.h, as ints or tensors; d_face_y entries are None for 1D
+    problems.  The library steps them in place; they must outlive the
+    handle."""
+    n = len(probs)
+    t0 = [0.0] * n if t0 is None else list(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
+    prec = [int(x) for x in np.broadcast_to(np.asarray(precision, dtype=np.int64), (n,))]
+    cp = (gks_problem * n)(*[to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)])
+    for k, (p, q) in enumerate(zip(probs, prec)):
+        ext = gks_state_extent(p, q)
+        for x, elems, item, what in ((d_cell[k], ext[0], 8, "d_cell"), (d_face_x[k], ext[1], ext[3], "d_face_x"),
+                                     (d_face_y[k], ext[2], ext[3], "d_face_y")):
+            if x is None or isinstance(x, int) or not hasattr(x, "is_contiguous"):
+                continue  # raw addresses: the library checks them
+            if not (x.is_cuda and x.is_contiguous() and x.element_size() == item and x.is_floating_point()
+                    and x.numel() >= elems):
+                raise GKSError(GKS_EINVAL, f"gks_init_device: problem {k}: {what} must be a contiguous device "
+                                           f"tensor of {elems} floating-point elements of {item} bytes")
+    arrs = [(_P * n)(*[_addr(x) for x in lst]) for lst in (d_cell, d_face_x, d_face_y)]
+    h = _P()
+    rc = lib().gks_init_device(C.byref(h), n, cp, *arrs, stream)
+    if rc != GKS_OK:
+        raise GKSError(rc, "gks_init_device: " + lib().gks_last_error(None).decode())
     return h
 
 

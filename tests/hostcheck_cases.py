@@ -116,4 +116,84 @@ for tune in (False, True):
 same = all(np.array_equal(a, b) for a, b in zip(*outs))
 bad += not same
 print(f"tuned block sizes {sizes}: results {'identical' if same else 'DIFFER'}", flush=True)
+# device-borrow form: the caller's buffers (emulated device memory) with NaN in
+# every ghost entry, stepped in place; bitwise the host-copy form's results
+import ctypes as C  # noqa: E402
+L = gks.lib()
+L.gks_emu_alloc.restype = C.c_void_p
+L.gks_emu_alloc.argtypes = [C.c_size_t]
+L.gks_emu_free.argtypes = [C.c_void_p]
+
+
+def emu_buffers(arrs):
+    out = []
+    for a in arrs:
+        if a is None:
+            out.append(None)
+            continue
+        ptr = L.gks_emu_alloc(a.nbytes)
+        C.memmove(ptr, a.ctypes.data, a.nbytes)
+        out.append(ptr)
+    return out
+
+
+def emu_read(ptr, like):
+    a = np.empty_like(like)
+    C.memmove(a.ctypes.data, ptr, a.nbytes)
+    return a
+
+
+for name in ("vortex", "dmr", "cavity", "ns_smooth", "advection_1d", "sod_1d_char"):
+    for prec in (gks.GKS_FP64, gks.GKS_FP32_MIXED):
+        prob, st = CASES[name]()
+        if prob.bc[0].kind == "periodic":  # both forms take the seam from the first interface
+            st.fx[..., -1] += 0.25
+        if prob.dim == 2 and prob.bc[2].kind == "periodic":
+            st.fy[..., -1, :] += 0.25
+        host = gks.ghosted(prob, st, prec)
+        ptrs = emu_buffers(host)
+        h = gks.gks_init_device([prob], [ptrs[0]], [ptrs[1]], [ptrs[2]], prec)
+        gks.gks_step(h, 3, dt_fixed=[0.5 * O.dt(prob, st)])
+        got, t, n = gks.gks_fetch(h, 0, prob)
+        gks.gks_destroy(h)
+        direct = gks.unghosted(prob, *[None if q is None else emu_read(q, a) for q, a in zip(ptrs, host)])
+        with gks.Solver(prob, st, prec) as S:
+            S.step(3, dt=0.5 * O.dt(prob, st))
+            ref, tr, nr = S.fetch()
+        same = (n == nr == 3 and t == tr and np.array_equal(got.cell, ref.cell) and np.array_equal(got.fx, ref.fx)
+                and np.array_equal(got.fy, ref.fy) and np.array_equal(direct.cell, ref.cell)
+                and np.array_equal(direct.fx, ref.fx) and np.array_equal(direct.fy, ref.fy))
+        bad += not same
+        print(f"device-borrow {name} {prec}: {'identical' if same else 'DIFFER'}", flush=True)
+        for q in ptrs:
+            if q is not None:
+                L.gks_emu_free(q)
+# device-borrow rejections: a nonphysical initial cell (found by the scan), a
+# buffer too small for the extent, host memory
+prob, st = CASES["vortex"]()
+st.cell[0, 3, 5] = -1.0
+ptrs = emu_buffers(gks.ghosted(prob, st))
+try:
+    gks.gks_init_device([prob], [ptrs[0]], [ptrs[1]], [ptrs[2]])
+    bad += 1
+    print("nonphysical initial cell not rejected", flush=True)
+except gks.GKSError as e:
+    ok = e.code == gks.GKS_EINVAL and "(i, j) = (5, 3)" in str(e)
+    bad += not ok
+    print(f"nonphysical initial cell: {e} {'ok' if ok else 'FAIL'}", flush=True)
+prob, st = CASES["vortex"]()
+host = gks.ghosted(prob, st)
+small = L.gks_emu_alloc(host[1].nbytes - 8)
+for args, what in (((ptrs[0], small, ptrs[2]), "is smaller"), ((ptrs[0], host[1].ctypes.data, ptrs[2]), "not device")):
+    try:
+        gks.gks_init_device([prob], [args[0]], [args[1]], [args[2]])
+        bad += 1
+        print(f"bad buffer ({what}) not rejected", flush=True)
+    except gks.GKSError as e:
+        ok = e.code == gks.GKS_EINVAL and what in str(e)
+        bad += not ok
+        print(f"bad buffer: {e} {'ok' if ok else 'FAIL'}", flush=True)
+L.gks_emu_free(small)
+for q in ptrs:
+    L.gks_emu_free(q)
 sys.exit(1 if bad else 0)

@@ -57,3 +57,33 @@ def test_init_rejects_nonphysical_initial_state():
     with pytest.raises(gks.GKSError) as e:
         gks.gks_init([p], [s])
     assert e.value.code == gks.GKS_EINVAL and "nonphysical" in str(e.value)
+
+
+def test_state_extent_counts_the_ghosted_layouts():
+    # host-only: the element counts of the device buffers of gks_init_device
+    p, _ = W.vortex_2d(12)
+    p.ny = 7
+    assert gks.gks_state_extent(p, gks.GKS_FP64) == (4 * 11 * 16, 2 * 4 * 9 * 15, 2 * 4 * 10 * 14, 8)
+    assert gks.gks_state_extent(p, gks.GKS_FP32_MIXED)[3] == 4
+    q, _ = W.sod_1d(10)
+    assert gks.gks_state_extent(q) == (3 * 14, 3 * 13, 0, 8)
+    p.gamma = 0.5
+    with pytest.raises(gks.GKSError) as e:
+        gks.gks_state_extent(p)
+    assert e.value.code == gks.GKS_EINVAL and "gamma" in str(e.value)
+
+
+def test_ghosted_layouts_round_trip():
+    for prob, st in (W.vortex_2d(6), W.sod_1d(9)):
+        for prec in (gks.GKS_FP64, gks.GKS_FP32_MIXED):
+            arrs = gks.ghosted(prob, st, prec)
+            ext = gks.gks_state_extent(prob, prec)
+            assert [0 if a is None else a.size for a in arrs] == list(ext[:3])
+            assert arrs[1].itemsize == ext[3]
+            back = gks.unghosted(prob, *arrs)
+            tol = 0 if prec == gks.GKS_FP64 else 1e-6
+            assert np.allclose(back.cell, st.cell, rtol=0, atol=0)
+            assert np.allclose(back.fx, st.fx, rtol=tol, atol=0)
+            if prob.dim == 2:
+                assert np.allclose(back.fy, st.fy, rtol=tol, atol=0)
+            assert np.isnan(arrs[0]).sum() == arrs[0].size - st.cell.size
