@@ -253,7 +253,7 @@ def main():
         "batched": batched,
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": traffic_record(),
-                     "kernel": "k_iface_{pro,hydro,kin}_2d<float> (one launch set per step)",
+                     "kernel": "k_iface_{pro,corr,kin1}_2d<float> (one launch set per step)",
                      "flops_per_interface": interface_flops(False),
                      "interface_ms": round(t_if * 1e3, 5)},
     }

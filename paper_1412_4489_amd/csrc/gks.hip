@@ -12,8 +12,11 @@
 //       k_recon_2d               compact reconstruction (Sec. 3.2)
 //       k_iface_pro_2d           interface prologue: U0, equilibrium quadratic,
 //                                tau, time integrals, leading terms (double)
-//       k_iface_hydro_2d         eq. dis1 corrections (g0)
-//       k_iface_kin_2d (x2)      eq. dis2 corrections (g_l on u > 0, g_r on u < 0)
+//       k_iface_corr_2d          eq. dis1 corrections (g0) and the eq. dis2
+//                                corrections of side 0 (g_l on u > 0), one
+//                                launch with the two phases on alternate blocks
+//       k_iface_kin1_2d          eq. dis2 corrections of side 1 (g_r on u < 0),
+//                                summing all corrections
 //       k_update_2d              conservative update (eq. finite), nonphysical
 //                                flag, CFL bound of the new state
 //   1D: k_ghost_1d (+ time step), k_recon_1d, k_face_1d (fused interface), k_update_1d
@@ -25,7 +28,7 @@
 //   FY  TS     [2][4][ny+3][nx+2]   y-interface Gauss values, interfaces -1..ny+1, cols -1..nx
 //   PC  TP     [4][5][ny+2][nx+2]   reconstruction coefficients, cells -1..nx
 //   FLX double [4][ny][nx+1], FLY double [4][ny+1][nx]   integrated fluxes
-//   frame record of the interfaces (20 doubles + 85 TC each)
+//   frame record of the interfaces (ND_REC doubles + NT_REC TC each)
 // per 1D problem: W double [3][nx+4], FX TS [3][nx+3] (interfaces -1..nx+1),
 //   PC TP [3][2][nx+2], FLX double [3][nx+1].
 // TS = TP = TC = double (GKS_FP64) or float (GKS_FP32_MIXED).
@@ -55,20 +58,42 @@ struct Idx {
   // On a periodic axis the last interface is the first one and is not
   // computed again (fxr = nx, fyr = ny; else nx + 1, ny + 1).
   int fxr, fyr;
+  // Every index is (plane number) x (plane size) + (offset in the plane): the
+  // plane part is uniform over a wave, the in-plane part is one 32-bit
+  // multiply-add per lane shared by all planes (a plane holds fewer than 2^32
+  // entries: the grid size is bounded at initialisation).
+  __device__ __host__ unsigned off(int row, int col, int pitch) const {
+    return (unsigned)row * (unsigned)pitch + (unsigned)col;
+  }
   __device__ __host__ size_t w(int v, int j, int i) const {
-    return ((size_t)v * (ny + 4) + (size_t)(j + 2)) * (nx + 4) + (size_t)(i + 2);
+    return (size_t)v * ((size_t)(ny + 4) * (nx + 4)) + off(j + 2, i + 2, nx + 4);
   }
   __device__ __host__ size_t fx(int g, int v, int j, int fi) const {
-    return (((size_t)g * 4 + v) * (ny + 2) + (size_t)(j + 1)) * (nx + 3) + (size_t)(fi + 1);
+    return (size_t)(g * 4 + v) * ((size_t)(ny + 2) * (nx + 3)) + off(j + 1, fi + 1, nx + 3);
   }
   __device__ __host__ size_t fy(int g, int v, int fj, int i) const {
-    return (((size_t)g * 4 + v) * (ny + 3) + (size_t)(fj + 1)) * (nx + 2) + (size_t)(i + 1);
+    return (size_t)(g * 4 + v) * ((size_t)(ny + 3) * (nx + 2)) + off(fj + 1, i + 1, nx + 2);
   }
   __device__ __host__ size_t pc(int v, int m, int j, int i) const {
-    return (((size_t)v * 5 + m) * (ny + 2) + (size_t)(j + 1)) * (nx + 2) + (size_t)(i + 1);
+    return (size_t)(v * 5 + m) * ((size_t)(ny + 2) * (nx + 2)) + off(j + 1, i + 1, nx + 2);
   }
-  __device__ __host__ size_t flx(int v, int j, int fi) const { return ((size_t)v * ny + j) * (nx + 1) + fi; }
-  __device__ __host__ size_t fly(int v, int fj, int i) const { return ((size_t)v * (ny + 1) + fj) * nx + i; }
+  __device__ __host__ size_t flx(int v, int j, int fi) const {
+    return (size_t)v * ((size_t)ny * (nx + 1)) + off(j, fi, nx + 1);
+  }
+  __device__ __host__ size_t fly(int v, int fj, int i) const {
+    return (size_t)v * ((size_t)(ny + 1) * nx) + off(fj, i, nx);
+  }
+  // the same x / y interface indices in nested form, for the final
+  // read-modify-write of the correction phases: there the address is formed
+  // late, which keeps it out of the phases' register peak
+  __device__ __host__ size_t fx_late(int g, int v, int j, int fi) const {
+    return (((size_t)g * 4 + v) * (ny + 2) + (size_t)(j + 1)) * (nx + 3) + (size_t)(fi + 1);
+  }
+  __device__ __host__ size_t fy_late(int g, int v, int fj, int i) const {
+    return (((size_t)g * 4 + v) * (ny + 3) + (size_t)(fj + 1)) * (nx + 2) + (size_t)(i + 1);
+  }
+  __device__ __host__ size_t flx_late(int v, int j, int fi) const { return ((size_t)v * ny + j) * (nx + 1) + fi; }
+  __device__ __host__ size_t fly_late(int v, int fj, int i) const { return ((size_t)v * (ny + 1) + fj) * nx + i; }
   // 1D layouts (ny = 1)
   __device__ __host__ size_t w1(int v, int i) const { return (size_t)v * (nx + 4) + (size_t)(i + 2); }
   __device__ __host__ size_t f1(int v, int fi) const { return (size_t)v * (nx + 3) + (size_t)(fi + 1); }
@@ -695,34 +720,64 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
   }
 }
 
-// adds interface-frame corrections to the stored flux and point values
-template <typename TS, typename TP>
-__device__ __forceinline__ void add_corrections(const Grid<TS, TP>& g, const Face& F, const double (&flux)[4],
-                                                const double (&pvm)[4], const double (&pvp)[4]) {
+// adds interface-frame corrections to the stored flux and point values; with
+// kPart the partial of side 0 left in the record first.  The direction is a
+// template argument so that the interface-frame component of each global
+// component is a constant (the local arrays stay in registers).
+template <bool kPart, bool kX, typename TS, typename TP, typename TC>
+__device__ __forceinline__ void add_corrections_dir(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
+                                                    const double (&flux)[4], const double (&pvm)[4],
+                                                    const double (&pvp)[4]) {
   const Idx& x = g.ix;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int vl = loc(F.isx, v);
-    if (F.isx) {
-      g.FLX[x.flx(v, F.a, F.b)] += flux[vl];
-      TS* a = &g.FX[x.fx(0, v, F.a, F.b)];
-      TS* b = &g.FX[x.fx(1, v, F.a, F.b)];
-      *a = (TS)((double)*a + pvm[vl]);
-      *b = (TS)((double)*b + pvp[vl]);
+    const int vl = loc(kX, v);
+    double* fl = kX ? &g.FLX[x.flx_late(v, F.a, F.b)] : &g.FLY[x.fly_late(v, F.a, F.b)];
+    TS* a = kX ? &g.FX[x.fx_late(0, v, F.a, F.b)] : &g.FY[x.fy_late(0, v, F.a, F.b)];
+    TS* b = kX ? &g.FX[x.fx_late(1, v, F.a, F.b)] : &g.FY[x.fy_late(1, v, F.a, F.b)];
+    if (kPart) {
+      *fl = (*fl + R.D(D_PF0 + vl, f)) + flux[vl];
+      *a = (TS)(((double)*a + (double)R.T(T_PV0 + vl, f)) + pvm[vl]);
+      *b = (TS)(((double)*b + (double)R.T(T_PV0 + 4 + vl, f)) + pvp[vl]);
     } else {
-      g.FLY[x.fly(v, F.a, F.b)] += flux[vl];
-      TS* a = &g.FY[x.fy(0, v, F.a, F.b)];
-      TS* b = &g.FY[x.fy(1, v, F.a, F.b)];
+      *fl += flux[vl];
       *a = (TS)((double)*a + pvm[vl]);
       *b = (TS)((double)*b + pvp[vl]);
     }
   }
 }
 
+template <bool kPart, typename TS, typename TP, typename TC>
+__device__ __forceinline__ void add_corrections(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
+                                                const double (&flux)[4], const double (&pvm)[4],
+                                                const double (&pvp)[4]) {
+  if (F.isx)
+    add_corrections_dir<kPart, true>(g, F, R, f, flux, pvm, pvp);
+  else
+    add_corrections_dir<kPart, false>(g, F, R, f, flux, pvm, pvp);
+}
+
+// Prandtl-number fix on the complete flux of interface f: energy flux +=
+// (1/Pr - 1) q, q the heat flux relative to the velocity of g0 (interface
+// frame); Ed is the complete <psi f> of the interface
+template <bool kX, typename TS, typename TP, typename TC>
+__device__ __forceinline__ void prandtl_fix_dir(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
+                                                double prfix, const double (&Ed)[4]) {
+  const Idx& x = g.ix;
+  double Fl[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Fl[loc(kX, v)] = kX ? g.FLX[x.flx(v, F.a, F.b)] : g.FLY[x.fly(v, F.a, F.b)];
+  const double U0 = R.D(D_U0, f), V0 = R.D(D_V0, f), k2 = 0.5 * (U0 * U0 + V0 * V0);
+  const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
+  if (kX)
+    g.FLX[x.flx(3, F.a, F.b)] += prfix * qh;
+  else
+    g.FLY[x.fly(3, F.a, F.b)] += prfix * qh;
+}
+
+// eq. dis1 terms of interface id, added to the prologue's flux and point values
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_hydro_2d(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+__device__ __forceinline__ void iface_hydro_body(const Prob<TS, TP, TC>& Q, int id) {
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
@@ -733,16 +788,17 @@ __global__ void __launch_bounds__(256) k_iface_hydro_2d(KA<Prob<TS, TP, TC>> a) 
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
   iface_hydro_2d<TC>(P, dt, hs, R, (size_t)id, flux, pvm, pvp, E);
-  add_corrections(g, F, flux, pvm, pvp);
+  add_corrections<false>(g, F, R, (size_t)id, flux, pvm, pvp);
   if (P.viscous)
 #pragma unroll
     for (int v = 0; v < 4; ++v) R.D(D_E0 + v, id) += E[v];
 }
 
+// eq. dis2 terms of side `side` of interface id.  Side 0 leaves them in the
+// record's partial fields; side 1 adds the partial and its own terms to the
+// flux and point values, then applies the Prandtl-number fix.
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_kin_2d(KA<Prob<TS, TP, TC>> a, int side) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+__device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id, int side) {
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
@@ -755,28 +811,48 @@ __global__ void __launch_bounds__(256) k_iface_kin_2d(KA<Prob<TS, TP, TC>> a, in
   load_face_cell(g, F, side, Wc, pc);
   double flux[4], pvm[4], pvp[4], E[4];
   iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, (size_t)id, flux, pvm, pvp, E);
-  add_corrections(g, F, flux, pvm, pvp);
-  if (P.viscous) {
+  if (side == 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) R.D(D_E0 + v, id) += E[v];
-    if (side == 1) {
-      // Prandtl-number fix on the complete flux: energy flux += (1/Pr - 1) q,
-      // q the heat flux relative to the velocity of g0 (interface frame)
-      const Idx& x = g.ix;
-      double Fl[4], Ed[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Fl[loc(F.isx, v)] = F.isx ? g.FLX[x.flx(v, F.a, F.b)] : g.FLY[x.fly(v, F.a, F.b)];
-        Ed[v] = R.D(D_E0 + v, id);
-      }
-      const double U0 = R.D(D_U0, id), V0 = R.D(D_V0, id), k2 = 0.5 * (U0 * U0 + V0 * V0);
-      const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
-      if (F.isx)
-        g.FLX[x.flx(3, F.a, F.b)] += P.prfix * qh;
-      else
-        g.FLY[x.fly(3, F.a, F.b)] += P.prfix * qh;
+    for (int v = 0; v < 4; ++v) {
+      R.D(D_PF0 + v, id) = flux[v];
+      R.T(T_PV0 + v, id) = (TC)pvm[v];
+      R.T(T_PV0 + 4 + v, id) = (TC)pvp[v];
+      if (P.viscous) R.D(D_PE0 + v, id) = E[v];
     }
+    return;
   }
+  add_corrections<true>(g, F, R, (size_t)id, flux, pvm, pvp);
+  if (P.viscous) {
+    double Ed[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ed[v] = (R.D(D_E0 + v, id) + R.D(D_PE0 + v, id)) + E[v];
+    if (F.isx)
+      prandtl_fix_dir<true>(g, F, R, (size_t)id, P.prfix, Ed);
+    else
+      prandtl_fix_dir<false>(g, F, R, (size_t)id, P.prfix, Ed);
+  }
+}
+
+// the hydrodynamic phase (even logical blocks) and the kinetic phase of
+// side 0 (odd logical blocks) of the same interfaces in one launch of twice
+// the interface blocks; pairs of blocks share a tile, so both phases of an
+// interface run on the same XCD
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_corr_2d(KA<Prob<TS, TP, TC>> a) {
+  const unsigned L = logical_block(a.nblk), tile = L >> 1;
+  const Prob<TS, TP, TC>& Q = a.probs[a.owner[tile]];
+  const int id = (int)((tile - Q.first[KK_FACE]) * blockDim.x + threadIdx.x);
+  if (L & 1u)
+    iface_kin_body(Q, id, 0);
+  else
+    iface_hydro_body(Q, id);
+}
+
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_kin1_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  iface_kin_body(Q, id, 1);
 }
 
 // 1D interfaces 0..nx, fused
@@ -1206,9 +1282,10 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   record_begin(h, st);
   if (G.dim == 2) {
     k_iface_pro_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-    k_iface_hydro_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-    k_iface_kin_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE], 0);
-    k_iface_kin_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE], 1);
+    KA<PR> pair = A[KK_FACE];
+    pair.nblk = 2 * G.nblk[KK_FACE];  // logical block 2t + r: tile t, phase r
+    k_iface_corr_2d<TS, TP, TC><<<pair.nblk, G.bs[KK_FACE], 0, st>>>(pair);
+    k_iface_kin1_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   } else {
     k_face_1d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   }

@@ -245,6 +245,11 @@ struct Acc {
 //                       targets again (from its cell, same arithmetic as in
 //                       the prologue), (TC) the coefficients of g_k and the
 //                       terms of eq. dis2 (once per side).
+// The hydrodynamic phase and the kinetic phase of side 0 run in one launch
+// (alternate blocks): the former adds its terms to the prologue's flux and
+// point values, the latter leaves its own in the record (partial fields),
+// and the kinetic phase of side 1 adds both, in the order
+// ((prologue + hydrodynamic) + side 0) + side 1.
 // The record is a structure of arrays indexed by the interface.
 // ---------------------------------------------------------------------------
 enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
@@ -253,12 +258,15 @@ enum RecD {  // double fields
   D_RHO0, D_U0, D_V0, D_LAM0,
   D_TAU,                    // collision time (the phases rebuild the time weights)
   D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
-  ND_REC
+  D_PF0 = D_E3 + 1,         // side 0's flux (4, interface frame), left for side 1
+  D_PE0 = D_PF0 + 4,        // side 0's <psi f> (4; Navier-Stokes only)
+  ND_REC = D_PE0 + 4
 };
 enum RecT {  // compute-type fields
   T_CG = 0,                 // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar
                             // frame; in double precision its targets bx, by, bxx, bxy, byy (5 x 4)
-  NT_REC = 36
+  T_PV0 = 36,               // side 0's point values at the two Gauss points (2 x 4, interface frame)
+  NT_REC = T_PV0 + 8
 };
 
 // Where the coefficient systems of g0 are solved: in the prologue for a

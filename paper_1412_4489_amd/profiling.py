@@ -32,7 +32,7 @@ import os
 import re
 
 COPY_BYTES = 256 << 20  # the calibration copies of bench.py --pmc-probe
-IFACE = ("k_iface_pro_2d", "k_iface_hydro_2d", "k_iface_kin_2d")
+IFACE = ("k_iface_pro_2d", "k_iface_corr_2d", "k_iface_kin1_2d")
 FACES_256 = 131072  # interface threads of the periodic 256 x 256 grid
 BATCH_MIN_GRID = 400000  # launches of the 96-grid batch are larger than this
 KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
@@ -78,6 +78,12 @@ def kernel_markdown(agg, title, command):
     return "\n".join(lines) + "\n"
 
 
+def threads(kernel, faces):
+    """Launch size of an interface kernel: the combined hydrodynamic / kinetic
+    side 0 launch has two blocks per tile."""
+    return 2 * faces if kernel == "k_iface_corr_2d" else faces
+
+
 def _counter_rows(path):
     with open(path) as fh:
         return list(csv.DictReader(fh))
@@ -95,7 +101,7 @@ def traffic(fetch_csv, write_csv, faces, ttype="float"):
         per = collections.defaultdict(list)
         for r in rows:
             k, t = _short(r["Kernel_Name"])
-            if k in IFACE and t == ttype and int(r["Grid_Size"]) == faces:
+            if k in IFACE and t == ttype and int(r["Grid_Size"]) == threads(k, faces):
                 per[k].append(float(r["Counter_Value"]))
         out[name] = {"factor": factor, "copy_kib": sum(copies) / 3,
                      "kib_per_dispatch": {k: sum(v) / len(v) for k, v in per.items()}}
@@ -103,7 +109,7 @@ def traffic(fetch_csv, write_csv, faces, ttype="float"):
     for name in ("fetch", "write"):
         d = out[name]
         for k, kib in d["kib_per_dispatch"].items():
-            per_set += kib * 1024.0 * d["factor"] * (2 if k == "k_iface_kin_2d" else 1)
+            per_set += kib * 1024.0 * d["factor"]
     out["bytes_per_launch_set"] = per_set
     return out
 
@@ -141,10 +147,10 @@ def _averages(agg):
 
 
 def _step_line(d):
-    iface = d["k_iface_pro_2d"] + d["k_iface_hydro_2d"] + 2 * d["k_iface_kin_2d"]
+    iface = d["k_iface_pro_2d"] + d["k_iface_corr_2d"] + d["k_iface_kin1_2d"]
     tot = iface + d["k_recon_2d"] + d["k_update_2d"] + d["k_ghost_2d"]
-    return (f"interface phases {d['k_iface_pro_2d']:.1f} + {d['k_iface_hydro_2d']:.1f} + 2 x "
-            f"{d['k_iface_kin_2d']:.1f} = {iface:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
+    return (f"interface phases {d['k_iface_pro_2d']:.1f} + {d['k_iface_corr_2d']:.1f} + "
+            f"{d['k_iface_kin1_2d']:.1f} = {iface:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
             f"{d['k_update_2d']:.1f}, boundary (+ time step) {d['k_ghost_2d']:.1f}; sum {tot:.1f} us")
 
 
@@ -154,7 +160,7 @@ def write_kernel_summaries(trace_csv, out):
     big = {k: v for k, v in agg.items() if k[2] >= BATCH_MIN_GRID}
     avg = _averages(small)
     md = kernel_markdown(small, "Kernel trace: isentropic vortex 256 x 256, GKS_FP32_MIXED and GKS_FP64", TRACE_CMD)
-    md += ("\nPer step (averages over the launch sizes of a kernel; the kinetic phase runs twice):\n\n"
+    md += ("\nPer step (averages over the launch sizes of a kernel):\n\n"
            f"* FP32-mixed: {_step_line(avg['float'])}\n* FP64: {_step_line(avg['double'])}\n\n"
            f"{FACES_256} interface threads: on the periodic grid the last interface of each row and column is "
            "the first.\nThe same run also holds the 96-grid batch (kernels_batch96_fp32mixed.md).\n")
@@ -194,10 +200,11 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out):
     for k in IFACE:
         f_, w_ = tr["fetch"]["kib_per_dispatch"][k], tr["write"]["kib_per_dispatch"][k]
         b = (f_ * tr["fetch"]["factor"] + w_ * tr["write"]["factor"]) * 1024
-        s_ = sq.get((k, FACES_256), {})
+        s_ = sq.get((k, threads(k, FACES_256)), {})
         t.append(f"| {k} | {f_:.0f} | {w_:.0f} | {b / 1e6:.1f} MB | {s_.get('waves', 0):.0f} "
                  f"| {s_.get('valu_per_wave', 0):.0f} |")
-    t += ["", f"Interface launch set (prologue + hydrodynamic + 2 x kinetic): {tr['bytes_per_launch_set'] / 1e6:.1f} MB "
+    t += ["", f"Interface launch set (prologue, hydrodynamic + kinetic side 0, kinetic side 1): "
+          f"{tr['bytes_per_launch_set'] / 1e6:.1f} MB "
           "of HBM traffic per step; the algorithmic bytes of the whole step are 12.6 MB (65536 cells x 192 B).",
           "Most of the difference is the frame record the prologue writes (9 doubles + 36 coefficients per "
           "interface) and the read-modify-write of fluxes and point values by the later phases.", "",
