@@ -152,8 +152,9 @@ struct Prob {
 template <class PR>
 struct KA {
   const PR* __restrict__ probs;
-  const uint16_t* __restrict__ owner;
+  const uint32_t* __restrict__ owner;
   unsigned nblk;
+  int single;  // one problem in the group: every block is its, no table lookup
 };
 
 // Blocks are dispatched round robin over the eight XCDs (each with its own
@@ -168,7 +169,7 @@ __device__ __forceinline__ unsigned logical_block(unsigned nblk) {
 template <class PR>
 __device__ __forceinline__ const PR& locate(const KA<PR>& a, int kind, int& local, int* problem = nullptr) {
   const unsigned L = logical_block(a.nblk);
-  const int p = a.owner[L];
+  const int p = a.single ? 0 : (int)a.owner[L];
   const PR& Q = a.probs[p];
   local = (int)((L - Q.first[kind]) * blockDim.x + threadIdx.x);
   if (problem) *problem = p;
@@ -384,19 +385,27 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
 // neither the step nor the CFL slots): ctl[2p] = fixed step (0: CFL),
 // ctl[2p+1] = end time (0: none; the step is shortened to reach it, later
 // steps are empty); the slots are reset for the update of this step
+// The time step of a problem, taken by the first wave of its boundary launch
+// (all 64 lanes active): lane q reads CFL slot q and resets it, a shuffle
+// minimum gives the bound, lane 0 writes the step (the fixed step if one is
+// set, clipped to the end time if one is set).
+static_assert(kDtSlots == 64, "one CFL slot per lane of a wave");
 template <typename TS, typename TP, typename TC>
-__device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ctl, int p) {
+__device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ctl, int p, int lane) {
   const Grid<TS, TP> g = Q.g;
-  const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1];
-  unsigned long long m = g.dtmin[0];
-  for (int q = 1; q < kDtSlots; ++q) {
-    const unsigned long long b = g.dtmin[q];
-    m = b < m ? b : m;
+  const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1], t = *g.t;
+  unsigned long long m = g.dtmin[lane];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off, 64);
+    m = o < m ? o : m;
   }
-  double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
-  if (t_end > 0.0) dt = fmin(dt, fmax(t_end - *g.t, 0.0));
-  *g.dt = dt;
-  for (int q = 0; q < kDtSlots; ++q) g.dtmin[q] = (unsigned long long)__double_as_longlong(1e300);
+  g.dtmin[lane] = (unsigned long long)__double_as_longlong(1e300);
+  if (lane == 0) {
+    double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
+    if (t_end > 0.0) dt = fmin(dt, fmax(t_end - t, 0.0));
+    *g.dt = dt;
+  }
 }
 
 // all 2D boundary images of a problem in one launch, and its time step
@@ -404,7 +413,7 @@ template <typename TS, typename TP, typename TC>
 __global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a, const double* __restrict__ ctl) {
   int id, p;
   const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id, &p);
-  if (id == 0) step_dt(Q, ctl, p);
+  if (id < 64) step_dt(Q, ctl, p, id);
   const int nx = Q.g.ix.nx, ny = Q.g.ix.ny;
   const int nwe = 4 * ny + 4 * ny + 4 * (ny + 1), nsn = 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
   if (id < nwe)
@@ -419,7 +428,7 @@ template <typename TS, typename TP, typename TC>
 __global__ void __launch_bounds__(256) k_ghost_1d(KA<Prob<TS, TP, TC>> a, const double* __restrict__ ctl) {
   int id, p;
   const Prob<TS, TP, TC>& Q = locate(a, KK_GA, id, &p);
-  if (id == 0) step_dt(Q, ctl, p);
+  if (id < 64) step_dt(Q, ctl, p, id);
   if (id >= 6) return;
   const Grid<TS, TP> g = Q.g;
   const double gamma = Q.P.gamma;
@@ -670,8 +679,7 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
   const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
-  const double dt = *g.dt;
-  if (!(dt > 0.0)) return;
+  const double dt = *g.dt;  // tested after the loads below, which do not wait for it
   const Phys P = Q.P;
   const Rec<TC> R = Q.R;
   const Idx& x = g.ix;
@@ -696,6 +704,7 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) Ueq[m][n][loc(false, v)] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
   }
+  if (!(dt > 0.0)) return;
   const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
   const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, (size_t)id, flux, pv);
   if (!ok) {
@@ -781,13 +790,16 @@ __device__ __forceinline__ void iface_hydro_body(const Prob<TS, TP, TC>& Q, int 
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
-  const double dt = *g.dt;
-  if (!(dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  // the step and the record's validity are tested before the stores only, so
+  // that the record loads need not wait for them (a skipped interface
+  // computes with whatever the record holds and discards it)
+  const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
   iface_hydro_2d<TC>(P, dt, hs, R, (size_t)id, flux, pvm, pvp, E);
+  if (!(dt > 0.0) || !(rho0 > 0.0)) return;
   add_corrections<false>(g, F, R, (size_t)id, flux, pvm, pvp);
   if (P.viscous)
 #pragma unroll
@@ -802,8 +814,8 @@ __device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const Rec<TC> R = Q.R;
-  const double dt = *g.dt;
-  if (!(dt > 0.0) || !(R.D(D_RHO0, id) > 0.0)) return;
+  // tested before the stores only (as in the hydrodynamic phase)
+  const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
   const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
@@ -811,6 +823,7 @@ __device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id
   load_face_cell(g, F, side, Wc, pc);
   double flux[4], pvm[4], pvp[4], E[4];
   iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, (size_t)id, flux, pvm, pvp, E);
+  if (!(dt > 0.0) || !(rho0 > 0.0)) return;
   if (side == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -840,7 +853,7 @@ __device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id
 template <typename TS, typename TP, typename TC>
 __global__ void __launch_bounds__(256) k_iface_corr_2d(KA<Prob<TS, TP, TC>> a) {
   const unsigned L = logical_block(a.nblk), tile = L >> 1;
-  const Prob<TS, TP, TC>& Q = a.probs[a.owner[tile]];
+  const Prob<TS, TP, TC>& Q = a.probs[a.single ? 0 : (int)a.owner[tile]];
   const int id = (int)((tile - Q.first[KK_FACE]) * blockDim.x + threadIdx.x);
   if (L & 1u)
     iface_kin_body(Q, id, 0);
@@ -906,28 +919,43 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) W[v] = g.W[x.w(v, j, i)];
     const double dt = kScan ? 0.0 : *g.dt;
-    if (dt > 0.0) {
-      const double ia = 1.0 / (g.geo.h * g.geo.k);
+    if (!kScan) {
+      // every load is issued before the step is tested: none waits for it
       // periodic seams: the last interface is the first one
       const int ie = (i + 1 == nx && x.fxr == nx) ? 0 : i + 1;
       const int je = (j + 1 == ny && x.fyr == ny) ? 0 : j + 1;
+      double d[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double d = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, ie)] + g.FLY[x.fly(v, j, i)] -
-                         g.FLY[x.fly(v, je, i)];
-        W[v] += d * ia;
-        g.W[x.w(v, j, i)] = W[v];
+      for (int v = 0; v < 4; ++v)
+        d[v] = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, ie)] + g.FLY[x.fly(v, j, i)] - g.FLY[x.fly(v, je, i)];
+      // the seam gets the first interface's new point values (read by the
+      // next reconstruction)
+      const bool sx = i == 0 && x.fxr == nx, sy = j == 0 && x.fyr == ny;
+      TS px[8], py[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        px[q] = sx ? g.FX[x.fx(q >> 2, q & 3, j, 0)] : TS(0);
+        py[q] = sy ? g.FY[x.fy(q >> 2, q & 3, 0, i)] : TS(0);
       }
-      // and gets its new point values (read by the next reconstruction)
-      if (i == 0 && x.fxr == nx)
+      const double t0 = id == 0 ? *g.t : 0.0;
+      const long long n0 = id == 0 ? *g.steps : 0;
+      if (dt > 0.0) {
+        const double ia = 1.0 / (g.geo.h * g.geo.k);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) g.FX[x.fx(q >> 2, q & 3, j, nx)] = g.FX[x.fx(q >> 2, q & 3, j, 0)];
-      if (j == 0 && x.fyr == ny)
+        for (int v = 0; v < 4; ++v) {
+          W[v] += d[v] * ia;
+          g.W[x.w(v, j, i)] = W[v];
+        }
+        if (sx)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) g.FY[x.fy(q >> 2, q & 3, ny, i)] = g.FY[x.fy(q >> 2, q & 3, 0, i)];
-      if (id == 0) {
-        *g.t += dt;
-        *g.steps += 1;
+          for (int q = 0; q < 8; ++q) g.FX[x.fx(q >> 2, q & 3, j, nx)] = px[q];
+        if (sy)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) g.FY[x.fy(q >> 2, q & 3, ny, i)] = py[q];
+        if (id == 0) {
+          *g.t = t0 + dt;
+          *g.steps = n0 + 1;
+        }
       }
     }
     // (the scan checks the state it is given: a caller's initial state)
@@ -1007,7 +1035,7 @@ struct Group {
   bool mixed = false;
   std::vector<int> members;
   void* dprobs = nullptr;                  // device Prob<...>[members]
-  uint16_t* owner[KK_COUNT] = {};          // device block-owner tables
+  uint32_t* owner[KK_COUNT] = {};          // device block-owner tables
   unsigned nblk[KK_COUNT] = {};
   unsigned cap[KK_COUNT] = {};             // allocated owner entries
   int bs[KK_COUNT] = {256, 256, 256, 256, 256};  // block size of each kind
@@ -1184,7 +1212,7 @@ int build_tables(gks_handle* h, Group& G) {
   using PR = Prob<TS, TP, TC>;
   const size_t n = G.members.size();
   std::vector<PR> host(n);
-  std::vector<std::vector<uint16_t>> own(KK_COUNT);
+  std::vector<std::vector<uint32_t>> own(KK_COUNT);
   for (size_t m = 0; m < n; ++m) {
     Problem& p = h->probs[G.members[m]];
     PR& d = host[m];
@@ -1201,17 +1229,17 @@ int build_tables(gks_handle* h, Group& G) {
     for (size_t m = 0; m < n; ++m) {
       host[m].first[k] = (unsigned)own[k].size();
       const unsigned nb = cdiv(work_items(h->probs[G.members[m]], G.dim, k), (size_t)G.bs[k]);
-      own[k].insert(own[k].end(), nb, (uint16_t)m);
+      own[k].insert(own[k].end(), nb, (uint32_t)m);
     }
     G.nblk[k] = (unsigned)own[k].size();
     if (G.nblk[k] > G.cap[k]) {
       if (G.owner[k]) (void)hipFree(G.owner[k]);
       G.owner[k] = nullptr;
       G.cap[k] = 0;
-      HIP_OR(h, hipMalloc(&G.owner[k], own[k].size() * sizeof(uint16_t)));
+      HIP_OR(h, hipMalloc(&G.owner[k], own[k].size() * sizeof(uint32_t)));
       G.cap[k] = G.nblk[k];
     }
-    if (G.nblk[k]) HIP_OR(h, hipMemcpy(G.owner[k], own[k].data(), own[k].size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    if (G.nblk[k]) HIP_OR(h, hipMemcpy(G.owner[k], own[k].data(), own[k].size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   }
   if (!G.dprobs) HIP_OR(h, hipMalloc(&G.dprobs, n * sizeof(PR)));
   HIP_OR(h, hipMemcpy(G.dprobs, host.data(), n * sizeof(PR), hipMemcpyHostToDevice));
@@ -1264,7 +1292,8 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   using PR = Prob<TS, TP, TC>;
   const PR* probs = (const PR*)G.dprobs;
   KA<PR> A[KK_COUNT];
-  for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k]};
+  const int single = G.members.size() == 1;
+  for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k], single};
   double* ctl = G.ctl;
   record_begin(h, st);
   if (G.dim == 2) {
@@ -1310,7 +1339,7 @@ void enqueue_step(gks_handle* h, hipStream_t st) {
 template <typename TS, typename TP, typename TC>
 void enqueue_scan(Group& G, hipStream_t st) {
   using PR = Prob<TS, TP, TC>;
-  KA<PR> a{(const PR*)G.dprobs, G.owner[KK_CELL], G.nblk[KK_CELL]};
+  KA<PR> a{(const PR*)G.dprobs, G.owner[KK_CELL], G.nblk[KK_CELL], (int)(G.members.size() == 1)};
   if (G.dim == 2)
     k_update_2d<TS, TP, TC, true><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(a);
   else

@@ -1,13 +1,21 @@
-// emulation.h -- serial host emulation of the HIP constructs used by the
-// kernels in gks.hip, for a bounds-checked CPU build of the kernel code
-// (make_hostcheck.py).  Every block and every thread of a launch runs one
-// after the other on the host; __syncthreads is a no-op, __shared__ arrays are
-// function-static, warp shuffles return the lane's own value.  The arithmetic
-// and every memory access of the kernels are those of the device code, so
-// AddressSanitizer on this build checks each access of each launch against
-// the exact size of its allocation.  Warp shuffles return the lane's own
-// value; make_hostcheck.py lets every lane reach the wave minimum's atomic.
+// emulation.h -- host emulation of the HIP constructs used by the kernels in
+// gks.hip, for a bounds-checked CPU build of the kernel code
+// (make_hostcheck.py).  The blocks of a launch run one after the other; the
+// threads of a block run as coroutines (ucontext fibers) on one host thread,
+// each until it finishes or reaches a cross-lane operation or __syncthreads,
+// which are barriers: when every thread of the block has finished or waits,
+// the waiting ones continue.  A shuffle publishes the lane's value, waits,
+// reads the source lane's value and waits again; a lane that has finished
+// supplies a NaN bit pattern.  __shared__ arrays are function-static.  The
+// arithmetic and every memory access of the kernels are those of the device
+// code, so AddressSanitizer on this build checks each access of each launch
+// against the exact size of its allocation.
 #pragma once
+#include <sys/mman.h>
+#include <ucontext.h>
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/common_interface_defs.h>
+#endif
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -37,10 +45,100 @@ struct dim3 {
 };
 inline thread_local dim3 blockIdx(0, 0, 0), threadIdx(0, 0, 0), blockDim(1, 1, 1), gridDim(1, 1, 1);
 
-inline void __syncthreads() {}
+// ---- fibers: the threads of the running block ----
+struct EmuFibers {
+  static constexpr size_t kStack = 8u << 20;  // per thread, with a guard page below
+  ucontext_t sched;
+  std::vector<ucontext_t> ctx;
+  std::vector<char*> stacks;
+  std::vector<int> state;  // 0 runnable, 1 waiting at a barrier, 2 finished
+  std::vector<unsigned long long> slot;
+  std::vector<char> slot_set;
+  std::function<void()>* body = nullptr;
+  int cur = -1;
+  void* fake_stack = nullptr;
+  const void* sched_bottom = nullptr;
+  size_t sched_size = 0;
+  ~EmuFibers() {
+    for (char* s : stacks) munmap(s, kStack);
+  }
+};
+inline EmuFibers& emu_fibers() {
+  static EmuFibers f;
+  return f;
+}
+inline void emu_switch_to_fiber(EmuFibers& F, int t) {
+#if defined(__SANITIZE_ADDRESS__)
+  __sanitizer_start_switch_fiber(&F.fake_stack, F.stacks[t] + 4096, EmuFibers::kStack - 4096);
+#endif
+  swapcontext(&F.sched, &F.ctx[t]);
+#if defined(__SANITIZE_ADDRESS__)
+  __sanitizer_finish_switch_fiber(F.fake_stack, nullptr, nullptr);
+#endif
+}
+inline void emu_switch_to_sched(EmuFibers& F, bool finished) {
+  const int t = F.cur;
+#if defined(__SANITIZE_ADDRESS__)
+  void* fake = nullptr;
+  __sanitizer_start_switch_fiber(finished ? nullptr : &fake, F.sched_bottom, F.sched_size);
+#endif
+  swapcontext(&F.ctx[t], &F.sched);
+#if defined(__SANITIZE_ADDRESS__)
+  __sanitizer_finish_switch_fiber(fake, &F.sched_bottom, &F.sched_size);
+#endif
+}
+inline void emu_fiber_entry() {
+  EmuFibers& F = emu_fibers();
+#if defined(__SANITIZE_ADDRESS__)
+  __sanitizer_finish_switch_fiber(nullptr, &F.sched_bottom, &F.sched_size);
+#endif
+  (*F.body)();
+  F.state[F.cur] = 2;
+  emu_switch_to_sched(F, true);
+}
+// barrier of the calling thread (a wave barrier is emulated as a block barrier)
+inline void emu_wait() {
+  EmuFibers& F = emu_fibers();
+  F.state[F.cur] = 1;
+  emu_switch_to_sched(F, false);
+}
+inline void __syncthreads() { emu_wait(); }
 template <typename T>
-inline T __shfl_down(T v, unsigned, int) {
-  return v;
+inline T emu_exchange(T v, int src_lane_in_wave) {
+  static_assert(sizeof(T) <= 8, "exchange of at most 64 bits");
+  EmuFibers& F = emu_fibers();
+  const int t = F.cur, base = t - (t & 63);
+  std::memcpy(&F.slot[t], &v, sizeof(T));
+  F.slot_set[t] = 1;
+  emu_wait();
+  T r;
+  const int s = base + src_lane_in_wave;
+  if (s < (int)F.slot.size() && F.slot_set[s]) {
+    std::memcpy(&r, &F.slot[s], sizeof(T));
+  } else {
+    std::memset(&r, 0xff, sizeof(T));  // an inactive lane: NaN / all ones
+  }
+  emu_wait();
+  F.slot_set[t] = 0;
+  return r;
+}
+inline int emu_lane() { return emu_fibers().cur & 63; }
+template <typename T>
+inline T __shfl(T v, int src, int width = 64) {
+  const int lane = emu_lane();
+  return emu_exchange(v, (lane & ~(width - 1)) + (src & (width - 1)));
+}
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  const int lane = emu_lane();
+  const int s = lane ^ mask;
+  return emu_exchange(v, (s & ~(width - 1)) == (lane & ~(width - 1)) ? s : lane);
+}
+template <typename T>
+inline T __shfl_down(T v, unsigned delta, int width = 64) {
+  const int lane = emu_lane();
+  const int s = lane + (int)delta;
+  return emu_exchange(v, (s & ~(width - 1)) == (lane & ~(width - 1)) ? s : lane);
 }
 inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cmp, unsigned long long val) {
   unsigned long long old = *p;
@@ -190,17 +288,56 @@ template <class F>
 inline void gks_emulated_run(dim3 grid, dim3 block, const F& body) {
   gridDim = grid;
   blockDim = block;
+  EmuFibers& E = emu_fibers();
+  const int n = (int)(block.x * block.y * block.z);
+  while ((int)E.stacks.size() < n) {
+    void* m = mmap(nullptr, EmuFibers::kStack, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE,
+                   -1, 0);
+    if (m == MAP_FAILED) std::abort();
+    mprotect(m, 4096, PROT_NONE);  // guard page: a stack overflow faults
+    E.stacks.push_back((char*)m);
+  }
+  E.ctx.resize(n);
+  E.state.assign(n, 0);
+  E.slot.assign(n, 0);
+  E.slot_set.assign(n, 0);
+  std::function<void()> fn = body;
+  E.body = &fn;
   for (unsigned bz = 0; bz < grid.z; ++bz)
     for (unsigned by = 0; by < grid.y; ++by)
       for (unsigned bx = 0; bx < grid.x; ++bx) {
         blockIdx = dim3(bx, by, bz);
-        for (unsigned tz = 0; tz < block.z; ++tz)
-          for (unsigned ty = 0; ty < block.y; ++ty)
-            for (unsigned tx = 0; tx < block.x; ++tx) {
-              threadIdx = dim3(tx, ty, tz);
-              body();
+        for (int t = 0; t < n; ++t) {
+          getcontext(&E.ctx[t]);
+          E.ctx[t].uc_stack.ss_sp = E.stacks[t] + 4096;
+          E.ctx[t].uc_stack.ss_size = EmuFibers::kStack - 4096;
+          E.ctx[t].uc_link = nullptr;
+          makecontext(&E.ctx[t], emu_fiber_entry, 0);
+          E.state[t] = 0;
+          E.slot_set[t] = 0;
+        }
+        for (;;) {
+          bool any = false;
+          for (int t = 0; t < n; ++t) {
+            if (E.state[t] != 0) continue;
+            threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+            E.cur = t;
+            emu_switch_to_fiber(E, t);
+            any = true;
+          }
+          // every thread has finished or waits at a barrier: release them
+          bool waiting = false;
+          for (int t = 0; t < n; ++t)
+            if (E.state[t] == 1) {
+              E.state[t] = 0;
+              waiting = true;
             }
+          if (!waiting) break;
+          (void)any;
+        }
       }
+  E.body = nullptr;
+  E.cur = -1;
 }
 
 template <class F>
