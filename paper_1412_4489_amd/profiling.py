@@ -206,8 +206,9 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out):
     t += ["", f"Interface launch set (prologue, hydrodynamic + kinetic side 0, kinetic side 1): "
           f"{tr['bytes_per_launch_set'] / 1e6:.1f} MB "
           "of HBM traffic per step; the algorithmic bytes of the whole step are 12.6 MB (65536 cells x 192 B).",
-          "Most of the difference is the frame record the prologue writes (9 doubles + 36 coefficients per "
-          "interface) and the read-modify-write of fluxes and point values by the later phases.", "",
+          "Most of the difference is the frame record: the prologue writes 9 doubles + 36 coefficients per "
+          "interface, kinetic side 0 leaves 4 doubles + 8 point values for side 1, and the phases "
+          "read-modify-write the fluxes and point values.", "",
           "traffic_iface_vortex256_fp32mixed.json holds these figures with the hash of the kernel sources they "
           "were taken from (bench.py reports `traffic` only while the sources match)."]
     with open(os.path.join(out, "counters_iface_vortex256_fp32mixed.md"), "w") as fh:
