@@ -521,13 +521,14 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
     Wn[4][v] = g.W[x.w(v, j - 1, i)];
   }
   double p[4][5], Wc[4];
+  const ReconDiv D(h, k);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     Wc[v] = Wn[0][v];
     recon_2d(Wc[v], Wn[1][v], Wn[2][v], Wn[3][v], Wn[4][v], (double)g.FX[x.fx(1, v, j, i + 1)],
              (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)],
              (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)], (double)g.FY[x.fy(1, v, j, i)],
-             (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, p[v]);
+             (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, D, p[v]);
   }
   // an inadmissible polynomial is replaced by the constant cell average for
   // this step

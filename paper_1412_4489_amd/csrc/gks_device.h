@@ -328,6 +328,22 @@ struct Coefs {
   TC ax[4], ay[4], At[4], dxx[4], dxy[4], dyy[4], bxt[4], byt[4], Bt[4];
 };
 
+// Division by a divisor b with a precomputed reciprocal rb = RN(1/b): the
+// quotient q = RN(a rb) is within one ulp of a/b, its remainder a - q b is
+// exact with an FMA, and q + remainder rb rounded once is the correctly
+// rounded a/b (Markstein's correction step; finite normal operands), the
+// same bits as the division itself in three dependent operations.
+struct Divisor {
+  double b, rb;
+};
+__device__ __forceinline__ Divisor divisor(double b) { return Divisor{b, 1.0 / b}; }
+__device__ __forceinline__ double div_by(double a, const Divisor& d) {
+#pragma clang fp contract(off)
+  const double q = a * d.rb;
+  const double r = fma(-q, d.b, a);
+  return fma(r, d.rb, q);
+}
+
 // State of side s (0: left cell, 1: right cell) at the interface centre from
 // its cell average Wc and reconstruction pc = (p_n, p_s, p_nn, p_ss, p_ns) in
 // the interface frame; false if nonphysical.
@@ -344,8 +360,9 @@ __device__ __forceinline__ bool side_state_2d(const Phys& P, int s, double hn, d
     W[v] = Wc[v] + p[0] * xn + p[2] * (hn * hn * (1.0 / 12.0)) - p[3] * (hs * hs * (1.0 / 24.0));
   }
   o.rho = W[0];
-  o.U = W[1] / o.rho;
-  o.V = W[2] / o.rho;
+  const Divisor dr = divisor(o.rho);
+  o.U = div_by(W[1], dr);
+  o.V = div_by(W[2], dr);
   o.pr = (P.gamma - 1.0) * (W[3] - 0.5 * o.rho * (o.U * o.U + o.V * o.V));
   o.lam = 0.5 * o.rho / o.pr;
   return o.rho > 0.0 && o.pr > 0.0;
@@ -403,7 +420,8 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
     Fk[2] += rho * V * m.M1;
     Fk[3] += rho * 0.5 * (m.M3 + e2 * m.M1);
   }
-  const double rho0 = W0[0], U0 = W0[1] / rho0, V0 = W0[2] / rho0;
+  const Divisor d0 = divisor(W0[0]);
+  const double rho0 = W0[0], U0 = div_by(W0[1], d0), V0 = div_by(W0[2], d0);
   const double p0 = g1 * (W0[3] - 0.5 * rho0 * (U0 * U0 + V0 * V0));
   if (!(p0 > 0.0)) return false;
   const double lam0 = 0.5 * rho0 / p0;
@@ -414,6 +432,9 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   // equilibrium quadratic (Sec. 3.3) -> targets and coefficients of g0
   {
     const double ir = 1.0 / rho0;
+    // the divisors of the five derivatives (uniform over a launch)
+    const Divisor qdiv[5] = {divisor(4.0 * hn), divisor(4.0 * hs), divisor(8.0 * hn * hn), divisor(2.0 * hn * hs),
+                             divisor(2.0 * hs * hs)};
     TC b[5][4];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -422,12 +443,12 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
       for (int v = 0; v < 4; ++v) {
         const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
         const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
-        qd[v] = (k == 0   ? ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)) / (4.0 * hn)                      // U_x
-                 : k == 1 ? (R2 - R0 + L2 - L0) / (4.0 * hs)                                            // U_y
-                 : k == 2 ? (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]) / (8.0 * hn * hn)  // U_xx
-                 : k == 3 ? (R2 - L2 - R0 + L0) / (2.0 * hn * hs)                                       // U_xy
-                          : (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0) / (2.0 * hs * hs)) *              // U_yy
-                ir;
+        const double num = k == 0   ? (R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0)                    // U_x
+                           : k == 1 ? R2 - R0 + L2 - L0                                            // U_y
+                           : k == 2 ? 26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]      // U_xx
+                           : k == 3 ? R2 - L2 - R0 + L0                                            // U_xy
+                                    : R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0;                   // U_yy
+        qd[v] = div_by(num, qdiv[k]) * ir;
       }
       double bf[4];
       to_frame_2d(qd, U0, V0, bf);
@@ -630,49 +651,60 @@ __device__ __forceinline__ double mm2(double a, double b) {
   return fabs(a) < fabs(b) ? a : b;
 }
 
+// the divisors of the 2D reconstruction of a cell of size h x k
+struct ReconDiv {
+  Divisor h, k, hh, kk, hk, h2, k2, hk2, six;
+  __device__ __forceinline__ explicit ReconDiv(double h_, double k_)
+      : h(divisor(h_)), k(divisor(k_)), hh(divisor(h_ * h_)), kk(divisor(k_ * k_)), hk(divisor(h_ * k_)),
+        h2(divisor(2.0 * h_)), k2(divisor(2.0 * k_)), hk2(divisor(2.0 * (h_ * k_))), six(divisor(6.0)) {}
+};
+
 // 2D: c = cell average; e, w, n, s = face-neighbour averages; E+-, W+-, N+-, S+-
 // = Gauss-point values on the four interfaces.  p = (p2..p6).
 // The quantities that decide branches (the one-sided estimates, the minmod
 // arguments and the cross-derivative candidates) are formed in the order of
 // their printed formulas and without FMA contraction, so that a tie or a sign
-// is decided from the same rounded values as in a plain evaluation.
+// is decided from the same rounded values as in a plain evaluation (every
+// quotient is the correctly rounded one, see div_by).
 __device__ __forceinline__ void recon_2d(double c, double e, double w, double n, double s, double Ep, double Em,
                                          double Wp, double Wm, double Np, double Nm, double Sp, double Sm, double h,
-                                         double k, double eps, double Cw, double* p) {
+                                         double k, double eps, double Cw, const ReconDiv& D, double* p) {
 #pragma clang fp contract(off)
   // eq. over-sys: normal (x) and tangential (y) pairs of the one-sided stencils
-  const double cxE = 3.0 * ((c + e) - (Ep + Em)) / (h * h), sxE = (Ep + Em - 2.0 * c) / h;
-  const double cxW = 3.0 * ((c + w) - (Wp + Wm)) / (h * h), sxW = (Wp + Wm - 2.0 * c) / h;
-  const double cyN = 3.0 * ((c + n) - (Np + Nm)) / (k * k), syN = (Np + Nm - 2.0 * c) / k;
-  const double cyS = 3.0 * ((c + s) - (Sp + Sm)) / (k * k), syS = (Sp + Sm - 2.0 * c) / k;
+  const double cxE = div_by(3.0 * ((c + e) - (Ep + Em)), D.hh), sxE = div_by(Ep + Em - 2.0 * c, D.h);
+  const double cxW = div_by(3.0 * ((c + w) - (Wp + Wm)), D.hh), sxW = div_by(Wp + Wm - 2.0 * c, D.h);
+  const double cyN = div_by(3.0 * ((c + n) - (Np + Nm)), D.kk), syN = div_by(Np + Nm - 2.0 * c, D.k);
+  const double cyS = div_by(3.0 * ((c + s) - (Sp + Sm)), D.kk), syS = div_by(Sp + Sm - 2.0 * c, D.k);
   // eq. limiter on each pair
   const double a4 = mm2(cxW, cxE);
-  const double a2 = mm2(-sxW + a4 * h / 6.0, sxE - a4 * h / 6.0);
+  const double a2 = mm2(-sxW + div_by(a4 * h, D.six), sxE - div_by(a4 * h, D.six));
   const double a5 = mm2(cyS, cyN);
-  const double a3 = mm2(-syS + a5 * k / 6.0, syN - a5 * k / 6.0);
+  const double a3 = mm2(-syS + div_by(a5 * k, D.six), syN - div_by(a5 * k, D.six));
   // cross term of the stencils NE, NW, SW, SE with the limited slopes; the one
   // of smallest magnitude (the earlier one on an exact tie)
   const double s3 = 1.7320508075688772;  // sqrt(3)
   const double dE = Ep - Em, dW = Wp - Wm, dN = Np - Nm, dS = Sp - Sm;
-  const double hk = h * k;
-  double a6 = s3 * (dE + dN) / hk - (a2 / k + a3 / h);
-  double cand = s3 * (dN - dW) / hk - (a2 / k - a3 / h);
+  const double ak = div_by(a2, D.k), ah = div_by(a3, D.h);
+  double a6 = div_by(s3 * (dE + dN), D.hk) - (ak + ah);
+  double cand = div_by(s3 * (dN - dW), D.hk) - (ak - ah);
   if (fabs(cand) < fabs(a6)) a6 = cand;
-  cand = -s3 * (dS + dW) / hk + (a2 / k + a3 / h);
+  cand = div_by(-s3 * (dS + dW), D.hk) + (ak + ah);
   if (fabs(cand) < fabs(a6)) a6 = cand;
-  cand = s3 * (dE - dS) / hk + (a2 / k - a3 / h);
+  cand = div_by(s3 * (dE - dS), D.hk) + (ak - ah);
   if (fabs(cand) < fabs(a6)) a6 = cand;
   // central stencil
-  const double c2 = (e - w) / (2.0 * h), c4 = (e - 2.0 * c + w) / (h * h);
-  const double c3 = (n - s) / (2.0 * k), c5 = (n - 2.0 * c + s) / (k * k);
-  const double c6 = s3 * ((dE - dW) + (dN - dS)) / (2.0 * hk);
+  const double c2 = div_by(e - w, D.h2), c4 = div_by(e - 2.0 * c + w, D.hh);
+  const double c3 = div_by(n - s, D.k2), c5 = div_by(n - 2.0 * c + s, D.kk);
+  const double c6 = div_by(s3 * ((dE - dW) + (dN - dS)), D.hk2);
   // nonlinear weights, I(U1) = C |cell|, I(U2) from the derivatives of U2
+  const double hk = h * k;
   const double A = hk;
   const double I1 = Cw * A;
   const double I2 = A * (c2 * c2 + c3 * c3) + A * (c4 * c4 * (h * h / 12.0 + A) + c5 * c5 * (k * k / 12.0 + A) +
                                                   c6 * c6 * ((h * h + k * k) / 12.0 + A));
   const double b1 = 1.0 / ((eps + I1) * (eps + I1)), b2 = 1.0 / ((eps + I2) * (eps + I2));
-  const double w1 = b1 / (b1 + b2), w2 = b2 / (b1 + b2);
+  const Divisor sb = divisor(b1 + b2);
+  const double w1 = div_by(b1, sb), w2 = div_by(b2, sb);
   p[0] = w1 * a2 + w2 * c2;
   p[1] = w1 * a3 + w2 * c3;
   p[2] = w1 * a4 + w2 * c4;
