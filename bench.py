@@ -18,9 +18,12 @@ reported beside it.  The interface phases (the dominant kernels) are timed
 live with HIP events on the stream they run on, in an eager run of the same
 steps; `roofline` prices their algorithmic floating-point operations (the
 straight-line operation count of the generated interface arithmetic plus the
-double-precision prologue) against the vector ALU peak, and `traffic` gives
-their HBM bytes from the committed counter record while the kernel sources
-still match it.  `cpu_baseline` times the FP64 oracle on this host for a
+double-precision prologue) against the vector ALU peak (and against the rate
+without packed FP32, which this build does not use); `traffic` (HBM bytes) and
+`valu_busy` (rocprofv3's VALUBusy of the interface kernels) come from the
+committed counter record while the kernel sources still match it.  `configs`
+gives the throughput of the other full-size 2D workloads (lid-driven cavity
+512^2, Navier-Stokes; double Mach reflection 1920x480) in both forms.  `cpu_baseline` times the FP64 oracle on this host for a
 bounded number of steps of the same workload; the same steps on the GPU give
 the L1 difference to the oracle.
 
@@ -40,6 +43,9 @@ import numpy as np  # noqa: E402
 
 N = 256
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
+# the same without packed FP32 (not used by this build): 256 CU x 4 SIMD x 16
+# lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_NONPACKED = 78.6e12
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 # double-precision work per interface outside the generated functions
 # (interface values, primitives, half-space moments, U0, equilibrium
@@ -55,19 +61,20 @@ KIN_TERMS_NS = KIN_TERMS_EULER + ("A", "tlin", "ty")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_iface_vortex256_fp32mixed.json")
 
 
-def traffic_record():
-    """HBM bytes per launch set of the interface kernels from the committed
-    counter record (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    factors), or None if there is none for the present kernel sources."""
+def counter_record():
+    """The committed counter record of the interface kernels (HBM bytes per
+    launch set from FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors,
+    VALUBusy), or {} if there is none for the present kernel sources."""
     try:
         with open(TRAFFIC_RECORD) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     from paper_1412_4489_amd.profiling import source_hash
     if rec.get("source_hash") != source_hash():
-        return None
-    return rec.get("bytes_per_launch_set")
+        return {}
+    return rec
+
 
 
 def pmc_probe():
@@ -139,6 +146,34 @@ def run_gpu(precision, steps, warmup, items=None):
     return wall, kt, probs, sizes
 
 
+def config_rates(steps=20, warmup=3):
+    """Throughput of the other full-size 2D workloads of the paper (FP32-mixed
+    and FP64): tuned launch shapes, graph replays, steps from the CFL
+    condition.  Returns {name: {precision: Mcell-updates/s}}."""
+    import torch
+    from paper_1412_4489_amd import gks
+    from paper_1412_4489_amd import workloads as W
+    out = {}
+    for name, mk in (("cavity_512x512_ns_re1000", lambda: W.cavity(512)),
+                     ("double_mach_reflection_1920x480", lambda: W.dmr(1920, 480))):
+        prob, st = mk()
+        out[name] = {}
+        for pname, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
+            side = torch.cuda.Stream()
+            with gks.Solver(prob, st, prec, stream=side.cuda_stream) as S:
+                S.tune(2)
+                S.step(warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.step(steps)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                S.fetch()
+            out[name][pname] = round(prob.ncells * steps / wall / 1e6, 3)
+        print(f"# {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def gpu_fixed_steps(precision, nsteps, dt):
     from paper_1412_4489_amd import gks
     from paper_1412_4489_amd import workloads as W
@@ -173,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-grid batched form")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the cavity 512^2 and double Mach reflection 1920x480 throughputs")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the copy calibration and a few vortex steps (for rocprofv3 --pmc)")
     a = ap.parse_args()
@@ -232,6 +269,7 @@ def main():
         print(f"# batched: {bsteps} steps of {len(bprobs)} grids ({bcells} cells) in {bwall * 1e3:.2f} ms",
               file=sys.stderr, flush=True)
 
+    rec = counter_record()
     out = {
         "metric": "Mcell-updates/s (FP32 & batched vs FP64) at stated L1 err vs oracle",
         "value": round(value, 3),
@@ -252,11 +290,16 @@ def main():
                  "interface_tflops": round(achieved64 / 1e12, 3)},
         "batched": batched,
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": traffic_record(),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 5), "traffic": rec.get("bytes_per_launch_set"),
+                     "peak_nonpacked": PEAK_FP32_NONPACKED / 1e12,
+                     "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED, 5),
+                     "valu_busy": rec.get("valu_busy_launch_set"),
                      "kernel": "k_iface_{pro,corr,kin1}_2d<float> (one launch set per step)",
                      "flops_per_interface": interface_flops(False),
                      "interface_ms": round(t_if * 1e3, 5)},
     }
+    if not a.no_configs:
+        out["configs"] = config_rates()
     if not a.no_cpu:
         cb, ref, nref, dt = cpu_baseline()
         out["cpu_baseline"] = cb

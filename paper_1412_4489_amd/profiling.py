@@ -34,6 +34,7 @@ import re
 COPY_BYTES = 256 << 20  # the calibration copies of bench.py --pmc-probe
 IFACE = ("k_iface_pro_2d", "k_iface_corr_2d", "k_iface_kin1_2d")
 FACES_256 = 131072  # interface threads of the periodic 256 x 256 grid
+CUS, CLOCK_MHZ = 256, 2400  # MI355X compute units and clock (VALUBusy below)
 BATCH_MIN_GRID = 400000  # launches of the 96-grid batch are larger than this
 KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -124,12 +125,21 @@ def sq_summary(sq_csv, faces, ttype="float"):
     for key, d in per.items():
         m = {c: sum(v) / len(v) for c, v in d.items()}
         if m.get("SQ_WAVES"):
-            res[key] = {"waves": m["SQ_WAVES"], "valu_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"]}
+            res[key] = {"waves": m["SQ_WAVES"], "valu_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+                        "valu_quad_cycles": m.get("SQ_ACTIVE_INST_VALU", 0.0)}
     return res
 
 
+def valu_busy(quad_cycles, duration_us):
+    """rocprofv3's VALUBusy (sum of SQ_ACTIVE_INST_VALU / CUs / GPU cycles),
+    with the kernel's own duration from the kernel trace as the cycle count:
+    the fraction of time the vector ALUs of a CU (4 SIMDs, one quad-cycle per
+    wave instruction) are issuing."""
+    return quad_cycles / CUS / (duration_us * CLOCK_MHZ)
+
+
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_bench "
-             "-o bench --output-format csv -- python -u $R/bench.py --steps 50 --warmup 5 --no-cpu")
+             "-o bench --output-format csv -- python -u $R/bench.py --steps 50 --warmup 5 --no-cpu --no-configs")
 PMC_PASSES = (("FETCH_SIZE", "pmc_fetch", "f"), ("WRITE_SIZE", "pmc_write", "w"),
               ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
                "pmc_sq", "s"))
@@ -175,15 +185,29 @@ def write_kernel_summaries(trace_csv, out):
             fh.write(md)
 
 
-def write_counter_summaries(fetch_csv, write_csv, sq_csv, out):
+def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
     tr = traffic(fetch_csv, write_csv, FACES_256)
     sq = sq_summary(sq_csv, FACES_256) if sq_csv else {}
+    # kernel durations of the same workload (FP32-mixed, 256 x 256) from the trace
+    dur = {}
+    if trace_csv:
+        for (k, t, g), v in kernel_table(trace_csv).items():
+            if t == "float" and k in IFACE and g == threads(k, FACES_256):
+                dur[k] = sum(v) / len(v)
+    busy = {k: valu_busy(sq[(k, threads(k, FACES_256))]["valu_quad_cycles"], dur[k])
+            for k in IFACE if k in dur and (k, threads(k, FACES_256)) in sq}
+    busy_set = None
+    if len(busy) == len(IFACE):
+        busy_set = (sum(sq[(k, threads(k, FACES_256))]["valu_quad_cycles"] for k in IFACE) / CUS
+                    / (sum(dur[k] for k in IFACE) * CLOCK_MHZ))
     rec = {"source_hash": source_hash(),
            "workload": "isentropic vortex 256x256, GKS_FP32_MIXED, tuned launch shapes",
            "bytes_per_launch_set": round(tr["bytes_per_launch_set"]),
            "fetch_factor": tr["fetch"]["factor"], "write_factor": tr["write"]["factor"],
            "fetch_kib_per_dispatch": tr["fetch"]["kib_per_dispatch"],
-           "write_kib_per_dispatch": tr["write"]["kib_per_dispatch"]}
+           "write_kib_per_dispatch": tr["write"]["kib_per_dispatch"],
+           "valu_busy": {k: round(v, 4) for k, v in busy.items()},
+           "valu_busy_launch_set": None if busy_set is None else round(busy_set, 4)}
     with open(os.path.join(out, "traffic_iface_vortex256_fp32mixed.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
@@ -195,20 +219,23 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out):
           "Calibration: `bench.py --pmc-probe` first copies 256 MiB three times (`__amd_rocclr_copyBuffer`).",
           f"FETCH_SIZE reads {tr['fetch']['copy_kib']:.0f} KiB per copy (factor {tr['fetch']['factor']:.4f}), "
           f"WRITE_SIZE {tr['write']['copy_kib']:.0f} KiB (factor {tr['write']['factor']:.4f}).", "",
+          "VALUBusy = SQ_ACTIVE_INST_VALU (quad-cycles, all CUs) / 256 CUs / kernel cycles (the kernel's mean "
+          "duration in the kernel trace x 2.4 GHz).", "",
           "| kernel | FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) | HBM bytes/dispatch (scaled) | waves "
-          "| VALU instr./wave |", "|---|---:|---:|---:|---:|---:|"]
+          "| VALU instr./wave | duration (us) | VALUBusy |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for k in IFACE:
         f_, w_ = tr["fetch"]["kib_per_dispatch"][k], tr["write"]["kib_per_dispatch"][k]
         b = (f_ * tr["fetch"]["factor"] + w_ * tr["write"]["factor"]) * 1024
         s_ = sq.get((k, threads(k, FACES_256)), {})
         t.append(f"| {k} | {f_:.0f} | {w_:.0f} | {b / 1e6:.1f} MB | {s_.get('waves', 0):.0f} "
-                 f"| {s_.get('valu_per_wave', 0):.0f} |")
+                 f"| {s_.get('valu_per_wave', 0):.0f} | {dur.get(k, 0):.2f} | {100 * busy.get(k, 0):.0f} % |")
     t += ["", f"Interface launch set (prologue, hydrodynamic + kinetic side 0, kinetic side 1): "
           f"{tr['bytes_per_launch_set'] / 1e6:.1f} MB "
           "of HBM traffic per step; the algorithmic bytes of the whole step are 12.6 MB (65536 cells x 192 B).",
           "Most of the difference is the frame record: the prologue writes 9 doubles + 36 coefficients per "
           "interface, kinetic side 0 leaves 4 doubles + 8 point values for side 1, and the phases "
-          "read-modify-write the fluxes and point values.", "",
+          "read-modify-write the fluxes and point values.",
+          "" if busy_set is None else f"VALUBusy of the launch set: {100 * busy_set:.0f} %.", "",
           "traffic_iface_vortex256_fp32mixed.json holds these figures with the hash of the kernel sources they "
           "were taken from (bench.py reports `traffic` only while the sources match)."]
     with open(os.path.join(out, "counters_iface_vortex256_fp32mixed.md"), "w") as fh:
@@ -226,7 +253,7 @@ def main():
     if a.trace:
         write_kernel_summaries(a.trace, a.out)
     if a.fetch and a.write:
-        write_counter_summaries(a.fetch, a.write, a.sq, a.out)
+        write_counter_summaries(a.fetch, a.write, a.sq, a.out, a.trace)
 
 
 if __name__ == "__main__":
