@@ -81,6 +81,8 @@ def main(outdir=None):
     s, n = re.subn(r"if \(\(threadIdx\.x & 63\) == 0\) (atomicMin\()", r"\1", s)
     assert n == 1, "wave-minimum pattern not found"
     s = rewrite_launches(s)
+    # the correctly rounded division helper of the device code, for a host test
+    s += ('\nextern "C" double gks_emu_div_by(double a, double b) { return gks::div_by(a, gks::divisor(b)); }\n')
     # emulated device memory for callers of gks_init_device
     s += ('\nextern "C" void* gks_emu_alloc(size_t n) {\n  void* p = nullptr;\n'
           '  return hipMalloc(&p, n) == hipSuccess ? p : nullptr;\n}\n'

@@ -1,4 +1,4 @@
-"""Runs the kernels of the HIP library through the serial host emulation
+"""Runs the kernels of the HIP library through the host emulation
 (paper_1412_4489_amd/csrc/hostcheck) under AddressSanitizer, for the cases of
 the GPU parity tests, and compares one FP64 step with the oracle.  Executed in
 a subprocess by test_hostcheck.py with libasan preloaded; prints one line per
@@ -16,6 +16,24 @@ from paper_1412_4489_amd import gks  # noqa: E402
 from paper_1412_4489_amd import workloads as W  # noqa: E402
 
 gks.LIB_PATH = sys.argv[1]
+
+# the device code's division by a divisor with a known reciprocal
+# (div_by(a, divisor(b))) must give the correctly rounded quotient, i.e. the
+# bits of a / b: random operands over 80 binades, and the divisors the
+# reconstruction uses (cell sizes and their products, 6)
+import ctypes as _C  # noqa: E402
+_L = _C.CDLL(sys.argv[1])
+_L.gks_emu_div_by.restype = _C.c_double
+_L.gks_emu_div_by.argtypes = [_C.c_double, _C.c_double]
+_rng = np.random.default_rng(20141215)
+_a = _rng.uniform(1.0, 2.0, 200000) * np.exp2(_rng.integers(-40, 40, 200000)) * _rng.choice([-1.0, 1.0], 200000)
+_b = _rng.uniform(1.0, 2.0, 200000) * np.exp2(_rng.integers(-30, 30, 200000))
+_h = 10.0 / np.array([64, 96, 128, 192, 256, 384, 512], dtype=np.float64)
+_b[:7000] = np.tile(np.concatenate([_h, _h * _h, 2.0 * _h, [6.0, 12.0, 3.0, 1.0 / 3.0]]), 1000)[:7000]
+_bad = sum(1 for x, y in zip(_a.tolist(), _b.tolist()) if _L.gks_emu_div_by(x, y) != x / y)
+print(f"division: {_bad} of {len(_a)} quotients differ from a / b", flush=True)
+if _bad == 0:
+    print("division ok", flush=True)
 CASES = {
     "smooth": lambda: W.smooth_periodic_2d(nx=17, ny=13, seed=1),
     "rough": lambda: W.random_perturbed_2d(nx=15, ny=11, seed=2, amp=0.15),
@@ -196,4 +214,4 @@ for args, what in (((ptrs[0], small, ptrs[2]), "is smaller"), ((ptrs[0], host[1]
 L.gks_emu_free(small)
 for q in ptrs:
     L.gks_emu_free(q)
-sys.exit(1 if bad else 0)
+sys.exit(1 if bad or _bad else 0)

@@ -2,7 +2,9 @@
 kernel code is compiled for the host in a serial emulation of the launch
 grid (paper_1412_4489_amd/csrc/hostcheck) with AddressSanitizer, and the
 cases of the GPU parity tests are run through the C ABI; the FP64 step also
-matches the oracle.  No GPU is needed."""
+matches the oracle.  The same build checks that the device code's division
+with a precomputed reciprocal gives the bits of the IEEE quotient.  No GPU
+is needed."""
 import os
 import subprocess
 import sys
@@ -29,3 +31,4 @@ def test_kernels_in_bounds_under_asan(tmp_path):
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-6000:]
     assert "ERROR: AddressSanitizer" not in r.stderr
     assert "batch ok" in r.stdout
+    assert "division ok" in r.stdout
