@@ -56,7 +56,10 @@ class Problem:
     tau_c: float = 1.0
     cfl: float = 0.2
     weno_eps: float = 1e-6
-    weno_c: float = 1.0
+    # C of I(U1) = C h^2 (Sec. 3.1; not printed): large enough that the central
+    # polynomial carries smooth regions (the third order of Table 2), small
+    # enough that the limited one-sided polynomial carries discontinuities
+    weno_c: float = 10.0
     recon_vars: int = 0
     bc: list = field(default_factory=lambda: [BC(), BC(), BC(), BC()])
     t_end: float = 0.0
