@@ -23,9 +23,11 @@ without packed FP32, which this build does not use); `traffic` (HBM bytes) and
 `valu_busy` (rocprofv3's VALUBusy of the interface kernels) come from the
 committed counter record while the kernel sources still match it.  `configs`
 gives the throughput of the other full-size 2D workloads (lid-driven cavity
-512^2, Navier-Stokes; double Mach reflection 1920x480) in both forms.  `cpu_baseline` times the FP64 oracle on this host for a
-bounded number of steps of the same workload; the same steps on the GPU give
-the L1 difference to the oracle.
+512^2, Navier-Stokes; double Mach reflection 1920x480) in both forms.
+`cpu_baseline` times the FP64 oracle on this host for a bounded number of
+steps of the same workload; the same steps on the GPU give the L1 difference
+to the oracle and the conservation drift (largest relative change of the
+totals of mass, momentum and energy).
 
 `--pmc-probe` runs the counter-collection workload (a 256 MiB calibration
 copy, then a few eager steps of the tuned FP32-mixed vortex).
@@ -175,13 +177,22 @@ def config_rates(steps=20, warmup=3):
 
 
 def gpu_fixed_steps(precision, nsteps, dt):
+    """The vortex after nsteps fixed steps on the GPU, and its initial state."""
     from paper_1412_4489_amd import gks
     from paper_1412_4489_amd import workloads as W
     prob, st = W.vortex_2d(N)
     with gks.Solver(prob, st, precision) as S:
         S.step(nsteps, dt=dt)
         got, t, n = S.fetch()
-    return got
+    return got, st
+
+
+def conservation_drift(init, got):
+    """Largest relative change of the totals of mass, both momenta and energy
+    (the periodic vortex conserves all four exactly)."""
+    t0 = init.cell.sum(axis=(1, 2))
+    t1 = got.cell.sum(axis=(1, 2))
+    return float(np.max(np.abs(t1 - t0) / np.abs(t0)))
 
 
 def cpu_baseline(budget_s=15.0):
@@ -303,11 +314,13 @@ def main():
     if not a.no_cpu:
         cb, ref, nref, dt = cpu_baseline()
         out["cpu_baseline"] = cb
-        errs = {}
+        errs, drift = {}, {}
         for name, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
-            got = gpu_fixed_steps(prec, nref, dt)
+            got, init = gpu_fixed_steps(prec, nref, dt)
             errs[name] = float(np.abs(got.cell[0] - ref.cell[0]).mean() / np.abs(ref.cell[0]).mean())
+            drift[name] = conservation_drift(init, got)
         out["l1_rel_err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
+        out["conservation_drift"] = {k: float(f"{v:.3e}") for k, v in drift.items()}
         out["l1_sample_steps"] = nref
     print(json.dumps(out), flush=True)
 
