@@ -135,7 +135,7 @@ constexpr int kDtSlots = 64;
 constexpr size_t kScalBytes = 64 + kDtSlots * 8;  // t, dt, steps, err (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
-enum Kind { KK_GA = 0, KK_GB, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };  // KK_GB: unused (no work)
+enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };  // boundary, cells+ring, interfaces, cells
 
 // device descriptor of one problem, read by every kernel
 template <typename TS, typename TP, typename TC>
@@ -1039,7 +1039,7 @@ struct Group {
   uint32_t* owner[KK_COUNT] = {};          // device block-owner tables
   unsigned nblk[KK_COUNT] = {};
   unsigned cap[KK_COUNT] = {};             // allocated owner entries
-  int bs[KK_COUNT] = {256, 256, 256, 256, 256};  // block size of each kind
+  int bs[KK_COUNT] = {256, 256, 256, 256};  // block size of each kind
   double* ctl = nullptr;                   // device [members][2]: fixed step, end time
   std::vector<double> ctl_host;            // values last uploaded
 };
@@ -1172,7 +1172,6 @@ size_t work_items(const Problem& p, int dim, int k) {
   if (dim == 2) {
     switch (k) {
       case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1) + 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
-      case KK_GB: return 0;
       case KK_RECON: return (nx + 2) * (ny + 2);
       case KK_FACE: return n_interfaces(p.ix);
       default: return nx * ny;
@@ -1180,7 +1179,6 @@ size_t work_items(const Problem& p, int dim, int k) {
   }
   switch (k) {
     case KK_GA: return 6;
-    case KK_GB: return 0;
     case KK_RECON: return nx + 2;
     case KK_FACE: return nx + 1;
     default: return nx;
@@ -1808,7 +1806,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
   // time every candidate block size for all kernel classes at once and
   // keep the fastest per class
   static const int cand[3] = {64, 128, 256};
-  static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE};
+  static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE};
   double best_t[GKS_K_COUNT];
   int best_bs[GKS_K_COUNT];
   for (int k = 0; k < GKS_K_COUNT; ++k) {
