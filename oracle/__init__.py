@@ -74,6 +74,9 @@ def lib():
         L.orc_f_assembled.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, _D, _D,
                                       C.c_double, C.c_double, C.c_int, _D, _D, _D, _D]
         L.orc_recon2d_scalar.argtypes = [C.c_double] * 17 + [_D]
+        L.orc_euler_eigvec_2d.argtypes = [C.c_double, _D, C.c_int, _D]
+        L.orc_recon2d_cell.argtypes = [C.c_int, C.c_double, _D, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, _D]
         L.orc_recon1d_scalar.argtypes = [C.c_double] * 8 + [_D]
         L.orc_equilibrium_poly.argtypes = [C.c_int, _D, _D, C.c_double, C.c_double, _D]
         L.orc_dt.argtypes = [C.POINTER(orc_problem), _D]
@@ -197,6 +200,24 @@ def recon2d_scalar(Uc, Ue, Uw, Un, Us, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps
     p = np.zeros(5)
     lib().orc_recon2d_scalar(Uc, Ue, Uw, Un, Us, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps, Cw, _p(p))
     return p
+
+
+def euler_eigvec_2d(gamma, W, ax):
+    """Right eigenvectors (columns) of the 2D Euler flux Jacobian along axis
+    ax (0: x, 1: y) at the conservative state W."""
+    R = np.zeros((4, 4))
+    if lib().orc_euler_eigvec_2d(gamma, _p(_arr(W, 4)), ax, _p(R)):
+        raise ValueError("nonphysical state")
+    return R
+
+
+def recon2d_cell(S, h, k, gamma=1.4, vars=0, eps=1e-6, Cw=1.0):
+    """p2..p6 of the four components of one 2D cell from the stencil values
+    S[13][4] (Uc, Ue, Uw, Un, Us, E+, E-, W+, W-, N+, N-, S+, S-)."""
+    S = np.ascontiguousarray(S, dtype=np.float64).reshape(13, 4)
+    pc = np.zeros((4, 5))
+    rc = lib().orc_recon2d_cell(vars, gamma, _p(S), h, k, eps, Cw, _p(pc))
+    return pc, rc
 
 
 def recon1d_scalar(Uc, Ue, Uw, Fp, Fm, h, eps=1e-6, Cw=1.0):

@@ -867,7 +867,7 @@ void orc_recon1d_scalar(double Uc, double Ue, double Uw, double Fp, double Fm, d
   double a2 = minmod(-ta2_1 + a3 * h / 6.0, ta2_2 - a3 * h / 6.0);
   /* central stencil S3: cell averages of U2 on I_{i-1}, I_i, I_{i+1} */
   double c2 = (Ue - Uw) / (2.0 * h);
-  double c4 = (Ue - 2.0 * Uc + Uw) / (h * h);
+  double c4 = ((Ue + Uw) - 2.0 * Uc) / (h * h);
   /* eq. average with I(U1) = C h^2 and I = sum_l int h^(2l-1) (U^(l))^2 */
   double I1 = C * h * h;
   double I2 = h * h * c2 * c2 + 13.0 / 12.0 * h * h * h * h * c4 * c4;
@@ -878,26 +878,30 @@ void orc_recon1d_scalar(double Uc, double Ue, double Uw, double Fp, double Fm, d
   p[1] = w1 * a3 + w2 * c4;
 }
 
-/* Sec. 3.2.  E+-, W+-: x-interface values at y_j +- sqrt(3)/6 k; N+-, S+-:
- * y-interface values at x_i +- sqrt(3)/6 h.  Output p2..p6. */
-void orc_recon2d_scalar(double Uc, double Ue, double Uw, double Un, double Us, double Ep, double Em, double Wp,
-                        double Wm, double Np, double Nm, double Sp, double Sm, double h, double k, double eps, double C,
-                        double* p) {
+/* Sec. 3.2, eq. over-sys and the limiter, one direction: from the cell
+ * average Uc, the neighbour averages Up (positive side) and Um (negative side)
+ * and the two Gauss-point values on each of the cell's two interfaces across
+ * that direction (Pp, Pm on the positive side, Mp, Mm on the negative side),
+ * the one-sided normal pairs (first, second derivative) of the two stencils,
+ * limited.  h is the cell size along the direction. */
+static void limited_normal_pair(double Uc, double Up, double Um, double Pp, double Pm, double Mp, double Mm, double h,
+                                double* d1, double* d2) {
+  double a4P = 3.0 * ((Uc + Up) - (Pp + Pm)) / (h * h);
+  double ta2P = (Pp + Pm - 2.0 * Uc) / h;
+  double a4M = 3.0 * ((Uc + Um) - (Mp + Mm)) / (h * h);
+  double ta2M = (Mp + Mm - 2.0 * Uc) / h;
+  double a4 = minmod(a4M, a4P);
+  *d2 = a4;
+  *d1 = minmod(-ta2M + a4 * h / 6.0, ta2P - a4 * h / 6.0);
+}
+
+/* Sec. 3.2 after the limiter: the cross derivative of the one-sided stencils
+ * with the limited slopes a2, a3, the central stencil S5 and the nonlinear
+ * weights.  Output p2..p6. */
+static void recon2d_finish(double Uc, double Ue, double Uw, double Un, double Us, double Ep, double Em, double Wp,
+                           double Wm, double Np, double Nm, double Sp, double Sm, double h, double k, double eps,
+                           double C, double a2, double a3, double a4, double a5, double* p) {
   double s3 = sqrt(3.0);
-  /* eq. over-sys, normal pairs of the four one-sided stencils */
-  double a4E = 3.0 * ((Uc + Ue) - (Ep + Em)) / (h * h);
-  double ta2E = (Ep + Em - 2.0 * Uc) / h;
-  double a4W = 3.0 * ((Uc + Uw) - (Wp + Wm)) / (h * h);
-  double ta2W = (Wp + Wm - 2.0 * Uc) / h;
-  double a5N = 3.0 * ((Uc + Un) - (Np + Nm)) / (k * k);
-  double ta3N = (Np + Nm - 2.0 * Uc) / k;
-  double a5S = 3.0 * ((Uc + Us) - (Sp + Sm)) / (k * k);
-  double ta3S = (Sp + Sm - 2.0 * Uc) / k;
-  /* eq. limiter on the normal (a2, a4) and tangential (a3, a5) pairs */
-  double a4 = minmod(a4W, a4E);
-  double a2 = minmod(-ta2W + a4 * h / 6.0, ta2E - a4 * h / 6.0);
-  double a5 = minmod(a5S, a5N);
-  double a3 = minmod(-ta3S + a5 * k / 6.0, ta3N - a5 * k / 6.0);
   /* cross derivative of each one-sided stencil with the limited a2, a3;
    * stencil 1 (NE) as printed, NW / SW / SE by the same least squares */
   double dE = Ep - Em, dW = Wp - Wm, dN = Np - Nm, dS = Sp - Sm;
@@ -906,17 +910,25 @@ void orc_recon2d_scalar(double Uc, double Ue, double Uw, double Un, double Us, d
   cand[1] = s3 * (dN - dW) / (h * k) - (a2 / k - a3 / h); /* NW */
   cand[2] = -s3 * (dS + dW) / (h * k) + (a2 / k + a3 / h); /* SW */
   cand[3] = s3 * (dE - dS) / (h * k) + (a2 / k - a3 / h); /* SE */
-  /* the one with the smallest absolute value (reading: first on ties) */
-  double a6 = cand[0];
-  for (int s = 1; s < 4; ++s)
-    if (fabs(cand[s]) < fabs(a6)) a6 = cand[s];
+  /* the one with the smallest absolute value (reading: when that value is
+   * reached with both signs, zero -- the mean of the tied candidates -- so
+   * that a mirror image of the data gives the mirror image of a6) */
+  double m = fabs(cand[0]), a6 = cand[0];
+  for (int s = 1; s < 4; ++s) {
+    if (fabs(cand[s]) < m) {
+      m = fabs(cand[s]);
+      a6 = cand[s];
+    } else if (fabs(cand[s]) == m && cand[s] != a6) {
+      a6 = 0.0;
+    }
+  }
   /* central stencil S5 (reading of the garbled passage: x pair from the
    * (i+-1, j) averages, y pair from the (i, j+-1) averages, cross term from
    * the eight interface Gauss-point differences) */
   double c2 = (Ue - Uw) / (2.0 * h);
-  double c4 = (Ue - 2.0 * Uc + Uw) / (h * h);
+  double c4 = ((Ue + Uw) - 2.0 * Uc) / (h * h);
   double c3 = (Un - Us) / (2.0 * k);
-  double c5 = (Un - 2.0 * Uc + Us) / (k * k);
+  double c5 = ((Un + Us) - 2.0 * Uc) / (k * k);
   double c6 = s3 * ((dE - dW) + (dN - dS)) / (2.0 * h * k);
   /* weights (reading: I = sum_{|alpha|=1,2} |K|^(|alpha|-1) int (D^alpha U)^2,
    * I(U1) = C |K|) */
@@ -932,6 +944,117 @@ void orc_recon2d_scalar(double Uc, double Ue, double Uw, double Un, double Us, d
   p[2] = w1 * a4 + w2 * c4;
   p[3] = w1 * a5 + w2 * c5;
   p[4] = w1 * a6 + w2 * c6;
+}
+
+/* Sec. 3.2.  E+-, W+-: x-interface values at y_j +- sqrt(3)/6 k; N+-, S+-:
+ * y-interface values at x_i +- sqrt(3)/6 h.  Output p2..p6. */
+void orc_recon2d_scalar(double Uc, double Ue, double Uw, double Un, double Us, double Ep, double Em, double Wp,
+                        double Wm, double Np, double Nm, double Sp, double Sm, double h, double k, double eps, double C,
+                        double* p) {
+  /* eq. over-sys and the limiter on the normal (a2, a4) and tangential
+   * (a3, a5) pairs */
+  double a2, a3, a4, a5;
+  limited_normal_pair(Uc, Ue, Uw, Ep, Em, Wp, Wm, h, &a2, &a4);
+  limited_normal_pair(Uc, Un, Us, Np, Nm, Sp, Sm, k, &a3, &a5);
+  recon2d_finish(Uc, Ue, Uw, Un, Us, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps, C, a2, a3, a4, a5, p);
+}
+
+/* Right eigenvectors of the 2D Euler flux Jacobian along axis ax (0: x,
+ * 1: y) at the conservative state W, as columns: waves un - c, un (entropy),
+ * un (shear: the tangential velocity), un + c, with un, ut the normal and
+ * tangential velocities.  Returns -1 for a nonphysical state. */
+int orc_euler_eigvec_2d(double gamma, const double* W, int ax, double* Rout /* [4][4] */) {
+  double rho = W[0];
+  if (!(rho > 0.0)) return -1;
+  double u = W[1] / rho, v = W[2] / rho, q = 0.5 * (u * u + v * v);
+  double p = (gamma - 1.0) * (W[3] - rho * q);
+  if (!(p > 0.0)) return -1;
+  double c = sqrt(gamma * p / rho), H = (W[3] + p) / rho;
+  double un = ax == 0 ? u : v;
+  /* unit normal (nx, ny) and the tangential direction (-ny, nx) */
+  double nx = ax == 0 ? 1.0 : 0.0, ny = ax == 0 ? 0.0 : 1.0, ut = -ny * u + nx * v;
+  double col[4][4] = {{1.0, u - c * nx, v - c * ny, H - un * c},
+                      {1.0, u, v, q},
+                      {0.0, -ny, nx, ut},
+                      {1.0, u + c * nx, v + c * ny, H + un * c}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Rout[i * 4 + j] = col[j][i];
+  return 0;
+}
+
+/* inverse of a 4x4 matrix by Gaussian elimination, column by column */
+static int invert4(const double* A /* [4][4] */, double* B /* [4][4] */) {
+  for (int c = 0; c < 4; ++c) {
+    double M[4][4], e[4] = {0, 0, 0, 0}, x[4];
+    e[c] = 1.0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) M[i][j] = A[i * 4 + j];
+    if (gauss_solve(4, M, e, x)) return -1;
+    for (int i = 0; i < 4; ++i) B[i * 4 + c] = x[i];
+  }
+  return 0;
+}
+
+/* Sec. 3.2 on one 2D cell, all four components.  S[s][v]: the thirteen
+ * stencil values in the order of orc_recon2d_scalar's arguments (Uc, Ue, Uw,
+ * Un, Us, E+, E-, W+, W-, N+, N-, S+, S-) for conservative component v.
+ * vars = 0: every component reconstructed on its own.  vars = 1 (reading of
+ * the remark on characteristic variables in Sec. 4, carried to 2D): the
+ * limiter of each direction acts in the characteristic variables of that
+ * direction's flux Jacobian at the cell average -- the x-stencil data (Uc,
+ * Ue, Uw, E+-, W+-) are multiplied by L_x = R_x^-1, the normal pair of each
+ * field is formed and limited as for a scalar, and the limited (a2, a4) are
+ * multiplied back by R_x; the y pair (a3, a5) likewise with R_y.  The cross
+ * derivative, the central stencil and the weights stay in conservative
+ * variables.  A nonphysical average gives the constant polynomial (p = 0).
+ * Returns -1 in that case, else 0. */
+int orc_recon2d_cell(int vars, double gamma, const double* S /* [13][4] */, double h, double k, double eps, double C,
+                     double* pc /* [4][5] */) {
+#define SV(s, v) S[(s) * 4 + (v)]
+  double a[4][4]; /* a2, a3, a4, a5 of each conservative component */
+  if (vars == 0) {
+    for (int v = 0; v < 4; ++v) {
+      limited_normal_pair(SV(0, v), SV(1, v), SV(2, v), SV(5, v), SV(6, v), SV(7, v), SV(8, v), h, &a[v][0], &a[v][2]);
+      limited_normal_pair(SV(0, v), SV(3, v), SV(4, v), SV(9, v), SV(10, v), SV(11, v), SV(12, v), k, &a[v][1],
+                          &a[v][3]);
+    }
+  } else {
+    const double Wc[4] = {SV(0, 0), SV(0, 1), SV(0, 2), SV(0, 3)};
+    /* x: stencil entries 0, 1, 2, 5..8; y: 0, 3, 4, 9..12 */
+    const int ent[2][7] = {{0, 1, 2, 5, 6, 7, 8}, {0, 3, 4, 9, 10, 11, 12}};
+    for (int ax = 0; ax < 2; ++ax) {
+      double R[16], L[16];
+      if (orc_euler_eigvec_2d(gamma, Wc, ax, R) || invert4(R, L)) {
+        for (int v = 0; v < 4; ++v)
+          for (int m = 0; m < 5; ++m) pc[v * 5 + m] = 0.0;
+        return -1;
+      }
+      double ch[7][4];
+      for (int e = 0; e < 7; ++e)
+        for (int r = 0; r < 4; ++r) {
+          ch[e][r] = 0.0;
+          for (int v = 0; v < 4; ++v) ch[e][r] += L[r * 4 + v] * SV(ent[ax][e], v);
+        }
+      double d1[4], d2[4];
+      for (int r = 0; r < 4; ++r)
+        limited_normal_pair(ch[0][r], ch[1][r], ch[2][r], ch[3][r], ch[4][r], ch[5][r], ch[6][r], ax == 0 ? h : k,
+                            &d1[r], &d2[r]);
+      for (int v = 0; v < 4; ++v) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int r = 0; r < 4; ++r) {
+          s1 += R[v * 4 + r] * d1[r];
+          s2 += R[v * 4 + r] * d2[r];
+        }
+        a[v][ax] = s1;
+        a[v][2 + ax] = s2;
+      }
+    }
+  }
+  for (int v = 0; v < 4; ++v)
+    recon2d_finish(SV(0, v), SV(1, v), SV(2, v), SV(3, v), SV(4, v), SV(5, v), SV(6, v), SV(7, v), SV(8, v), SV(9, v),
+                   SV(10, v), SV(11, v), SV(12, v), h, k, eps, C, a[v][0], a[v][1], a[v][2], a[v][3], pc + v * 5);
+#undef SV
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1151,12 +1274,25 @@ static void range_add(int dim, double gamma, const double* W, double* lo, double
 /* reconstruction of cell (i, j), all components (conservative variables),
  * with the admissibility reading above */
 static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
-  double pc[4][5];
-  for (int v = 0; v < G->nv; ++v)
-    orc_recon2d_scalar(GW(G, v, j, i), GW(G, v, j, i + 1), GW(G, v, j, i - 1), GW(G, v, j + 1, i),
-                       GW(G, v, j - 1, i), GFX(G, 1, v, j, i + 1), GFX(G, 0, v, j, i + 1), GFX(G, 1, v, j, i),
-                       GFX(G, 0, v, j, i), GFY(G, 1, v, j + 1, i), GFY(G, 0, v, j + 1, i), GFY(G, 1, v, j, i),
-                       GFY(G, 0, v, j, i), h, k, P->weno_eps, P->weno_c, pc[v]);
+  double S[13][4], pc[4][5];
+  for (int v = 0; v < G->nv; ++v) {
+    S[0][v] = GW(G, v, j, i);
+    S[1][v] = GW(G, v, j, i + 1);
+    S[2][v] = GW(G, v, j, i - 1);
+    S[3][v] = GW(G, v, j + 1, i);
+    S[4][v] = GW(G, v, j - 1, i);
+    S[5][v] = GFX(G, 1, v, j, i + 1);
+    S[6][v] = GFX(G, 0, v, j, i + 1);
+    S[7][v] = GFX(G, 1, v, j, i);
+    S[8][v] = GFX(G, 0, v, j, i);
+    S[9][v] = GFY(G, 1, v, j + 1, i);
+    S[10][v] = GFY(G, 0, v, j + 1, i);
+    S[11][v] = GFY(G, 1, v, j, i);
+    S[12][v] = GFY(G, 0, v, j, i);
+  }
+  /* a nonphysical average (characteristic variables) leaves p = 0; the
+   * interfaces of the cell report it */
+  (void)orc_recon2d_cell(P->recon_vars, P->gamma, &S[0][0], h, k, P->weno_eps, P->weno_c, &pc[0][0]);
   /* range of the averages of the cell and its four face neighbours */
   double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
   const int nb[5][2] = {{0, 0}, {0, 1}, {0, -1}, {1, 0}, {-1, 0}};

@@ -47,7 +47,7 @@ typedef struct {
   double tau_eps, tau_c;   /* collision time constants of Sec. 4 */
   double cfl;              /* CFL number for the time step */
   double weno_eps, weno_c; /* small number and I(U1) = C h^2 constant of Sec. 3.1 */
-  int recon_vars;          /* 0 conservative, 1 characteristic (1D) */
+  int recon_vars;          /* 0 conservative, 1 characteristic variables */
   int exact_c;             /* 0: C4..C6 as printed; 1: exact exponential integrals */
   int bc_kind[4];          /* W, E, S, N */
   double bc_state[4][4];   /* primitive (rho, u, v, p): INFLOW state; DMR post-shock state */
@@ -119,6 +119,20 @@ void orc_recon2d_scalar(double Uc, double Ue, double Uw, double Un, double Us,
                         double Ep, double Em, double Wp, double Wm,
                         double Np, double Nm, double Sp, double Sm,
                         double h, double k, double eps, double C, double* p);
+
+/* Right eigenvectors (columns; row-major [4][4]) of the 2D Euler flux
+ * Jacobian along axis ax (0: x, 1: y) at the conservative state W: waves
+ * un - c, un (entropy), un (shear), un + c.  Returns -1 for a nonphysical W. */
+int orc_euler_eigvec_2d(double gamma, const double* W, int ax, double* R);
+
+/* 2D reconstruction of one cell, all four conservative components.
+ * S[13][4]: Uc, Ue, Uw, Un, Us, E+, E-, W+, W-, N+, N-, S+, S- of each
+ * component; vars 0 = conservative, 1 = the limiter of each direction in the
+ * characteristic variables of that direction at the cell average.  pc[4][5]:
+ * p2..p6 of each component.  Returns -1 (and pc = 0) when vars = 1 and the
+ * cell average is nonphysical. */
+int orc_recon2d_cell(int vars, double gamma, const double* S, double h, double k,
+                     double eps, double C, double* pc);
 
 /* 1D reconstruction of one scalar: p = (p2, p4) of Ubar + p2 x + p4 w_x.
  * Fm, Fp = point values at x_{i-1/2}, x_{i+1/2}. */

@@ -9,7 +9,9 @@ Workloads (Sec. 4 of Pan & Xu, arXiv:1412.4489):
   * advection_1d     -- density advection, Sec. 4.1 (Table 1)
   * vortex_2d        -- isentropic vortex, Sec. 4.1 (Table 2), on [0,10]^2
   * sod_1d / blast_1d -- Sec. 4.2
+  * sod_2d           -- Sod's problem of Sec. 4.2 in a 2D channel
   * riemann_2d       -- 2D Riemann problems, Sec. 4.3 (cases 1, 2)
+  * shock_vortex     -- shock-vortex interaction, Sec. 4.4
   * dmr              -- double Mach reflection, Sec. 4.5
   * cavity           -- lid-driven cavity, Sec. 4.8
   * batch            -- many independent vortex / Riemann grids of uneven size
@@ -297,14 +299,14 @@ RIEMANN_CASES = {
 }
 
 
-def riemann_2d(case=1, n=200, t_end=0.2, nx=None, ny=None):
+def riemann_2d(case=1, n=200, t_end=0.2, nx=None, ny=None, recon_vars=0):
     """Sec. 4.3: quadrant Riemann problems on [0, 1]^2, non-reflecting
     (zero-gradient) boundaries."""
     g = 1.4
     nx = n if nx is None else nx
     ny = n if ny is None else ny
     prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=g,
-                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars,
                    bc=[BC("outflow") for _ in range(4)], name=f"riemann{case}_{nx}x{ny}")
     Q = np.stack([cons(g, *s) for s in RIEMANN_CASES[case]])
 
@@ -323,11 +325,84 @@ def riemann_2d(case=1, n=200, t_end=0.2, nx=None, ny=None):
     return prob, State(cell, fx, fy)
 
 
+def sod_2d(n=100, m=4, axis=0, t_end=0.2, recon_vars=1):
+    """Sod's problem of Sec. 4.2 in a 2D channel: the tube along x (axis 0,
+    n x m cells on [0, 1] x [0, m/n]) or along y (axis 1), zero-gradient ends
+    and periodic across the channel."""
+    g = 1.4
+    w = m / n
+    if axis == 0:
+        nx, ny, x1, y1 = n, m, 1.0, w
+        bc = [BC("outflow"), BC("outflow"), BC(), BC()]
+    else:
+        nx, ny, x1, y1 = m, n, w, 1.0
+        bc = [BC(), BC(), BC("outflow"), BC("outflow")]
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=x1, y0=0.0, y1=y1, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars, bc=bc,
+                   name=f"sod2d_{'xy'[axis]}_{n}")
+    left, right = cons(g, 1.0, 0.0, 0.0, 1.0), cons(g, 0.125, 0.0, 0.0, 0.1)
+
+    def state_at(X, Y):
+        s = X if axis == 0 else Y
+        d = 1e-9
+        lo = np.where(s - d < 0.5, 1.0, 0.0)[None]
+        hi = np.where(s + d < 0.5, 1.0, 0.0)[None]
+        wl = 0.5 * (lo + hi)
+        return wl * left.reshape(4, *([1] * X.ndim)) + (1.0 - wl) * right.reshape(4, *([1] * X.ndim))
+
+    cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
+SHOCK_VORTEX_MACH = 1.1
+
+
+def shock_vortex(nx=201, ny=101, t_end=0.8, kappa=0.3, mu=0.204, rc=0.05, recon_vars=1):
+    """Sec. 4.4 shock-vortex interaction on [0, 2] x [0, 1]: a stationary
+    Mach 1.1 normal shock at x = 0.5, upstream state (Ma^2, sqrt(gamma), 0, 1),
+    downstream state from the Rankine-Hugoniot relations, and an isentropic
+    vortex centred at (0.25, 0.5) on the upstream flow (velocity perturbation
+    kappa eta exp(mu (1 - eta^2)) (sin theta, -cos theta), temperature
+    perturbation -(gamma - 1) kappa^2 / (4 mu gamma) exp(2 mu (1 - eta^2)),
+    entropy unchanged, eta = r / rc).  Reflecting top and bottom, the upstream
+    state flowing in on the left, zero-gradient outflow on the right."""
+    g = 1.4
+    M = SHOCK_VORTEX_MACH
+    up = (M * M, math.sqrt(g), 0.0, 1.0)
+    rr = (g + 1.0) * M * M / ((g - 1.0) * M * M + 2.0)
+    pr = 1.0 + 2.0 * g / (g + 1.0) * (M * M - 1.0)
+    down = (up[0] * rr, up[1] / rr, 0.0, up[3] * pr)
+    bc = [BC("inflow", state=up), BC("outflow"), BC("reflect"), BC("reflect")]
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=2.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars, bc=bc,
+                   name=f"shock_vortex_{nx}x{ny}")
+    T0 = up[3] / up[0]
+    S0 = up[3] / up[0] ** g
+
+    def state_at(X, Y):
+        dx, dy = X - 0.25, Y - 0.5
+        r = np.hypot(dx, dy)
+        eta = r / rc
+        e = np.exp(mu * (1.0 - eta * eta))
+        # (sin theta, -cos theta) r = (dy, -dx)
+        amp = np.where(r > 0.0, kappa * eta * e / np.where(r > 0.0, r, 1.0), 0.0)
+        T = T0 - (g - 1.0) * kappa * kappa / (4.0 * mu * g) * e * e
+        rho = (T / S0) ** (1.0 / (g - 1.0))
+        upstream = cons(g, rho, up[1] + amp * dy, amp * -dx, rho * T)
+        downstream = cons(g, *[np.full(X.shape, q) for q in down])
+        d = 1e-9
+        wl = 0.5 * (np.where(X - d < 0.5, 1.0, 0.0) + np.where(X + d < 0.5, 1.0, 0.0))[None]
+        return wl * upstream + (1.0 - wl) * downstream
+
+    cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
 DMR_POST = (8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5)
 DMR_PRE = (1.4, 0.0, 0.0, 1.0)
 
 
-def dmr(nx=1920, ny=480, t_end=0.2):
+def dmr(nx=1920, ny=480, t_end=0.2, recon_vars=0):
     """Sec. 4.5 double Mach reflection on [0, 4] x [0, 1]: a Mach 10 shock
     through (1/6, 0) at 60 degrees; post-shock inflow at the left edge and on
     the bottom for x < 1/6, slip wall beyond, exact shock motion on top,
@@ -336,7 +411,8 @@ def dmr(nx=1920, ny=480, t_end=0.2):
     bc = [BC("inflow", state=DMR_POST), BC("outflow"),
           BC("dmr_bottom", state=DMR_POST), BC("dmr_top", state=DMR_POST, alt=DMR_PRE)]
     prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, gamma=g,
-                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, bc=bc, name=f"dmr_{nx}x{ny}")
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, bc=bc, recon_vars=recon_vars,
+                   name=f"dmr_{nx}x{ny}")
     post, pre = cons(g, *DMR_POST), cons(g, *DMR_PRE)
     s3 = math.sqrt(3.0)
 
