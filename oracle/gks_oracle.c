@@ -910,18 +910,26 @@ static void recon2d_finish(double Uc, double Ue, double Uw, double Un, double Us
   cand[1] = s3 * (dN - dW) / (h * k) - (a2 / k - a3 / h); /* NW */
   cand[2] = -s3 * (dS + dW) / (h * k) + (a2 / k + a3 / h); /* SW */
   cand[3] = s3 * (dE - dS) / (h * k) + (a2 / k - a3 / h); /* SE */
-  /* the one with the smallest absolute value (reading: when that value is
-   * reached with both signs, zero -- the mean of the tied candidates -- so
-   * that a mirror image of the data gives the mirror image of a6) */
-  double m = fabs(cand[0]), a6 = cand[0];
-  for (int s = 1; s < 4; ++s) {
+  /* the one with the smallest absolute value.  Reading for ties: when
+   * candidates of both signs lie within a relative 1e-6 of that smallest
+   * magnitude (a tie up to the rounding of point values held in single
+   * precision), zero -- the mean of the tied candidates -- so that a mirror
+   * image of the data gives the mirror image of a6 */
+  double m = fabs(cand[0]);
+  int best = 0;
+  for (int s = 1; s < 4; ++s)
     if (fabs(cand[s]) < m) {
       m = fabs(cand[s]);
-      a6 = cand[s];
-    } else if (fabs(cand[s]) == m && cand[s] != a6) {
-      a6 = 0.0;
+      best = s;
     }
-  }
+  double band = m * (1.0 + 1e-6);
+  int pos = 0, neg = 0;
+  for (int s = 0; s < 4; ++s)
+    if (fabs(cand[s]) <= band) {
+      if (cand[s] > 0.0) pos = 1;
+      if (cand[s] < 0.0) neg = 1;
+    }
+  double a6 = (pos && neg) ? 0.0 : cand[best];
   /* central stencil S5 (reading of the garbled passage: x pair from the
    * (i+-1, j) averages, y pair from the (i, j+-1) averages, cross term from
    * the eight interface Gauss-point differences) */

@@ -314,3 +314,26 @@ def test_recon2d_characteristic_limits_each_wave_as_a_scalar(oracle, ax, seed):
     cons, _ = oracle.recon2d_cell(S, h, k, gamma=g, vars=0, **weights)
     got_c = cons[:, [0, 2]] if ax == 0 else cons[:, [1, 3]]
     assert np.abs(got_c - expect).max() > 1e-3 * np.abs(expect).max()
+
+
+def test_recon2d_cross_derivative_near_ties(oracle):
+    """The tie of the cross-derivative candidates is taken up to a relative
+    1e-6 of the smallest magnitude (the rounding of point values held in
+    single precision).  A y-uniform jump, its candidates +-3500: perturbing
+    one north Gauss value by 1e-9 moves them by 1.5e-5 (relative 4e-9), and
+    the cross derivative stays zero (only the central polynomial's share,
+    weighted by ~1e-24, is left); perturbed by 1e-6 (relative 4e-6) the
+    smallest candidate wins."""
+    h = k = 0.01
+    d = S3 / 6
+    U = lambda x: 1.0 if x < 0.3 * h else 0.125
+    Uc = 0.8 * 1.0 + 0.2 * 0.125
+    base = [Uc, 0.125, 1.0, Uc, Uc, 0.125, 0.125, 1.0, 1.0, U(d * h), U(-d * h), U(d * h), U(-d * h)]
+    for eps, zero in ((0.0, True), (1e-9, True), (1e-6, False), (1e-3, False)):
+        a = list(base)
+        a[9] += eps
+        p = oracle.recon2d_scalar(*a, h, k, 1e-14, 1e-12)
+        if zero:
+            assert abs(p[4]) < 1e-20, (eps, p[4])
+        else:
+            assert abs(p[4]) > 1e3, (eps, p[4])
