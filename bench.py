@@ -23,7 +23,9 @@ without packed FP32, which this build does not use); `traffic` (HBM bytes) and
 `valu_busy` (rocprofv3's VALUBusy of the interface kernels) come from the
 committed counter record while the kernel sources still match it.  `configs`
 gives the throughput of the other full-size 2D workloads (lid-driven cavity
-512^2, Navier-Stokes; double Mach reflection 1920x480) in both forms.
+512^2, Navier-Stokes; double Mach reflection 1920x480 with the reconstruction
+in conservative and in characteristic variables; the shock-vortex interaction
+of Sec. 4.4 on 801x401, characteristic variables) in both forms.
 `cpu_baseline` times the FP64 oracle on this host for a bounded number of
 steps of the same workload; the same steps on the GPU give the L1 difference
 to the oracle and the conservation drift (largest relative change of the
@@ -157,7 +159,9 @@ def config_rates(steps=20, warmup=3):
     from paper_1412_4489_amd import workloads as W
     out = {}
     for name, mk in (("cavity_512x512_ns_re1000", lambda: W.cavity(512)),
-                     ("double_mach_reflection_1920x480", lambda: W.dmr(1920, 480))):
+                     ("double_mach_reflection_1920x480", lambda: W.dmr(1920, 480)),
+                     ("double_mach_reflection_1920x480_characteristic", lambda: W.dmr(1920, 480, recon_vars=1)),
+                     ("shock_vortex_801x401_characteristic", lambda: W.shock_vortex(801, 401))):
         prob, st = mk()
         out[name] = {}
         for pname, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):

@@ -10,8 +10,10 @@
  *   3. compact reconstruction of every cell from its average, its face
  *      neighbours' averages and the tracked interface Gauss-point values
  *      (Sec. 3.1, 3.2: one-sided stencils, limiter eq. limiter, central
- *      stencil, nonlinear weights eq. average; in 1D optionally in
- *      characteristic variables, Sec. 4);
+ *      stencil, nonlinear weights eq. average; optionally with the limiter
+ *      in characteristic variables, Sec. 4: in 1D the whole reconstruction,
+ *      in 2D the limited normal pair of each direction in the eigenvector
+ *      basis of that direction's flux Jacobian at the cell average);
  *   4. at every interface: the equilibrium state U0 (eq. compatibility2), its
  *      quadratic (Sec. 3.3), the collision time (Sec. 4), the expansion
  *      coefficients (system after eq. dis3), the time- and interface-integrated
@@ -21,8 +23,8 @@
  *
  * A handle advances any number of independent problems (1D and 2D, both
  * precisions, uneven sizes) together: every step is one launch per phase for
- * all problems of a dimension and precision, replayed from one captured HIP
- * graph.  Where the paper leaves the reconstruction's robustness open, a
+ * all problems of a dimension, precision and (2D) reconstruction kind,
+ * replayed from one captured HIP graph.  Where the paper leaves the reconstruction's robustness open, a
  * reconstructed cell polynomial whose density or pressure at an interface
  * centre is nonpositive or more than a factor two outside the range of the
  * neighbouring averages is replaced by the constant average for the step.
@@ -97,7 +99,7 @@ typedef struct {
   double tau_eps, tau_c;
   double cfl;               /* dt = cfl * min over cells of min(dx/(|u|+c+2nu/dx), dy/(|v|+c+2nu/dy)) */
   double weno_eps, weno_c;  /* small number and C of I(U1) = C h^2 in the weights */
-  int32_t recon_vars;       /* 0: conservative variables (the only kind in 2D) */
+  int32_t recon_vars;       /* 0: conservative variables; 1: characteristic (see step 3) */
   int32_t precision;        /* GKS_FP64 or GKS_FP32_MIXED */
   gks_bc bc[4];             /* W, E, S, N */
   double t0;                /* time of the initial state (restart from a fetched state) */

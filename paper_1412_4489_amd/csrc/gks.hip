@@ -144,7 +144,7 @@ struct Prob {
   Phys P;
   BCDev bc[4];
   Rec<TC> R;
-  int recon_vars;            // 1D: 0 conservative, 1 characteristic variables
+  int recon_vars;            // 0 conservative, 1 characteristic variables
   unsigned first[KK_COUNT];  // first logical block of the problem in each kind's launch
 };
 
@@ -498,8 +498,9 @@ __device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* sl
 // reconstruction
 // ---------------------------------------------------------------------------
 
-// 2D: cells -1..nx x -1..ny except the four corners
-template <typename TS, typename TP, typename TC>
+// 2D: cells -1..nx x -1..ny except the four corners; kChar: the limiter of
+// each direction in that direction's characteristic variables
+template <typename TS, typename TP, typename TC, bool kChar>
 __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   int id;
   const Prob<TS, TP, TC>& Q = locate(a, KK_RECON, id);
@@ -522,13 +523,47 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   }
   double p[4][5], Wc[4];
   const ReconDiv D(h, k);
+  if constexpr (!kChar) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    Wc[v] = Wn[0][v];
-    recon_2d(Wc[v], Wn[1][v], Wn[2][v], Wn[3][v], Wn[4][v], (double)g.FX[x.fx(1, v, j, i + 1)],
-             (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)],
-             (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)], (double)g.FY[x.fy(1, v, j, i)],
-             (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, D, p[v]);
+    for (int v = 0; v < 4; ++v) {
+      Wc[v] = Wn[0][v];
+      recon_2d(Wc[v], Wn[1][v], Wn[2][v], Wn[3][v], Wn[4][v], (double)g.FX[x.fx(1, v, j, i + 1)],
+               (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)],
+               (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)],
+               (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, D, p[v]);
+    }
+  } else {
+    double S[13][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wc[v] = Wn[0][v];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) S[q][v] = Wn[q][v];
+      S[5][v] = (double)g.FX[x.fx(1, v, j, i + 1)];
+      S[6][v] = (double)g.FX[x.fx(0, v, j, i + 1)];
+      S[7][v] = (double)g.FX[x.fx(1, v, j, i)];
+      S[8][v] = (double)g.FX[x.fx(0, v, j, i)];
+      S[9][v] = (double)g.FY[x.fy(1, v, j + 1, i)];
+      S[10][v] = (double)g.FY[x.fy(0, v, j + 1, i)];
+      S[11][v] = (double)g.FY[x.fy(1, v, j, i)];
+      S[12][v] = (double)g.FY[x.fy(0, v, j, i)];
+    }
+    double lim[4][4];
+    if (recon_pair_characteristic<true>(gamma, S, h, D.h, D.hh, D.six, lim) &&
+        recon_pair_characteristic<false>(gamma, S, k, D.k, D.kk, D.six, lim)) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        recon_finish(S[0][v], S[1][v], S[2][v], S[3][v], S[4][v], S[5][v], S[6][v], S[7][v], S[8][v], S[9][v],
+                     S[10][v], S[11][v], S[12][v], h, k, eps, Cw, D, lim[v][0], lim[v][1], lim[v][2], lim[v][3],
+                     p[v]);
+    } else {
+      // a nonphysical average: the constant polynomial (the interfaces and
+      // the update report the state)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int m = 0; m < 5; ++m) p[v][m] = 0.0;
+    }
   }
   // an inadmissible polynomial is replaced by the constant cell average for
   // this step
@@ -1034,6 +1069,7 @@ struct Problem {
 struct Group {
   int dim = 2;
   bool mixed = false;
+  bool chr = false;  // 2D reconstruction in characteristic variables
   std::vector<int> members;
   void* dprobs = nullptr;                  // device Prob<...>[members]
   uint32_t* owner[KK_COUNT] = {};          // device block-owner tables
@@ -1111,8 +1147,7 @@ std::string validate(const gks_problem& p) {
   if (!(p.cfl > 0.0) || !(p.weno_eps > 0.0) || !(p.weno_c >= 0.0)) return "cfl, weno_eps must be > 0";
   if (!(p.tau_eps >= 0.0) || !(p.tau_c >= 0.0)) return "tau constants must be >= 0";
   if (!std::isfinite(p.t0)) return "t0 must be finite";
-  if (p.dim == 2 && p.recon_vars != 0) return "2D reconstruction is in conservative variables (recon_vars = 0)";
-  if (p.dim == 1 && p.recon_vars != 0 && p.recon_vars != 1) return "recon_vars must be 0 or 1";
+  if (p.recon_vars != 0 && p.recon_vars != 1) return "recon_vars must be 0 or 1";
   if (p.precision != GKS_FP64 && p.precision != GKS_FP32_MIXED) return "unknown precision";
   const int nsides = p.dim == 2 ? 4 : 2;
   for (int s = 0; s < nsides; ++s) {
@@ -1302,8 +1337,10 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   }
   record_end(h, st, GKS_K_GHOST);  // includes the time step
   record_begin(h, st);
-  if (G.dim == 2)
-    k_recon_2d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  if (G.dim == 2 && G.chr)
+    k_recon_2d<TS, TP, TC, true><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  else if (G.dim == 2)
+    k_recon_2d<TS, TP, TC, false><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
   else
     k_recon_1d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
   record_end(h, st, GKS_K_RECON);
@@ -1580,17 +1617,21 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     }
     if (!up) return init_fail(GKS_EDEVICE, "upload failed");
   }
-  // groups: problems of one dimension and precision, in problem order
+  // groups: problems of one dimension, precision and (2D) reconstruction
+  // variables, in problem order (1D chooses the variables per problem in the
+  // kernel)
   for (int n = 0; n < n_problems; ++n) {
     const Problem& p = h->probs[n];
     Group* G = nullptr;
+    const bool chr = p.spec.dim == 2 && p.spec.recon_vars == 1;
     for (Group& g : h->groups)
-      if (g.dim == p.spec.dim && g.mixed == p.mixed) G = &g;
+      if (g.dim == p.spec.dim && g.mixed == p.mixed && g.chr == chr) G = &g;
     if (!G) {
       h->groups.emplace_back();
       G = &h->groups.back();
       G->dim = p.spec.dim;
       G->mixed = p.mixed;
+      G->chr = chr;
     }
     G->members.push_back(n);
   }

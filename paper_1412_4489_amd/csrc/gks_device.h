@@ -659,42 +659,64 @@ struct ReconDiv {
         h2(divisor(2.0 * h_)), k2(divisor(2.0 * k_)), hk2(divisor(2.0 * (h_ * k_))), six(divisor(6.0)) {}
 };
 
-// 2D: c = cell average; e, w, n, s = face-neighbour averages; E+-, W+-, N+-, S+-
-// = Gauss-point values on the four interfaces.  p = (p2..p6).
-// The quantities that decide branches (the one-sided estimates, the minmod
-// arguments and the cross-derivative candidates) are formed in the order of
-// their printed formulas and without FMA contraction, so that a tie or a sign
-// is decided from the same rounded values as in a plain evaluation (every
-// quotient is the correctly rounded one, see div_by).
-__device__ __forceinline__ void recon_2d(double c, double e, double w, double n, double s, double Ep, double Em,
-                                         double Wp, double Wm, double Np, double Nm, double Sp, double Sm, double h,
-                                         double k, double eps, double Cw, const ReconDiv& D, double* p) {
+// 2D reconstruction (Sec. 3.2).  Stencil values of one component: c = cell
+// average; e, w, n, s = face-neighbour averages; E+-, W+-, N+-, S+- =
+// Gauss-point values on the four interfaces.  The quantities that decide
+// branches (the one-sided estimates, the minmod arguments and the
+// cross-derivative candidates) are formed in the order of their printed
+// formulas and without FMA contraction, so that a tie or a sign is decided
+// from the same rounded values as in a plain evaluation (every quotient is the
+// correctly rounded one, see div_by).
+
+// eq. over-sys and the limiter along one direction: the normal pair (first,
+// second derivative) of the one-sided stencils on the positive side (up, the
+// neighbour average; Pp, Pm, the Gauss-point values of the interface between)
+// and on the negative side (um; Mp, Mm), limited.  hd = cell size along the
+// direction.
+__device__ __forceinline__ void recon_pair(double c, double up, double um, double Pp, double Pm, double Mp, double Mm,
+                                           double hd, const Divisor& Dh, const Divisor& Dhh, const Divisor& six,
+                                           double& d1, double& d2) {
 #pragma clang fp contract(off)
-  // eq. over-sys: normal (x) and tangential (y) pairs of the one-sided stencils
-  const double cxE = div_by(3.0 * ((c + e) - (Ep + Em)), D.hh), sxE = div_by(Ep + Em - 2.0 * c, D.h);
-  const double cxW = div_by(3.0 * ((c + w) - (Wp + Wm)), D.hh), sxW = div_by(Wp + Wm - 2.0 * c, D.h);
-  const double cyN = div_by(3.0 * ((c + n) - (Np + Nm)), D.kk), syN = div_by(Np + Nm - 2.0 * c, D.k);
-  const double cyS = div_by(3.0 * ((c + s) - (Sp + Sm)), D.kk), syS = div_by(Sp + Sm - 2.0 * c, D.k);
-  // eq. limiter on each pair
-  const double a4 = mm2(cxW, cxE);
-  const double a2 = mm2(-sxW + div_by(a4 * h, D.six), sxE - div_by(a4 * h, D.six));
-  const double a5 = mm2(cyS, cyN);
-  const double a3 = mm2(-syS + div_by(a5 * k, D.six), syN - div_by(a5 * k, D.six));
+  const double cP = div_by(3.0 * ((c + up) - (Pp + Pm)), Dhh), sP = div_by(Pp + Pm - 2.0 * c, Dh);
+  const double cM = div_by(3.0 * ((c + um) - (Mp + Mm)), Dhh), sM = div_by(Mp + Mm - 2.0 * c, Dh);
+  d2 = mm2(cM, cP);
+  d1 = mm2(-sM + div_by(d2 * hd, six), sP - div_by(d2 * hd, six));
+}
+
+// the rest of Sec. 3.2 once the pairs a2, a4 (x) and a3, a5 (y) are limited:
+// the cross term, the central stencil and the nonlinear weights.  p = p2..p6.
+__device__ __forceinline__ void recon_finish(double c, double e, double w, double n, double s, double Ep, double Em,
+                                             double Wp, double Wm, double Np, double Nm, double Sp, double Sm,
+                                             double h, double k, double eps, double Cw, const ReconDiv& D, double a2,
+                                             double a3, double a4, double a5, double* p) {
+#pragma clang fp contract(off)
   // cross term of the stencils NE, NW, SW, SE with the limited slopes; the one
-  // of smallest magnitude (the earlier one on an exact tie)
+  // of smallest magnitude, zero when candidates of both signs lie within a
+  // relative 1e-6 of that magnitude (a tie up to the rounding of point values
+  // held in single precision; mirrored data then give the mirrored term)
   const double s3 = 1.7320508075688772;  // sqrt(3)
   const double dE = Ep - Em, dW = Wp - Wm, dN = Np - Nm, dS = Sp - Sm;
   const double ak = div_by(a2, D.k), ah = div_by(a3, D.h);
-  double a6 = div_by(s3 * (dE + dN), D.hk) - (ak + ah);
-  double cand = div_by(s3 * (dN - dW), D.hk) - (ak - ah);
-  if (fabs(cand) < fabs(a6)) a6 = cand;
-  cand = div_by(-s3 * (dS + dW), D.hk) + (ak + ah);
-  if (fabs(cand) < fabs(a6)) a6 = cand;
-  cand = div_by(s3 * (dE - dS), D.hk) + (ak - ah);
-  if (fabs(cand) < fabs(a6)) a6 = cand;
+  const double cand[4] = {div_by(s3 * (dE + dN), D.hk) - (ak + ah), div_by(s3 * (dN - dW), D.hk) - (ak - ah),
+                          div_by(-s3 * (dS + dW), D.hk) + (ak + ah), div_by(s3 * (dE - dS), D.hk) + (ak - ah)};
+  double a6 = cand[0], m6 = fabs(cand[0]);
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (fabs(cand[q]) < m6) {
+      m6 = fabs(cand[q]);
+      a6 = cand[q];
+    }
+  const double band = m6 * (1.0 + 1e-6);
+  bool pos = false, neg = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    pos = pos || (fabs(cand[q]) <= band && cand[q] > 0.0);
+    neg = neg || (fabs(cand[q]) <= band && cand[q] < 0.0);
+  }
+  if (pos && neg) a6 = 0.0;
   // central stencil
-  const double c2 = div_by(e - w, D.h2), c4 = div_by(e - 2.0 * c + w, D.hh);
-  const double c3 = div_by(n - s, D.k2), c5 = div_by(n - 2.0 * c + s, D.kk);
+  const double c2 = div_by(e - w, D.h2), c4 = div_by((e + w) - 2.0 * c, D.hh);
+  const double c3 = div_by(n - s, D.k2), c5 = div_by((n + s) - 2.0 * c, D.kk);
   const double c6 = div_by(s3 * ((dE - dW) + (dN - dS)), D.hk2);
   // nonlinear weights, I(U1) = C |cell|, I(U2) from the derivatives of U2
   const double hk = h * k;
@@ -710,6 +732,91 @@ __device__ __forceinline__ void recon_2d(double c, double e, double w, double n,
   p[2] = w1 * a4 + w2 * c4;
   p[3] = w1 * a5 + w2 * c5;
   p[4] = w1 * a6 + w2 * c6;
+}
+
+// one component in conservative variables
+__device__ __forceinline__ void recon_2d(double c, double e, double w, double n, double s, double Ep, double Em,
+                                         double Wp, double Wm, double Np, double Nm, double Sp, double Sm, double h,
+                                         double k, double eps, double Cw, const ReconDiv& D, double* p) {
+  double a2, a3, a4, a5;
+  recon_pair(c, e, w, Ep, Em, Wp, Wm, h, D.h, D.hh, D.six, a2, a4);
+  recon_pair(c, n, s, Np, Nm, Sp, Sm, k, D.k, D.kk, D.six, a3, a5);
+  recon_finish(c, e, w, n, s, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps, Cw, D, a2, a3, a4, a5, p);
+}
+
+// Eigenvectors of the 2D Euler flux Jacobian along x (kX) or y at the
+// conservative state W: columns of R for the waves un - c, un (entropy),
+// un (shear), un + c; L = R^-1 in closed form (b1 = (gamma - 1) / c^2,
+// b2 = b1 q, q = |u|^2 / 2).  False for a nonphysical state.
+template <bool kX>
+__device__ __forceinline__ bool euler_eigen_2d(double gamma, const double* W, double (&R)[4][4],
+                                               double (&L)[4][4]) {
+  const double rho = W[0];
+  if (!(rho > 0.0)) return false;
+  const double u = W[1] / rho, v = W[2] / rho, q = 0.5 * (u * u + v * v);
+  const double p = (gamma - 1.0) * (W[3] - rho * q);
+  if (!(p > 0.0)) return false;
+  const double c = sqrt(gamma * p / rho), H = (W[3] + p) / rho, ic = 1.0 / c;
+  const double un = kX ? u : v, ut = kX ? v : u;  // normal and tangential velocity
+  const int in = kX ? 1 : 2, it = kX ? 2 : 1;      // their momentum components
+  const double b1 = (gamma - 1.0) / (c * c), b2 = b1 * q;
+  // R: column 0 = (1, u - c n, H - un c), 1 = (1, u, q), 2 = tangential unit
+  // vector with ut, 3 = (1, u + c n, H + un c)
+  R[0][0] = 1.0, R[0][1] = 1.0, R[0][2] = 0.0, R[0][3] = 1.0;
+  R[in][0] = un - c, R[in][1] = un, R[in][2] = 0.0, R[in][3] = un + c;
+  R[it][0] = ut, R[it][1] = ut, R[it][2] = 1.0, R[it][3] = ut;
+  R[3][0] = H - un * c, R[3][1] = q, R[3][2] = ut, R[3][3] = H + un * c;
+  // L rows: 0.5 (b2 + un/c, -b1 u - n/c, b1); (1 - b2, b1 u, -b1);
+  // (-ut, tangential unit vector); 0.5 (b2 - un/c, -b1 u + n/c, b1)
+  L[0][0] = 0.5 * (b2 + un * ic), L[0][in] = -0.5 * (b1 * un + ic), L[0][it] = -0.5 * (b1 * ut), L[0][3] = 0.5 * b1;
+  L[1][0] = 1.0 - b2, L[1][in] = b1 * un, L[1][it] = b1 * ut, L[1][3] = -b1;
+  L[2][0] = -ut, L[2][in] = 0.0, L[2][it] = 1.0, L[2][3] = 0.0;
+  L[3][0] = 0.5 * (b2 - un * ic), L[3][in] = -0.5 * (b1 * un - ic), L[3][it] = -0.5 * (b1 * ut), L[3][3] = 0.5 * b1;
+  return true;
+}
+
+// The limited pair of one direction in the characteristic variables of that
+// direction at the cell average S[0] (the remark on characteristic variables
+// in Sec. 4, carried to 2D direction by direction): the direction's stencil
+// data are multiplied by L, each field's pair is limited as a scalar, and the
+// limited pairs are multiplied back by R.  S[13][4] in the order c, e, w, n,
+// s, E+, E-, W+, W-, N+, N-, S+, S-.  a[v] = (a2, a3, a4, a5) of component v;
+// this direction's two entries are written.  False for a nonphysical average.
+template <bool kX>
+__device__ __forceinline__ bool recon_pair_characteristic(double gamma, const double (&S)[13][4], double hd,
+                                                          const Divisor& Dh, const Divisor& Dhh, const Divisor& six,
+                                                          double (&a)[4][4]) {
+#pragma clang fp contract(off)
+  double R[4][4], L[4][4];
+  if (!euler_eigen_2d<kX>(gamma, S[0], R, L)) return false;
+  constexpr int e0 = 0, e1 = kX ? 1 : 3, e2 = kX ? 2 : 4, e3 = kX ? 5 : 9;  // c, up, um, first Gauss value
+  const int ent[7] = {e0, e1, e2, e3, e3 + 1, e3 + 2, e3 + 3};
+  double ch[7][4];
+#pragma unroll
+  for (int e = 0; e < 7; ++e)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc += L[r][v] * S[ent[e]][v];
+      ch[e][r] = acc;
+    }
+  double d1[4], d2[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    recon_pair(ch[0][r], ch[1][r], ch[2][r], ch[3][r], ch[4][r], ch[5][r], ch[6][r], hd, Dh, Dhh, six, d1[r], d2[r]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s1 += R[v][r] * d1[r];
+      s2 += R[v][r] * d2[r];
+    }
+    a[v][kX ? 0 : 1] = s1;
+    a[v][kX ? 2 : 3] = s2;
+  }
+  return true;
 }
 
 // Admissibility of a reconstructed cell polynomial (a robustness reading; the
@@ -792,7 +899,7 @@ __device__ __forceinline__ void recon_1d(double c, double e, double w, double Fp
   const double a3 = mm2(a3W, a3E);
   const double a2 = mm2(-s2W + a3 * h / 6.0, s2E - a3 * h / 6.0);
   // central stencil: averages of U2 over the three cells
-  const double c2 = (e - w) / (2.0 * h), c4 = (e - 2.0 * c + w) / (h * h);
+  const double c2 = (e - w) / (2.0 * h), c4 = ((e + w) - 2.0 * c) / (h * h);
   // weights: I(U1) = C h^2, I(U2) = h^2 c2^2 + 13/12 h^4 c4^2
   const double I1 = Cw * h * h;
   const double I2 = h * h * c2 * c2 + 13.0 / 12.0 * h * h * h * h * c4 * c4;

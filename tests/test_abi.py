@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
     (lambda p: setattr(p, "nx", 1), "nx"),
     (lambda p: setattr(p, "cfl", -1.0), "cfl"),
     (lambda p: setattr(p.bc[0], "kind", "outflow"), "periodic"),
-    (lambda p: setattr(p, "recon_vars", 1), "conservative"),
+    (lambda p: setattr(p, "recon_vars", 2), "recon_vars"),
     (lambda p: setattr(p, "dim", 3), "dim"),
 ])
 def test_init_rejects_invalid_problems(mutate, why):
