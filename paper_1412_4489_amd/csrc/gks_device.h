@@ -707,13 +707,14 @@ __device__ __forceinline__ void recon_finish(double c, double e, double w, doubl
       a6 = cand[q];
     }
   const double band = m6 * (1.0 + 1e-6);
-  bool pos = false, neg = false;
+  int pos = 0, neg = 0;  // bitwise logic: no branches
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    pos = pos || (fabs(cand[q]) <= band && cand[q] > 0.0);
-    neg = neg || (fabs(cand[q]) <= band && cand[q] < 0.0);
+    const int near = fabs(cand[q]) <= band;
+    pos |= near & (cand[q] > 0.0);
+    neg |= near & (cand[q] < 0.0);
   }
-  if (pos && neg) a6 = 0.0;
+  a6 = (pos & neg) ? 0.0 : a6;
   // central stencil
   const double c2 = div_by(e - w, D.h2), c4 = div_by((e + w) - 2.0 * c, D.hh);
   const double c3 = div_by(n - s, D.k2), c5 = div_by((n + s) - 2.0 * c, D.kk);
