@@ -13,7 +13,9 @@ Workloads (Sec. 4 of Pan & Xu, arXiv:1412.4489):
   * riemann_2d       -- 2D Riemann problems, Sec. 4.3 (cases 1, 2)
   * shock_vortex     -- shock-vortex interaction, Sec. 4.4
   * dmr              -- double Mach reflection, Sec. 4.5
+  * viscous_shock_tube -- Sec. 4.7 (no-slip adiabatic walls, symmetry line)
   * cavity           -- lid-driven cavity, Sec. 4.8
+  * shear_wave / entropy_wave -- linearised Navier-Stokes decay tests
   * batch            -- many independent vortex / Riemann grids of uneven size
 
 Initial point values are the exact initial data at the interface Gauss points
@@ -441,6 +443,62 @@ def cavity(n=512, re=1000.0, mach=0.15, prandtl=0.72, gamma=5.0 / 3.0, lid_trans
     cell[:] = cons(g, 1.0, 0.0, 0.0, 1.0)[:, None, None]
     fx = np.broadcast_to(cell[:, :, :1], (4, n, n + 1))[None].repeat(2, axis=0).copy()
     fy = np.broadcast_to(cell[:, :1, :], (4, n + 1, n))[None].repeat(2, axis=0).copy()
+    return prob, State(cell, fx, fy)
+
+
+def viscous_shock_tube(nx=300, ny=150, re=200.0, t_end=1.0, prandtl=0.73, recon_vars=1):
+    """Sec. 4.7 viscous shock tube on [0, 1] x [0, 0.5]: gas at rest,
+    (rho, p) = (120, 120/gamma) for x < 0.5 and (1.2, 1.2/gamma) beyond,
+    gamma = 1.4; no-slip adiabatic walls on the left, right and bottom, the
+    symmetry line (a slip wall) on top; constant mu = 1/Re, Pr = 0.73."""
+    g = 1.4
+    wall = BC("noslip_adia", wall=(0.0, 0.0, 0.0))
+    bc = [wall, BC("noslip_adia", wall=(0.0, 0.0, 0.0)), BC("noslip_adia", wall=(0.0, 0.0, 0.0)),
+          BC("reflect")]
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=0.5, gamma=g, viscous=True,
+                   mu=1.0 / re, prandtl=prandtl, tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end,
+                   recon_vars=recon_vars, bc=bc, name=f"viscous_shock_tube_{nx}x{ny}_re{int(re)}")
+    left, right = cons(g, 120.0, 0.0, 0.0, 120.0 / g), cons(g, 1.2, 0.0, 0.0, 1.2 / g)
+
+    def state_at(X, Y):
+        d = 1e-9
+        wl = 0.5 * (np.where(X - d < 0.5, 1.0, 0.0) + np.where(X + d < 0.5, 1.0, 0.0))[None]
+        return wl * left.reshape(4, *([1] * X.ndim)) + (1.0 - wl) * right.reshape(4, *([1] * X.ndim))
+
+    cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
+def shear_wave(n=32, m=4, amp=1e-3, mu=0.01, prandtl=1.0, gamma=1.4):
+    """Linearised Navier-Stokes test: rho = p = 1 at rest except the
+    transverse velocity v = amp sin(2 pi x) on the periodic [0, 1] x [0, m/n];
+    its amplitude decays as exp(-(mu / rho) (2 pi)^2 t)."""
+    prob = Problem(dim=2, nx=n, ny=m, x0=0.0, x1=1.0, y0=0.0, y1=m / n, gamma=gamma, viscous=True,
+                   mu=mu, prandtl=prandtl, tau_eps=0.0, tau_c=1.0, cfl=0.2, name=f"shear_wave_{n}")
+
+    def fun(X, Y):
+        return cons(gamma, np.ones_like(X), np.zeros_like(X), amp * np.sin(2 * np.pi * X), np.ones_like(X))
+
+    cell = _cell_average_2d(fun, prob, nq=6)
+    fx, fy = _face_values_2d(fun, prob)
+    return prob, State(cell, fx, fy)
+
+
+def entropy_wave(n=32, m=4, amp=1e-3, mu=0.01, prandtl=0.72, gamma=1.4):
+    """Linearised Navier-Stokes test: at rest under the uniform pressure 1,
+    temperature T = 1 + amp sin(2 pi x) (rho = 1/T) on the periodic
+    [0, 1] x [0, m/n]; heat conduction makes the temperature amplitude decay
+    as exp(-kappa (2 pi)^2 t / (rho c_p)) with kappa = c_p mu / Pr, i.e. at
+    the rate mu (2 pi)^2 / (rho Pr)."""
+    prob = Problem(dim=2, nx=n, ny=m, x0=0.0, x1=1.0, y0=0.0, y1=m / n, gamma=gamma, viscous=True,
+                   mu=mu, prandtl=prandtl, tau_eps=0.0, tau_c=1.0, cfl=0.2, name=f"entropy_wave_{n}")
+
+    def fun(X, Y):
+        T = 1.0 + amp * np.sin(2 * np.pi * X)
+        return cons(gamma, 1.0 / T, np.zeros_like(X), np.zeros_like(X), np.ones_like(X))
+
+    cell = _cell_average_2d(fun, prob, nq=6)
+    fx, fy = _face_values_2d(fun, prob)
     return prob, State(cell, fx, fy)
 
 
