@@ -42,6 +42,7 @@ CASES = {
     "riemann_char": lambda: W.riemann_2d(2, n=13, recon_vars=1),
     "sod_2d_char_y": lambda: W.sod_2d(20, 3, axis=1),
     "shock_vortex_char": lambda: W.shock_vortex(40, 20),
+    "viscous_shock_tube": lambda: W.viscous_shock_tube(16, 8, re=200.0),
     "ns_smooth": lambda: W.smooth_periodic_2d(nx=12, ny=14, seed=3, viscous=True, mu=2e-3, prandtl=0.72,
                                               tau_eps=0.0),
     "dmr": lambda: W.dmr(32, 8),
