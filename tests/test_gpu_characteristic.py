@@ -216,9 +216,10 @@ def test_stationary_shock_on_the_gpu(G):
         assert abs(xs - 0.5) < 0.25 * h, (p, xs)
 
 
-def _end_state_parity(G, oracle, prob, st, prec, t_end, label):
+def _end_state_parity(G, oracle, prob, st, prec, t_end, label, tol32=(1e-6, 1e-5)):
     """Run to t_end on the GPU; then one more step from the final state, on
-    the GPU and in the oracle, compared element by element."""
+    the GPU and in the oracle, compared element by element (FP32-mixed:
+    tol32 = bounds for the cells and the point values)."""
     p = G.GKS_FP64 if prec == "fp64" else G.GKS_FP32_MIXED
     print(f"{label} {prec}: to t = {t_end}", flush=True)
     nmax = _steps_for(prob, st, t_end)
@@ -233,10 +234,10 @@ def _end_state_parity(G, oracle, prob, st, prec, t_end, label):
     with G.Solver(prob, got, p, t0=t) as S:
         S.step(1, dt=dt)
         nxt, _, _ = S.fetch()
-    tol = 1e-11 if prec == "fp64" else 1e-6
-    assert _rel(nxt.cell, ref.cell) < tol, label
-    assert _rel(nxt.fx, ref.fx) < 10 * tol, label
-    assert _rel(nxt.fy, ref.fy) < 10 * tol, label
+    ctol, ptol = (1e-11, 1e-10) if prec == "fp64" else tol32
+    assert _rel(nxt.cell, ref.cell) < ctol, label
+    assert _rel(nxt.fx, ref.fx) < ptol, label
+    assert _rel(nxt.fy, ref.fy) < ptol, label
     return got, n
 
 
@@ -273,3 +274,34 @@ def test_shock_vortex_at_the_paper_resolutions(G, oracle, shape):
         row = got.cell[0, prob.ny // 2]
         print(f"{prob.name} {prec}: {steps} steps, centre-line density in [{row.min():.4f}, {row.max():.4f}]",
               flush=True)
+
+
+def _shock_x(row, xc, hi=8.0, lo=1.4):
+    """first crossing of the mid density between the post- and pre-shock
+    states along a row (linear interpolation)"""
+    mid = 0.5 * (hi + lo)
+    k = int(np.argmax(row < mid))
+    return xc[k - 1] + (row[k - 1] - mid) / (row[k - 1] - row[k]) * (xc[k] - xc[k - 1])
+
+
+@pytest.mark.parametrize("shape", [(400, 100), (800, 200)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_dmr_at_the_paper_resolutions(G, oracle, shape, prec):
+    """Sec. 4.5 on the paper's 400 x 100 and 800 x 200 cells, characteristic
+    variables, to t = 0.2: every state physical, the oracle's step of the
+    final grid matched, and on three upper rows the incident shock's
+    mid-density crossing within two cells of its exact line
+    x = 1/6 + (y + 20 t) / sqrt(3)."""
+    prob, st = W.dmr(*shape, recon_vars=1)
+    # FP32-mixed at the Mach 10 shock: 5e-6 of the cells, 1e-3 of the point
+    # values (the bounds of the conservative form's full-size test)
+    got, steps = _end_state_parity(G, oracle, prob, st, prec, 0.2, prob.name, tol32=(5e-6, 1e-3))
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
+    worst = 0.0
+    for j in (prob.ny // 2, 3 * prob.ny // 4, prob.ny - 1):
+        y = prob.y0 + (j + 0.5) * prob.dy
+        exact = 1.0 / 6.0 + (y + 4.0) / np.sqrt(3.0)
+        worst = max(worst, abs(_shock_x(got.cell[0, j], xc) - exact) / prob.dx)
+    print(f"{prob.name} {prec}: {steps} steps, incident shock within {worst:.2f} cells of the exact line",
+          flush=True)
+    assert worst < 2.0
