@@ -168,8 +168,10 @@ int gks_state_extent(const gks_problem* prob, int64_t* cell_elems, int64_t* face
  * launches: nsteps replays of the step graph, captured at the first call).  dt_fixed: NULL to take each step from the CFL condition on the
  * device, else dt_fixed[p] for every step of problem p.  t_end: NULL for no
  * limit, else the last step of problem p is shortened to end at t_end[p] and
- * later steps leave it unchanged.  Arguments are validated before anything
- * is enqueued (GKS_EINVAL). */
+ * later steps leave it unchanged.  Once a step has produced a nonphysical
+ * state in problem p (see gks_fetch), later steps leave p unchanged too, so
+ * that gks_fetch returns the state of the failing step.  Arguments are
+ * validated before anything is enqueued (GKS_EINVAL). */
 int gks_step(gks_handle* h, int32_t nsteps, const double* dt_fixed, const double* t_end);
 
 /* Wait for the enqueued work and copy the state of one problem to host

@@ -388,7 +388,8 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
 // The time step of a problem, taken by the first wave of its boundary launch
 // (all 64 lanes active): lane q reads CFL slot q and resets it, a shuffle
 // minimum gives the bound, lane 0 writes the step (the fixed step if one is
-// set, clipped to the end time if one is set).
+// set, clipped to the end time if one is set; zero once the problem has a
+// nonphysical state).
 static_assert(kDtSlots == 64, "one CFL slot per lane of a wave");
 template <typename TS, typename TP, typename TC>
 __device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ctl, int p, int lane) {
@@ -404,6 +405,9 @@ __device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ct
   if (lane == 0) {
     double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
     if (t_end > 0.0) dt = fmin(dt, fmax(t_end - t, 0.0));
+    // after a nonphysical state the problem's steps are empty: its state stays
+    // the one the failing step produced
+    if (*g.err) dt = 0.0;
     *g.dt = dt;
   }
 }

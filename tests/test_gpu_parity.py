@@ -166,6 +166,9 @@ def test_nonphysical_state_is_reported(G):
     prob, st = W.riemann_2d(2, n=16)
     with G.Solver(prob, st) as S:
         S.step(3, dt=5.0)  # far beyond any CFL limit: the state blows up (no memory access depends on values)
+        # the steps after the failing one are empty: time and step count stop
+        got, t, n, rc = S.fetch(check=False)
+        assert rc == G.GKS_ENONPHYS and 1 <= n < 3 and t == 5.0 * n
         with pytest.raises(G.GKSError) as e:
             S.fetch()
         assert e.value.code == G.GKS_ENONPHYS
