@@ -761,18 +761,28 @@ __device__ __forceinline__ bool euler_eigen_2d(double gamma, const double* W, do
   const double un = kX ? u : v, ut = kX ? v : u;  // normal and tangential velocity
   const int in = kX ? 1 : 2, it = kX ? 2 : 1;      // their momentum components
   const double b1 = (gamma - 1.0) / (c * c), b2 = b1 * q;
-  // R: column 0 = (1, u - c n, H - un c), 1 = (1, u, q), 2 = tangential unit
-  // vector with ut, 3 = (1, u + c n, H + un c)
-  R[0][0] = 1.0, R[0][1] = 1.0, R[0][2] = 0.0, R[0][3] = 1.0;
-  R[in][0] = un - c, R[in][1] = un, R[in][2] = 0.0, R[in][3] = un + c;
-  R[it][0] = ut, R[it][1] = ut, R[it][2] = 1.0, R[it][3] = ut;
-  R[3][0] = H - un * c, R[3][1] = q, R[3][2] = ut, R[3][3] = H + un * c;
-  // L rows: 0.5 (b2 + un/c, -b1 u - n/c, b1); (1 - b2, b1 u, -b1);
-  // (-ut, tangential unit vector); 0.5 (b2 - un/c, -b1 u + n/c, b1)
-  L[0][0] = 0.5 * (b2 + un * ic), L[0][in] = -0.5 * (b1 * un + ic), L[0][it] = -0.5 * (b1 * ut), L[0][3] = 0.5 * b1;
-  L[1][0] = 1.0 - b2, L[1][in] = b1 * un, L[1][it] = b1 * ut, L[1][3] = -b1;
-  L[2][0] = -ut, L[2][in] = 0.0, L[2][it] = 1.0, L[2][3] = 0.0;
-  L[3][0] = 0.5 * (b2 - un * ic), L[3][in] = -0.5 * (b1 * un - ic), L[3][it] = -0.5 * (b1 * ut), L[3][3] = 0.5 * b1;
+  // R: columns (1, u - c n, H - un c), (1, u, q), (0, tangential unit vector,
+  // ut), (1, u + c n, H + un c); rows 0 (density), in / it (normal and
+  // tangential momentum), 3 (energy)
+  const double rcol[4][4] = {{1.0, un - c, ut, H - un * c},
+                             {1.0, un, ut, q},
+                             {0.0, 0.0, 1.0, ut},
+                             {1.0, un + c, ut, H + un * c}};  // (rho, normal, tangential, energy)
+  // L rows in the same order of components: 0.5 (b2 + un/c, -b1 un - 1/c,
+  // -b1 ut, b1); (1 - b2, b1 un, b1 ut, -b1); (-ut, 0, 1, 0);
+  // 0.5 (b2 - un/c, -b1 un + 1/c, -b1 ut, b1)
+  const double lrow[4][4] = {{0.5 * (b2 + un * ic), -0.5 * (b1 * un + ic), -0.5 * (b1 * ut), 0.5 * b1},
+                             {1.0 - b2, b1 * un, b1 * ut, -b1},
+                             {-ut, 0.0, 1.0, 0.0},
+                             {0.5 * (b2 - un * ic), -0.5 * (b1 * un - ic), -0.5 * (b1 * ut), 0.5 * b1}};
+  const int comp[4] = {0, in, it, 3};  // frame component -> conservative component
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      R[comp[f]][r] = rcol[r][f];
+      L[r][comp[f]] = lrow[r][f];
+    }
   return true;
 }
 
