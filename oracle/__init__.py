@@ -41,6 +41,7 @@ class orc_problem(C.Structure):
         ("weno_eps", C.c_double), ("weno_c", C.c_double), ("recon_vars", C.c_int),
         ("exact_c", C.c_int), ("bc_kind", C.c_int * 4), ("bc_state", (C.c_double * 4) * 4),
         ("bc_alt", (C.c_double * 4) * 4), ("bc_wall", (C.c_double * 3) * 4),
+        ("obst_i0", C.c_int), ("obst_nj", C.c_int),
     ]
 
 
@@ -114,6 +115,7 @@ def make_problem(prob, exact_c=False) -> orc_problem:
             P.bc_alt[s][i] = bc.alt[i]
         for i in range(3):
             P.bc_wall[s][i] = bc.wall[i]
+    P.obst_i0, P.obst_nj = prob.obstacle
     return P
 
 

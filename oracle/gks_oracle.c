@@ -1341,6 +1341,99 @@ static void side_values(double Ub, const double* p, int ax, double sgn, double h
   *Wss = pss;
 }
 
+/* ---- 2D solid step (Sec. 4.6) ---------------------------------------- */
+
+/* cell (i, j) lies inside the solid step {i >= i0, j < nj} (ghost indices
+ * included) */
+static int solid(const orc_problem* P, int i, int j) {
+  return P->obst_nj > 0 && i >= P->obst_i0 && j < P->obst_nj;
+}
+
+/* negate the momentum along x (ax = 0) and/or y (ax = 1) */
+static void flip(const double* Ws, int fu, int fv, double* Wg) {
+  for (int v = 0; v < 4; ++v) Wg[v] = Ws[v];
+  if (fu) Wg[1] = -Ws[1];
+  if (fv) Wg[2] = -Ws[2];
+}
+
+/* Reading (the paper defers the corner to an external reference): the two
+ * layers of solid cells along the step's faces are slip-wall images of the
+ * gas: below the top face the image across it (v negated), and beside the
+ * vertical face, below those two rows, the image across that face (u
+ * negated).  The 2 x 2 block at the corner thus takes the image across the
+ * top face.  (Its image through the corner point lets the expansion round
+ * the corner empty the cells above the step: the Mach 3 flow of Sec. 4.6
+ * leaves the physical states by t = 0.25 on 60 x 20 cells.)  The
+ * Gauss-point values on the interfaces between those solid cells are imaged
+ * the same way (a mirror swaps the Gauss points along it), and so are the
+ * few boundary images next to the step that the first solid layer reads:
+ * the south images below the vertical face's solid columns and the east
+ * images of the top face's solid rows, each the boundary's own image of the
+ * solid cell's.  Filled after the boundary images of the domain edges. */
+static void fill_obstacle_2d(const orc_problem* P, grid2* G) {
+  if (P->obst_nj <= 0) return;
+  int nx = G->nx, i0 = P->obst_i0, nj = P->obst_nj;
+  double Ws[4], Wg[4], Wm[4];
+  /* cells: the two rows below the top face, then the two columns beside
+   * the vertical face below them */
+  for (int dy = 0; dy < 2; ++dy)
+    for (int i = i0; i < nx; ++i) {
+      get_cell(G, nj + dy, i, Ws);
+      flip(Ws, 0, 1, Wg);
+      set_cell(G, nj - 1 - dy, i, Wg);
+    }
+  for (int dx = 0; dx < 2; ++dx)
+    for (int j = 0; j < nj - 2; ++j) {
+      get_cell(G, j, i0 - 1 - dx, Ws);
+      flip(Ws, 1, 0, Wg);
+      set_cell(G, j, i0 + dx, Wg);
+    }
+  /* the south boundary's images of the vertical face's solid columns, the
+   * east boundary's images of the top face's solid rows */
+  for (int dx = 0; dx < 2; ++dx)
+    for (int m = 0; m < 2; ++m) {
+      get_cell(G, m, i0 - 1 - dx, Ws);
+      flip(Ws, 1, 0, Wm);
+      mirror_state(P, 2, P->bc_kind[2], Wm, Wg);
+      set_cell(G, -1 - m, i0 + dx, Wg);
+    }
+  for (int m = 0; m < 2; ++m)
+    for (int dy = 0; dy < 2; ++dy) {
+      get_cell(G, nj + dy, nx - 1 - m, Ws);
+      flip(Ws, 0, 1, Wm);
+      mirror_state(P, 1, P->bc_kind[1], Wm, Wg);
+      set_cell(G, nj - 1 - dy, nx + m, Wg);
+    }
+  /* x interfaces: fi = i0+1..nx in the two rows below the top face, fi =
+   * i0 + 1 beside the vertical face below them */
+  for (int dy = 0; dy < 2; ++dy)
+    for (int fi = i0 + 1; fi <= nx; ++fi)
+      for (int g = 0; g < 2; ++g) {
+        for (int v = 0; v < 4; ++v) Ws[v] = GFX(G, 1 - g, v, nj + dy, fi);
+        flip(Ws, 0, 1, Wg);
+        for (int v = 0; v < 4; ++v) GFX(G, g, v, nj - 1 - dy, fi) = Wg[v];
+      }
+  for (int j = 0; j < nj - 2; ++j)
+    for (int g = 0; g < 2; ++g) {
+      for (int v = 0; v < 4; ++v) Ws[v] = GFX(G, g, v, j, i0 - 1);
+      flip(Ws, 1, 0, Wg);
+      for (int v = 0; v < 4; ++v) GFX(G, g, v, j, i0 + 1) = Wg[v];
+    }
+  /* y interfaces: fj = nj - 1 (columns i0..nx-1), column i0 (fj = 0..nj-2) */
+  for (int i = i0; i < nx; ++i)
+    for (int g = 0; g < 2; ++g) {
+      for (int v = 0; v < 4; ++v) Ws[v] = GFY(G, g, v, nj + 1, i);
+      flip(Ws, 0, 1, Wg);
+      for (int v = 0; v < 4; ++v) GFY(G, g, v, nj - 1, i) = Wg[v];
+    }
+  for (int fj = 0; fj <= nj - 2; ++fj)
+    for (int g = 0; g < 2; ++g) {
+      for (int v = 0; v < 4; ++v) Ws[v] = GFY(G, 1 - g, v, fj, i0 - 1);
+      flip(Ws, 1, 0, Wg);
+      for (int v = 0; v < 4; ++v) GFY(G, g, v, fj, i0) = Wg[v];
+    }
+}
+
 static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, double dt, double t, double* fluxx,
                   double* fluxy) {
   grid2 Gs, *G = &Gs;
@@ -1367,6 +1460,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
         for (int i = 0; i < nx; ++i) GFY(G, g, v, fj, i) = fy[(((size_t)g * nv + v) * (ny + 1) + fj) * nx + i];
     }
   fill_ghosts_2d(P, G, t);
+  fill_obstacle_2d(P, G);
 
   /* reconstruction: interior cells and the edge ghost cells */
 #pragma omp parallel for schedule(static)
@@ -1381,6 +1475,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
 #pragma omp parallel for schedule(static) reduction(| : status)
   for (int j = 0; j < ny; ++j)
     for (int fi = 0; fi <= nx; ++fi) {
+      if (solid(P, fi - 1, j) && solid(P, fi, j)) continue; /* inside the step */
       orc_face_input in;
       memset(&in, 0, sizeof(in));
       in.dn = h;
@@ -1410,6 +1505,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
 #pragma omp parallel for schedule(static) reduction(| : status)
   for (int fj = 0; fj <= ny; ++fj)
     for (int i = 0; i < nx; ++i) {
+      if (solid(P, i, fj - 1) && solid(P, i, fj)) continue; /* inside the step */
       orc_face_input in;
       memset(&in, 0, sizeof(in));
       in.dn = k;
@@ -1439,6 +1535,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
   for (int v = 0; v < nv; ++v)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
+        if (solid(P, i, j)) continue;
         double d = FLX[((size_t)v * ny + j) * (nx + 1) + i] - FLX[((size_t)v * ny + j) * (nx + 1) + i + 1] +
                    FLY[((size_t)v * (ny + 1) + j) * nx + i] - FLY[((size_t)v * (ny + 1) + j + 1) * nx + i];
         cell[((size_t)v * ny + j) * nx + i] += d / (h * k);
@@ -1640,6 +1737,7 @@ double orc_dt(const orc_problem* P, const double* cell) {
   double best = INFINITY;
   size_t n = (size_t)nx * ny;
   for (size_t c = 0; c < n; ++c) {
+    if (dim == 2 && solid(P, (int)(c % nx), (int)(c / nx))) continue;
     double W[4];
     for (int v = 0; v < nv; ++v) W[v] = cell[(size_t)v * n + c];
     double rho = W[0], u = W[1] / rho, vv = dim == 2 ? W[2] / rho : 0.0;

@@ -53,6 +53,7 @@ typedef struct {
   double bc_state[4][4];   /* primitive (rho, u, v, p): INFLOW state; DMR post-shock state */
   double bc_alt[4][4];     /* primitive (rho, u, v, p): DMR pre-shock state (top edge) */
   double bc_wall[4][3];    /* wall u, v, T for no-slip walls */
+  int obst_i0, obst_nj;    /* 2D solid step: cells i >= obst_i0, j < obst_nj (none: obst_nj = 0) */
 } orc_problem;
 
 /* --- kinetic building blocks ------------------------------------------- */

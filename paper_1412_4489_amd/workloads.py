@@ -12,6 +12,7 @@ Workloads (Sec. 4 of Pan & Xu, arXiv:1412.4489):
   * sod_2d           -- Sod's problem of Sec. 4.2 in a 2D channel
   * riemann_2d       -- 2D Riemann problems, Sec. 4.3 (cases 1, 2)
   * shock_vortex     -- shock-vortex interaction, Sec. 4.4
+  * forward_facing_step -- Sec. 4.6 (a solid step inside the grid)
   * dmr              -- double Mach reflection, Sec. 4.5
   * viscous_shock_tube -- Sec. 4.7 (no-slip adiabatic walls, symmetry line)
   * cavity           -- lid-driven cavity, Sec. 4.8
@@ -66,6 +67,9 @@ class Problem:
     weno_c: float = 10.0
     recon_vars: int = 0
     bc: list = field(default_factory=lambda: [BC(), BC(), BC(), BC()])
+    # 2D solid step in the lower right corner: cells i >= i0, j < nj
+    # ((i0, nj) = (0, 0): none)
+    obstacle: tuple = (0, 0)
     t_end: float = 0.0
     name: str = ""
 
@@ -397,6 +401,27 @@ def shock_vortex(nx=201, ny=101, t_end=0.8, kappa=0.3, mu=0.204, rc=0.05, recon_
         return wl * upstream + (1.0 - wl) * downstream
 
     cell, fx, fy = _piecewise_2d(prob, state_at)
+    return prob, State(cell, fx, fy)
+
+
+def forward_facing_step(nx=120, ny=40, t_end=4.0, recon_vars=1):
+    """Sec. 4.6 forward-facing step: the tunnel [0, 3] x [0, 1] with a solid
+    step from x = 0.6 to the exit of height 0.2 (cells i >= 0.2 nx,
+    j < 0.2 ny), a Mach 3 flow (rho, u, v, p) = (1.4, 3, 0, 1) everywhere at
+    t = 0 and flowing in on the left, outflow on the right, slip walls on
+    the tunnel's walls and the step."""
+    g = 1.4
+    if nx % 5 or ny % 5:
+        raise ValueError("nx and ny must be multiples of 5 (the step on cell edges)")
+    state = (1.4, 3.0, 0.0, 1.0)
+    bc = [BC("inflow", state=state), BC("outflow"), BC("reflect"), BC("reflect")]
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, gamma=g,
+                   tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end, recon_vars=recon_vars, bc=bc,
+                   obstacle=(nx // 5, ny // 5), name=f"forward_facing_step_{nx}x{ny}")
+    q = cons(g, *state)
+    cell = np.broadcast_to(q[:, None, None], (4, ny, nx)).copy()
+    fx = np.broadcast_to(q[None, :, None, None], (2, 4, ny, nx + 1)).copy()
+    fy = np.broadcast_to(q[None, :, None, None], (2, 4, ny + 1, nx)).copy()
     return prob, State(cell, fx, fy)
 
 

@@ -314,3 +314,67 @@ def test_entropy_wave_decays_by_heat_conduction(oracle, prandtl, n, tol):
     rate = -np.log(a1 / a0) / t
     exact = -np.log(entropy_wave_temperature(prob.mu, prandtl, t)) / t
     assert abs(rate / exact - 1.0) < tol, (rate, exact)
+
+
+# --------------------------------------------------------------------------
+# The solid step of Sec. 4.6
+# --------------------------------------------------------------------------
+
+def _sub(st, rows, cols, nxf):
+    """the state of a sub-rectangle of cells (rows, cols) with its faces"""
+    j0, j1 = rows
+    i0, i1 = cols
+    return W.State(st.cell[:, j0:j1, i0:i1].copy(), st.fx[:, :, j0:j1, i0:i1 + 1].copy(),
+                   st.fy[:, :, j0:j1 + 1, i0:i1].copy())
+
+
+@pytest.mark.parametrize("face", ["top", "vertical"])
+def test_step_faces_are_slip_walls(oracle, face):
+    """Away from its corner a face of the step must act exactly as a slip
+    wall on the domain edge: the gas above the step (or left of it) is
+    stepped beside the same gas on a rectangle whose south (or east) edge is
+    a slip wall.  After three steps every cell farther than 11 cells from
+    the corner (beyond the reach of three steps of the compact stencil)
+    agrees to rounding, the cells next to the face included."""
+    from dataclasses import replace
+    nx, ny, i0 = 40, 30, 12
+    nj = 10 if face == "top" else 25
+    h = 1.0 / 40
+    out = [W.BC("outflow") for _ in range(4)]
+    A = W.Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=nx * h, y0=0.0, y1=ny * h, gamma=1.4, tau_eps=0.05,
+                  cfl=0.2, recon_vars=1, bc=list(out), obstacle=(i0, nj))
+    sA = W.smooth_periodic_2d(nx=nx, ny=ny, seed=5 if face == "top" else 6, amp=0.1)[1]
+    if face == "top":
+        B = replace(A, nx=nx - i0, ny=ny - nj, x0=i0 * h, y0=nj * h, obstacle=(0, 0),
+                    bc=[W.BC("outflow"), W.BC("outflow"), W.BC("reflect"), W.BC("outflow")])
+        sB = _sub(sA, (nj, ny), (i0, nx), nx)
+    else:
+        B = replace(A, nx=i0, x1=i0 * h, obstacle=(0, 0),
+                    bc=[W.BC("outflow"), W.BC("reflect"), W.BC("outflow"), W.BC("outflow")])
+        sB = _sub(sA, (0, ny), (0, i0), nx)
+    dt = 0.5 * oracle.dt(A, sA)
+    for n in range(3):
+        oracle.step(A, sA, dt, n * dt)
+        oracle.step(B, sB, dt, n * dt)
+    m = 11
+    if face == "top":
+        far, near = (sA.cell[:, nj:, i0 + m:], sB.cell[:, :, m:]), (sA.cell[:, nj:, i0:i0 + m], sB.cell[:, :, :m])
+    else:
+        far, near = (sA.cell[:, :nj - m, :i0], sB.cell[:, :nj - m, :]), (sA.cell[:, nj - m:, :i0], sB.cell[:, nj - m:, :])
+    assert np.abs(far[0] - far[1]).max() < 1e-14
+    # (the corner itself is another matter)
+    assert np.abs(near[0] - near[1]).max() > 1e-6
+
+
+def test_forward_facing_step_coarse(oracle):
+    """Sec. 4.6 on 60 x 20 cells to t = 1: every gas cell physical, the
+    solid cells untouched."""
+    prob, st = W.forward_facing_step(60, 20, t_end=1.0)
+    solid0 = st.cell[:, :4, 12:].copy()
+    steps, t = oracle.run(prob, st, t_end=1.0)
+    c = st.cell
+    gas = np.ones(c.shape[1:], bool)
+    gas[:4, 12:] = False
+    pr = (prob.gamma - 1.0) * (c[3] - 0.5 * (c[1] ** 2 + c[2] ** 2) / c[0])
+    assert (c[0][gas] > 0).all() and (pr[gas] > 0).all()
+    assert np.array_equal(c[:, :4, 12:], solid0)
