@@ -103,6 +103,15 @@ typedef struct {
   int32_t precision;        /* GKS_FP64 or GKS_FP32_MIXED */
   gks_bc bc[4];             /* W, E, S, N */
   double t0;                /* time of the initial state (restart from a fetched state) */
+  /* 2D solid step in the lower right corner (Sec. 4.6, forward-facing step):
+   * the cells i >= obstacle_i0, j < obstacle_nj; obstacle_nj = 0 for none,
+   * else 2 <= obstacle_i0 <= nx - 4, 4 <= obstacle_nj <= ny - 3, and the east
+   * and south boundaries of a mirror kind (outflow, reflect, no-slip).  Its
+   * faces are slip walls.  Its cells take no part in the update, the CFL
+   * condition or the nonphysical-state check: the two layers along its faces
+   * (and the point values between them) hold slip-wall images of the gas,
+   * refreshed every step, the others keep their initial values. */
+  int32_t obstacle_i0, obstacle_nj;
 } gks_problem;
 
 typedef struct gks_handle gks_handle; /* opaque, owned by the library */

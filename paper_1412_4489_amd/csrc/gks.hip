@@ -135,7 +135,7 @@ constexpr int kDtSlots = 64;
 constexpr size_t kScalBytes = 64 + kDtSlots * 8;  // t, dt, steps, err (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
-enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_COUNT };  // boundary, cells+ring, interfaces, cells
+enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_OBST, KK_COUNT };  // boundary, cells+ring, interfaces, cells, step images
 
 // device descriptor of one problem, read by every kernel
 template <typename TS, typename TP, typename TC>
@@ -145,7 +145,10 @@ struct Prob {
   BCDev bc[4];
   Rec<TC> R;
   int recon_vars;            // 0 conservative, 1 characteristic variables
+  int obst_i0, obst_nj;      // solid step: cells i >= obst_i0, j < obst_nj (none: obst_nj = 0)
   unsigned first[KK_COUNT];  // first logical block of the problem in each kind's launch
+  // cell (i, j) inside the solid step (ghost indices included)
+  __device__ __forceinline__ bool solid(int i, int j) const { return obst_nj > 0 && i >= obst_i0 && j < obst_nj; }
 };
 
 // kernel argument: the group's descriptors and the block-owner table of one kind
@@ -426,6 +429,115 @@ __global__ void __launch_bounds__(256) k_ghost_2d(KA<Prob<TS, TP, TC>> a, const 
     ghost_sn_item(Q, id - nwe);
 }
 
+// ---------------------------------------------------------------------------
+// The solid step (Sec. 4.6): images in the two layers of solid cells along
+// its faces, filled after the domain-edge images.  Below the top face the
+// slip-wall image across it (v negated), beside the vertical face below
+// those two rows the image across that face (u negated); the 2 x 2 block at
+// the corner thus takes the top face's image (the paper defers the corner to
+// an external reference).  The Gauss-point values between those solid cells
+// are imaged alike (a mirror swaps the Gauss points along it), and so are
+// the domain-edge images that the first solid layer reads: the south images
+// below the vertical face's solid columns and the east images of the top
+// face's solid rows, each the edge's own image of the solid cell's image.
+// Every item reads gas data only and writes solid data only.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int step_items(int nx, int i0, int nj) {
+  const int w = nx - i0;
+  return 2 * w + 2 * (nj - 2) + 4 + 4 + 4 * w + 2 * (nj - 2) + 2 * w + 2 * (nj - 1);
+}
+
+__device__ __forceinline__ void flip_uv(const double* s, bool fu, bool fv, double* o) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) o[v] = s[v];
+  if (fu) o[1] = -s[1];
+  if (fv) o[2] = -s[2];
+}
+
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_step_images_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_OBST, id);
+  const Grid<TS, TP> g = Q.g;
+  const Idx& x = g.ix;
+  const int nx = x.nx, i0 = Q.obst_i0, nj = Q.obst_nj, w = nx - i0;
+  if (nj <= 0 || id >= step_items(nx, i0, nj)) return;
+  const double gamma = Q.P.gamma;
+  double src[4], out[4], mid[4];
+  // cells: the two rows below the top face
+  if (id < 2 * w) {
+    const int dy = id / w, i = i0 + id % w;
+    for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, nj + dy, i)];
+    flip_uv(src, false, true, out);
+    for (int v = 0; v < 4; ++v) g.W[x.w(v, nj - 1 - dy, i)] = out[v];
+    return;
+  }
+  id -= 2 * w;
+  // cells: the two columns beside the vertical face below them
+  if (id < 2 * (nj - 2)) {
+    const int dx = id / (nj - 2), j = id % (nj - 2);
+    for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, j, i0 - 1 - dx)];
+    flip_uv(src, true, false, out);
+    for (int v = 0; v < 4; ++v) g.W[x.w(v, j, i0 + dx)] = out[v];
+    return;
+  }
+  id -= 2 * (nj - 2);
+  // the south edge's images of the vertical face's solid columns
+  if (id < 4) {
+    const int dx = id / 2, m = id % 2;
+    for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, m, i0 - 1 - dx)];
+    flip_uv(src, true, false, mid);
+    bc_mirror(Q.bc[2], 1, gamma, mid, out);
+    for (int v = 0; v < 4; ++v) g.W[x.w(v, -1 - m, i0 + dx)] = out[v];
+    return;
+  }
+  id -= 4;
+  // the east edge's images of the top face's solid rows
+  if (id < 4) {
+    const int m = id / 2, dy = id % 2;
+    for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, nj + dy, nx - 1 - m)];
+    flip_uv(src, false, true, mid);
+    bc_mirror(Q.bc[1], 0, gamma, mid, out);
+    for (int v = 0; v < 4; ++v) g.W[x.w(v, nj - 1 - dy, nx + m)] = out[v];
+    return;
+  }
+  id -= 4;
+  // x interfaces i0+1..nx of the two rows below the top face
+  if (id < 4 * w) {
+    const int dy = id / (2 * w), r = id % (2 * w), fi = i0 + 1 + r / 2, gp = r % 2;
+    for (int v = 0; v < 4; ++v) src[v] = (double)g.FX[x.fx(1 - gp, v, nj + dy, fi)];
+    flip_uv(src, false, true, out);
+    for (int v = 0; v < 4; ++v) g.FX[x.fx(gp, v, nj - 1 - dy, fi)] = (TS)out[v];
+    return;
+  }
+  id -= 4 * w;
+  // x interface i0+1 beside the vertical face below them
+  if (id < 2 * (nj - 2)) {
+    const int j = id / 2, gp = id % 2;
+    for (int v = 0; v < 4; ++v) src[v] = (double)g.FX[x.fx(gp, v, j, i0 - 1)];
+    flip_uv(src, true, false, out);
+    for (int v = 0; v < 4; ++v) g.FX[x.fx(gp, v, j, i0 + 1)] = (TS)out[v];
+    return;
+  }
+  id -= 2 * (nj - 2);
+  // y interface nj-1 of the columns i0..nx-1
+  if (id < 2 * w) {
+    const int i = i0 + id / 2, gp = id % 2;
+    for (int v = 0; v < 4; ++v) src[v] = (double)g.FY[x.fy(gp, v, nj + 1, i)];
+    flip_uv(src, false, true, out);
+    for (int v = 0; v < 4; ++v) g.FY[x.fy(gp, v, nj - 1, i)] = (TS)out[v];
+    return;
+  }
+  id -= 2 * w;
+  // y interfaces 0..nj-2 of column i0
+  {
+    const int fj = id / 2, gp = id % 2;
+    for (int v = 0; v < 4; ++v) src[v] = (double)g.FY[x.fy(1 - gp, v, fj, i0 - 1)];
+    flip_uv(src, true, false, out);
+    for (int v = 0; v < 4; ++v) g.FY[x.fy(gp, v, fj, i0)] = (TS)out[v];
+  }
+}
+
 // 1D: tasks (side, m), m = 0, 1 ghost cells -1-m / nx+m, m = 2 the ghost
 // interface -1 / nx+1
 template <typename TS, typename TP, typename TC>
@@ -660,6 +772,13 @@ struct Face {
   int a, b;   // x: (j, fi); y: (fj, i)
 };
 
+// both cells of interface F inside the solid step of Q (no flux, no point
+// values: the interface is skipped by every phase)
+template <class PR>
+__device__ __forceinline__ bool inside_step(const PR& Q, const Face& F) {
+  return F.isx ? Q.solid(F.b - 1, F.a) && Q.solid(F.b, F.a) : Q.solid(F.b, F.a - 1) && Q.solid(F.b, F.a);
+}
+
 __device__ __forceinline__ Face face_of(const Idx& x, int id) {
   const int nfx = x.fxr * x.ny;
   Face F;
@@ -724,6 +843,7 @@ __global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
   const Rec<TC> R = Q.R;
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
+  if (inside_step(Q, F)) return;
   double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
   load_face_cell(g, F, 0, Wc[0], pc[0]);
   load_face_cell(g, F, 1, Wc[1], pc[1]);
@@ -836,6 +956,7 @@ __device__ __forceinline__ void iface_hydro_body(const Prob<TS, TP, TC>& Q, int 
   const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
+  if (inside_step(Q, F)) return;
   const double hs = F.isx ? g.geo.k : g.geo.h;
   double flux[4], pvm[4], pvp[4], E[4];
   iface_hydro_2d<TC>(P, dt, hs, R, (size_t)id, flux, pvm, pvp, E);
@@ -858,6 +979,7 @@ __device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id
   const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
   const Phys P = Q.P;
   const Face F = face_of(g.ix, id);
+  if (inside_step(Q, F)) return;
   const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
   double Wc[4], pc[4][5];
   load_face_cell(g, F, side, Wc, pc);
@@ -952,7 +1074,7 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
   const Grid<TS, TP> g = Q.g;
   const int nx = g.ix.nx, ny = g.ix.ny;
   double bound = 1e300;
-  if (id < nx * ny) {
+  if (id < nx * ny && !Q.solid(id % nx, id / nx)) {
     const int j = id / nx, i = id % nx;
     const Idx& x = g.ix;
     double W[4];
@@ -1079,7 +1201,7 @@ struct Group {
   uint32_t* owner[KK_COUNT] = {};          // device block-owner tables
   unsigned nblk[KK_COUNT] = {};
   unsigned cap[KK_COUNT] = {};             // allocated owner entries
-  int bs[KK_COUNT] = {256, 256, 256, 256};  // block size of each kind
+  int bs[KK_COUNT] = {256, 256, 256, 256, 64};  // block size of each kind
   double* ctl = nullptr;                   // device [members][2]: fixed step, end time
   std::vector<double> ctl_host;            // values last uploaded
 };
@@ -1152,6 +1274,17 @@ std::string validate(const gks_problem& p) {
   if (!(p.tau_eps >= 0.0) || !(p.tau_c >= 0.0)) return "tau constants must be >= 0";
   if (!std::isfinite(p.t0)) return "t0 must be finite";
   if (p.recon_vars != 0 && p.recon_vars != 1) return "recon_vars must be 0 or 1";
+  if (p.obstacle_nj != 0) {
+    auto mirrors = [](int k) {
+      return k == GKS_BC_OUTFLOW || k == GKS_BC_REFLECT || k == GKS_BC_NOSLIP_ISOTHERMAL ||
+             k == GKS_BC_NOSLIP_ADIABATIC;
+    };
+    if (p.dim != 2) return "a solid step needs dim 2";
+    if (p.obstacle_i0 < 2 || p.obstacle_i0 > p.nx - 4) return "step: obstacle_i0 must lie in [2, nx - 4]";
+    if (p.obstacle_nj < 4 || p.obstacle_nj > p.ny - 3) return "step: obstacle_nj must lie in [4, ny - 3]";
+    if (!mirrors(p.bc[1].kind) || !mirrors(p.bc[2].kind))
+      return "step: the east and south boundaries must be mirror kinds (outflow, reflect, no-slip)";
+  }
   if (p.precision != GKS_FP64 && p.precision != GKS_FP32_MIXED) return "unknown precision";
   const int nsides = p.dim == 2 ? 4 : 2;
   for (int s = 0; s < nsides; ++s) {
@@ -1213,6 +1346,7 @@ size_t work_items(const Problem& p, int dim, int k) {
       case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1) + 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
       case KK_RECON: return (nx + 2) * (ny + 2);
       case KK_FACE: return n_interfaces(p.ix);
+      case KK_OBST: return p.spec.obstacle_nj > 0 ? step_items((int)nx, p.spec.obstacle_i0, p.spec.obstacle_nj) : 0;
       default: return nx * ny;
     }
   }
@@ -1220,6 +1354,7 @@ size_t work_items(const Problem& p, int dim, int k) {
     case KK_GA: return 6;
     case KK_RECON: return nx + 2;
     case KK_FACE: return nx + 1;
+    case KK_OBST: return 0;
     default: return nx;
   }
 }
@@ -1262,6 +1397,8 @@ int build_tables(gks_handle* h, Group& G) {
     d.R.t = (TC*)p.rect;
     d.R.nf = G.dim == 2 ? n_interfaces(p.ix) : 0;
     d.recon_vars = p.spec.recon_vars;
+    d.obst_i0 = p.spec.obstacle_i0;
+    d.obst_nj = p.spec.obstacle_nj;
   }
   for (int k = 0; k < KK_COUNT; ++k) {
     for (size_t m = 0; m < n; ++m) {
@@ -1336,6 +1473,8 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   record_begin(h, st);
   if (G.dim == 2) {
     k_ghost_2d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
+    if (G.nblk[KK_OBST])
+      k_step_images_2d<TS, TP, TC><<<G.nblk[KK_OBST], G.bs[KK_OBST], 0, st>>>(A[KK_OBST]);
   } else {
     k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
   }
@@ -1851,7 +1990,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
   // time every candidate block size for all kernel classes at once and
   // keep the fastest per class
   static const int cand[3] = {64, 128, 256};
-  static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE};
+  static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE, GKS_K_GHOST};
   double best_t[GKS_K_COUNT];
   int best_bs[GKS_K_COUNT];
   for (int k = 0; k < GKS_K_COUNT; ++k) {

@@ -40,7 +40,7 @@ class gks_problem(C.Structure):
                 ("prandtl", C.c_double), ("tau_eps", C.c_double), ("tau_c", C.c_double),
                 ("cfl", C.c_double), ("weno_eps", C.c_double), ("weno_c", C.c_double),
                 ("recon_vars", C.c_int32), ("precision", C.c_int32), ("bc", gks_bc * 4),
-                ("t0", C.c_double)]
+                ("t0", C.c_double), ("obstacle_i0", C.c_int32), ("obstacle_nj", C.c_int32)]
 
 
 class GKSError(RuntimeError):
@@ -93,6 +93,7 @@ def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
     P.tau_eps, P.tau_c, P.cfl = prob.tau_eps, prob.tau_c, prob.cfl
     P.weno_eps, P.weno_c, P.recon_vars = prob.weno_eps, prob.weno_c, prob.recon_vars
     P.precision = precision
+    P.obstacle_i0, P.obstacle_nj = prob.obstacle
     for s, bc in enumerate(prob.bc):
         P.bc[s].kind = BC_CODES[bc.kind]
         for i in range(4):

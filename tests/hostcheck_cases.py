@@ -43,6 +43,7 @@ CASES = {
     "sod_2d_char_y": lambda: W.sod_2d(20, 3, axis=1),
     "shock_vortex_char": lambda: W.shock_vortex(40, 20),
     "viscous_shock_tube": lambda: W.viscous_shock_tube(16, 8, re=200.0),
+    "forward_facing_step": lambda: W.forward_facing_step(30, 20),
     "ns_smooth": lambda: W.smooth_periodic_2d(nx=12, ny=14, seed=3, viscous=True, mu=2e-3, prandtl=0.72,
                                               tau_eps=0.0),
     "dmr": lambda: W.dmr(32, 8),
@@ -52,6 +53,18 @@ CASES = {
     "sod_1d_cons": lambda: W.sod_1d(24, recon_vars=0),
     "blast_1d": lambda: W.blast_1d(30),
 }
+
+
+def _gas(prob, c):
+    """the cells outside a solid step (whose cells hold images, not gas)"""
+    i0, nj = prob.obstacle
+    if not nj:
+        return c
+    c = c.copy()
+    c[:, :nj, i0:] = 0.0
+    return c
+
+
 bad = 0
 for name, mk in CASES.items():
     for prec in (gks.GKS_FP64, gks.GKS_FP32_MIXED):
@@ -81,15 +94,15 @@ for name, mk in CASES.items():
                 assert e.code == gks.GKS_ENONPHYS, e
                 gok2 = False
         same = gok2 == ok2
-        if ok2 and gok2 and not any(k in name for k in ("rough", "riemann", "dmr", "sod", "blast", "shock")):
+        if ok2 and gok2 and not any(k in name for k in ("rough", "riemann", "dmr", "sod", "blast", "shock", "step")):
             # free-running on smooth data (discontinuous data may flip a
             # limiter branch on rounding-level differences)
-            e2 = np.abs(got2.cell - ref2.cell).max() / np.abs(ref2.cell).max()
+            e2 = np.abs(_gas(prob, got2.cell) - _gas(prob, ref2.cell)).max() / np.abs(ref2.cell).max()
             same = e2 < (1e-11 if prec == gks.GKS_FP64 else 1e-5)
         bad += not same
         if not same:
             print(f"{name} CFL steps differ from the oracle (physical: gpu {gok2}, oracle {ok2})", flush=True)
-        err = np.abs(got.cell - ref.cell).max() / np.abs(ref.cell).max()
+        err = np.abs(_gas(prob, got.cell) - _gas(prob, ref.cell)).max() / np.abs(ref.cell).max()
         tol = 1e-12 if prec == gks.GKS_FP64 else 1e-6
         ok = err < tol
         bad += not ok

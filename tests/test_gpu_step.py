@@ -1,0 +1,198 @@
+"""The solid step of Sec. 4.6 (forward-facing step) on the GPU.
+
+* Each face acts exactly as a slip wall on a domain edge away from the
+  corner: the GPU steps the gas beside a step and the same gas on a
+  rectangle with a reflecting edge, and beyond the reach of the stencil from
+  the corner the two agree to rounding (the oracle's pin, here on the GPU's
+  own images).
+* Parity with the oracle: FP64 step by step (1e-11), FP32-mixed one step
+  (1e-6), on the Mach 3 step flow and on rough data around a step, also in a
+  handle with problems without a step.  Cells and interfaces inside the step
+  are not compared (they hold images, not gas).
+* The paper's 120 x 40 and 240 x 80 cells to t = 4: every gas cell
+  physical, and one further step from the final state matching the
+  oracle's step of the same grid.  (360 x 120 leaves the physical states at
+  the corner; see the resolution test.)
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_1412_4489_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_4489_amd import gks
+    gks.lib()
+    return gks
+
+
+def _masks(prob):
+    """gas cells, and the x / y interfaces not inside the step"""
+    i0, nj = prob.obstacle
+    nx, ny = prob.nx, prob.ny
+    cell = np.ones((ny, nx), bool)
+    fx = np.ones((ny, nx + 1), bool)
+    fy = np.ones((ny + 1, nx), bool)
+    if nj:
+        cell[:nj, i0:] = False
+        fx[:nj, i0 + 1:] = False
+        fy[:nj, i0:] = False
+    return cell, fx, fy
+
+
+def _rel(a, b, mask):
+    """max |a - b| over the masked entries relative to each component's
+    magnitude (the momenta share the momentum vector's)"""
+    a = np.where(mask, a, 0.0)
+    b = np.where(mask, b, 0.0)
+    assert np.isfinite(a).all() and np.isfinite(b).all()
+    vax = b.ndim - 3
+    scale = np.abs(b).max(axis=tuple(k for k in range(b.ndim) if k != vax), keepdims=True)
+    idx = [slice(None)] * b.ndim
+    idx[vax] = slice(1, 3)
+    scale[tuple(idx)] = scale[tuple(idx)].max()
+    return float((np.abs(a - b) / np.maximum(scale, 1e-300)).max())
+
+
+def _compare(prob, got, ref, ctol, ptol, what=""):
+    mc, mx, my = _masks(prob)
+    assert _rel(got.cell, ref.cell, mc) < ctol, what
+    assert _rel(got.fx, ref.fx, mx) < ptol, what
+    assert _rel(got.fy, ref.fy, my) < ptol, what
+
+
+def _physical(prob, c):
+    mc = _masks(prob)[0]
+    pr = (prob.gamma - 1.0) * (c[3] - 0.5 * (c[1] ** 2 + c[2] ** 2) / c[0])
+    return bool((c[0][mc] > 0).all() and (pr[mc] > 0).all())
+
+
+def _rough_step():
+    h = 1.0 / 40
+    prob = W.Problem(dim=2, nx=36, ny=26, x0=0.0, x1=36 * h, y0=0.0, y1=26 * h, gamma=1.4, tau_eps=0.05,
+                     cfl=0.2, recon_vars=1, obstacle=(14, 9),
+                     bc=[W.BC("outflow"), W.BC("outflow"), W.BC("reflect"), W.BC("reflect")])
+    return prob, W.smooth_periodic_2d(nx=36, ny=26, seed=8, amp=0.15)[1]
+
+
+CASES = {
+    "mach3": lambda: W.forward_facing_step(60, 20),
+    "rough": _rough_step,
+}
+
+
+@pytest.mark.parametrize("face", ["top", "vertical"])
+def test_step_faces_are_slip_walls_on_the_gpu(G, oracle, face):
+    nx, ny, i0 = 40, 30, 12
+    nj = 10 if face == "top" else 25
+    h = 1.0 / 40
+    out = [W.BC("outflow") for _ in range(4)]
+    A = W.Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=nx * h, y0=0.0, y1=ny * h, gamma=1.4, tau_eps=0.05,
+                  cfl=0.2, recon_vars=1, bc=list(out), obstacle=(i0, nj))
+    sA = W.smooth_periodic_2d(nx=nx, ny=ny, seed=5 if face == "top" else 6, amp=0.1)[1]
+    if face == "top":
+        B = replace(A, nx=nx - i0, ny=ny - nj, x0=i0 * h, y0=nj * h, obstacle=(0, 0),
+                    bc=[W.BC("outflow"), W.BC("outflow"), W.BC("reflect"), W.BC("outflow")])
+        sB = W.State(sA.cell[:, nj:, i0:].copy(), sA.fx[:, :, nj:, i0:].copy(), sA.fy[:, :, nj:, i0:].copy())
+    else:
+        B = replace(A, nx=i0, x1=i0 * h, obstacle=(0, 0),
+                    bc=[W.BC("outflow"), W.BC("reflect"), W.BC("outflow"), W.BC("outflow")])
+        sB = W.State(sA.cell[:, :, :i0].copy(), sA.fx[:, :, :, :i0 + 1].copy(), sA.fy[:, :, :, :i0].copy())
+    dt = 0.5 * oracle.dt(A, sA)
+    with G.Solver([A, B], [sA, sB], G.GKS_FP64) as S:
+        S.step(3, dt=[dt, dt])
+        gA, _, _ = S.fetch(0)
+        gB, _, _ = S.fetch(1)
+    m = 11
+    if face == "top":
+        d = np.abs(gA.cell[:, nj:, i0 + m:] - gB.cell[:, :, m:]).max()
+    else:
+        d = np.abs(gA.cell[:, :nj - m, :i0] - gB.cell[:, :nj - m, :]).max()
+    print(f"{face} face: largest difference beyond the corner's reach {d:.1e}", flush=True)
+    assert d < 1e-14
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity_fp64_per_step(G, oracle, case):
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    t = 0.0
+    print(f"step {case} fp64", flush=True)
+    for n in range(4):
+        ref = st.copy()
+        oracle.step(prob, ref, dt, t)
+        with G.Solver(prob, st, G.GKS_FP64, t0=t) as S:
+            S.step(1, dt=dt)
+            got, tg, steps = S.fetch()
+        _compare(prob, got, ref, 1e-11, 1e-10, n)
+        st, t = ref, t + dt
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity_fp32_mixed(G, oracle, case):
+    prob, st = CASES[case]()
+    dt = 0.8 * oracle.dt(prob, st)
+    ref = st.copy()
+    oracle.step(prob, ref, dt, 0.0)
+    with G.Solver(prob, st, G.GKS_FP32_MIXED) as S:
+        S.step(1, dt=dt)
+        got, tg, steps = S.fetch()
+    _compare(prob, got, ref, 1e-6, 1e-5)
+
+
+def test_step_in_a_mixed_handle(G, oracle):
+    """A step problem among problems without one (the step-image launch has
+    blocks of the step problem only), both precisions."""
+    items = [W.vortex_2d(16), _rough_step(), W.forward_facing_step(30, 20), W.riemann_2d(1, n=12)]
+    probs, states = [p for p, _ in items], [s for _, s in items]
+    precs = [G.GKS_FP64, G.GKS_FP64, G.GKS_FP32_MIXED, G.GKS_FP32_MIXED]
+    dts = [0.7 * oracle.dt(p, s) for p, s in items]
+    refs = []
+    for p, s, dt in zip(probs, states, dts):
+        r = s.copy()
+        oracle.step(p, r, dt, 0.0)
+        refs.append(r)
+    with G.Solver(probs, states, precs) as S:
+        S.step(1, dt=dts)
+        for k, (p, r) in enumerate(zip(probs, refs)):
+            got, t, n = S.fetch(k)
+            tol = 1e-11 if precs[k] == G.GKS_FP64 else 1e-6
+            assert _rel(got.cell, r.cell, _masks(p)[0]) < tol, p.name
+
+
+@pytest.mark.parametrize("shape", [(120, 40), (240, 80)])
+def test_forward_facing_step_at_the_paper_resolutions(G, oracle, shape):
+    """Sec. 4.6 to t = 4 in both forms.  (On the paper's finest 360 x 120 the
+    expansion round the corner empties the gas cell above it: a
+    nonphysical state there before t = 4.  The paper modifies the flow near
+    the corner after an external reference that the source does not give.)"""
+    prob, st = W.forward_facing_step(*shape)
+    nmax = int(3.0 * 4.0 / oracle.dt(prob, st)) + 50
+    for prec in ["fp64", "fp32_mixed"]:
+        p = G.GKS_FP64 if prec == "fp64" else G.GKS_FP32_MIXED
+        print(f"{prob.name} {prec}: to t = 4", flush=True)
+        with G.Solver(prob, st, p) as S:
+            S.step(nmax, t_end=4.0)
+            got, t, n = S.fetch()
+        assert t == pytest.approx(4.0, rel=1e-14) and n < nmax
+        assert _physical(prob, got.cell)
+        dt = 0.8 * oracle.dt(prob, got)
+        ref = got.copy()
+        oracle.step(prob, ref, dt, t)
+        with G.Solver(prob, got, p, t0=t) as S:
+            S.step(1, dt=dt)
+            nxt, _, _ = S.fetch()
+        if prec == "fp64":
+            _compare(prob, nxt, ref, 1e-11, 1e-10, prob.name)
+        else:
+            _compare(prob, nxt, ref, 5e-6, 1e-3, prob.name)
+        c = got.cell[0][_masks(prob)[0]]
+        print(f"{prob.name} {prec}: {n} steps, gas density in [{c.min():.3f}, {c.max():.3f}]", flush=True)
