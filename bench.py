@@ -24,8 +24,10 @@ without packed FP32, which this build does not use); `traffic` (HBM bytes) and
 committed counter record while the kernel sources still match it.  `configs`
 gives the throughput of the other full-size 2D workloads (lid-driven cavity
 512^2, Navier-Stokes; double Mach reflection 1920x480 with the reconstruction
-in conservative and in characteristic variables; the shock-vortex interaction
-of Sec. 4.4 on 801x401, characteristic variables) in both forms.
+in conservative and in characteristic variables; in characteristic variables
+the shock-vortex interaction of Sec. 4.4 on 801x401, Riemann case 2 on 400^2
+and the forward-facing step of Sec. 4.6 on 240x80; the viscous shock tube of
+Sec. 4.7 on 600x300 at Re 1000) in both forms.
 `cpu_baseline` times the FP64 oracle on this host for a bounded number of
 steps of the same workload; the same steps on the GPU give the L1 difference
 to the oracle and the conservation drift (largest relative change of the
@@ -161,7 +163,10 @@ def config_rates(steps=20, warmup=3):
     for name, mk in (("cavity_512x512_ns_re1000", lambda: W.cavity(512)),
                      ("double_mach_reflection_1920x480", lambda: W.dmr(1920, 480)),
                      ("double_mach_reflection_1920x480_characteristic", lambda: W.dmr(1920, 480, recon_vars=1)),
-                     ("shock_vortex_801x401_characteristic", lambda: W.shock_vortex(801, 401))):
+                     ("shock_vortex_801x401_characteristic", lambda: W.shock_vortex(801, 401)),
+                     ("riemann2_400x400_characteristic", lambda: W.riemann_2d(2, n=400, recon_vars=1)),
+                     ("forward_facing_step_240x80_characteristic", lambda: W.forward_facing_step(240, 80)),
+                     ("viscous_shock_tube_600x300_re1000", lambda: W.viscous_shock_tube(600, 300, re=1000.0))):
         prob, st = mk()
         out[name] = {}
         for pname, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):
@@ -175,7 +180,9 @@ def config_rates(steps=20, warmup=3):
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
                 S.fetch()
-            out[name][pname] = round(prob.ncells * steps / wall / 1e6, 3)
+            i0, nj = prob.obstacle
+            gas = prob.ncells - (prob.nx - i0) * nj if nj else prob.ncells  # cells of a solid step are not updated
+            out[name][pname] = round(gas * steps / wall / 1e6, 3)
         print(f"# {name}: {out[name]}", file=sys.stderr, flush=True)
     return out
 
