@@ -139,15 +139,17 @@ with gks.Solver(probs, states, precision=precs[:len(probs)]) as S:
                   flush=True)
 print("batch ok", flush=True)
 # autotuned launch shapes: bitwise the same results, the state not advanced
-pair = [W.smooth_periodic_2d(nx=13, ny=11, seed=5), W.sod_1d(20)]
+# (with a solid step: its image launch takes the boundary kernel's size)
+pair = [W.smooth_periodic_2d(nx=13, ny=11, seed=5), W.sod_1d(20), W.forward_facing_step(30, 20)]
 outs = []
 for tune in (False, True):
-    with gks.Solver([q[0] for q in pair], [q[1] for q in pair], precision=[gks.GKS_FP64, gks.GKS_FP32_MIXED]) as S:
+    with gks.Solver([q[0] for q in pair], [q[1] for q in pair],
+                    precision=[gks.GKS_FP64, gks.GKS_FP32_MIXED, gks.GKS_FP64]) as S:
         if tune:
             sizes = S.tune(2)
-            assert all(S.fetch(k)[2] == 0 for k in range(2)), "tuning advanced the state"
-        S.step(2, dt=[1e-3, 1e-3])
-        outs.append([S.fetch(k)[0].cell for k in range(2)])
+            assert all(S.fetch(k)[2] == 0 for k in range(3)), "tuning advanced the state"
+        S.step(2, dt=[1e-3, 1e-3, 1e-3])
+        outs.append([S.fetch(k)[0].cell for k in range(3)])
 same = all(np.array_equal(a, b) for a, b in zip(*outs))
 bad += not same
 print(f"tuned block sizes {sizes}: results {'identical' if same else 'DIFFER'}", flush=True)
