@@ -30,6 +30,7 @@ CASES = {
                                               tau_eps=0.0),
     "advection_1d": lambda: W.advection_1d(40),
     "sod_1d_char": lambda: W.sod_1d(48),
+    "forward_facing_step": lambda: W.forward_facing_step(30, 20),
 }
 
 
