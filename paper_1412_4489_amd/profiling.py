@@ -71,7 +71,7 @@ def kernel_table(trace_csv, grid_sizes=None):
 
 
 def kernel_markdown(agg, title, command):
-    lines = [f"# {title}", "", "Command (on the GPU box, repository root R):", "", "    " + command, "",
+    lines = [f"# {title}", "", "Command (on the machine with the GPU, repository root R, output directory O):", "", "    " + command, "",
              "| kernel | type | grid (threads) | calls | average (us) | min (us) | max (us) |",
              "|---|---|---:|---:|---:|---:|---:|"]
     for (k, t, g), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
@@ -138,15 +138,15 @@ def valu_busy(quad_cycles, duration_us):
     return quad_cycles / CUS / (duration_us * CLOCK_MHZ)
 
 
-TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_bench "
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $O/prof_bench "
              "-o bench --output-format csv -- python -u $R/bench.py --steps 50 --warmup 5 --no-cpu --no-configs")
 PMC_PASSES = (("FETCH_SIZE", "pmc_fetch", "f"), ("WRITE_SIZE", "pmc_write", "w"),
               ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
                "pmc_sq", "s"))
-SUMMARY_CMD = ("python -m paper_1412_4489_amd.profiling --trace $R/gpurun_out/prof_bench/bench_kernel_trace.csv "
-               "--fetch $R/gpurun_out/pmc_fetch/f_counter_collection.csv "
-               "--write $R/gpurun_out/pmc_write/w_counter_collection.csv "
-               "--sq $R/gpurun_out/pmc_sq/s_counter_collection.csv --out $R/profiles")
+SUMMARY_CMD = ("python -m paper_1412_4489_amd.profiling --trace $O/prof_bench/bench_kernel_trace.csv "
+               "--fetch $O/pmc_fetch/f_counter_collection.csv "
+               "--write $O/pmc_write/w_counter_collection.csv "
+               "--sq $O/pmc_sq/s_counter_collection.csv --out $R/profiles")
 
 
 def _averages(agg):
@@ -212,8 +212,8 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     t = ["# Counters: interface kernels, isentropic vortex 256 x 256, GKS_FP32_MIXED", "",
-         "Commands (on the GPU box, from /tmp with TMPDIR=/tmp, repository root R), one counter pass per run:", ""]
-    t += [f"    timeout -s KILL 120 rocprofv3 --pmc {c} -d $R/gpurun_out/{d} -o {o} --output-format csv "
+         "Commands (on the machine with the GPU, from /tmp with TMPDIR=/tmp, repository root R, output directory O), one counter pass per run:", ""]
+    t += [f"    timeout -s KILL 120 rocprofv3 --pmc {c} -d $O/{d} -o {o} --output-format csv "
           "-- python -u $R/bench.py --pmc-probe" for c, d, o in PMC_PASSES]
     t += ["", "Summary:", "", "    " + SUMMARY_CMD, "",
           "Calibration: `bench.py --pmc-probe` first copies 256 MiB three times (`__amd_rocclr_copyBuffer`).",
