@@ -626,6 +626,30 @@ def random_perturbed_2d(nx=24, ny=20, seed=0, amp=0.2, gamma=1.4, bc="periodic",
     return prob, State(np.ascontiguousarray(cell), np.ascontiguousarray(fx), np.ascontiguousarray(fy))
 
 
+def mirror_extension(prob, st, axis):
+    """the problem doubled across its low edge along `axis` (0: x, 1: y) with
+    the mirror image of the data there (normal momentum negated, Gauss points
+    along the edge's direction swapped)"""
+    m = 1 + axis  # normal momentum component
+    if axis == 1:
+        D = replace(prob, ny=2 * prob.ny, y0=prob.y0 - (prob.y1 - prob.y0))
+        c = np.concatenate([st.cell[:, ::-1, :], st.cell], axis=1)
+        fx = np.concatenate([st.fx[::-1, :, ::-1, :], st.fx], axis=2)
+        fy = np.concatenate([st.fy[:, :, ::-1, :][:, :, :-1, :], st.fy], axis=2)
+        c[m, :prob.ny] *= -1
+        fx[:, m, :prob.ny] *= -1
+        fy[:, m, :prob.ny] *= -1
+    else:
+        D = replace(prob, nx=2 * prob.nx, x0=prob.x0 - (prob.x1 - prob.x0))
+        c = np.concatenate([st.cell[:, :, ::-1], st.cell], axis=2)
+        fx = np.concatenate([st.fx[:, :, :, ::-1][:, :, :, :-1], st.fx], axis=3)
+        fy = np.concatenate([st.fy[::-1, :, :, ::-1], st.fy], axis=3)
+        c[m, :, :prob.nx] *= -1
+        fx[:, m, :, :prob.nx] *= -1
+        fy[:, m, :, :prob.nx] *= -1
+    return D, State(np.ascontiguousarray(c), np.ascontiguousarray(fx), np.ascontiguousarray(fy))
+
+
 def state_for(prob: Problem, cell, fx, fy=None) -> State:
     if fy is None:
         fy = np.zeros((2, prob.nvar, prob.ny + 1, prob.nx))

@@ -197,3 +197,45 @@ def test_periodic_seam_is_one_interface(G, oracle):
     assert np.array_equal(got.fy[..., prob.ny, :], got.fy[..., 0, :])
     _compare(got.cell, ref.cell, 1e-11, "cell")
     _compare(got.fx, ref.fx, 1e-10, "x point values")
+
+
+@pytest.mark.parametrize("axis", [0, 1], ids=["x", "y"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mixed"])
+def test_reflecting_wall_is_the_mirror_extension(G, axis, prec):
+    """The GPU's slip wall against its own mirror extension (the oracle's
+    pin of the boundary images, here on the kernels): rough data between
+    two reflecting walls and the same data doubled across one wall, stepped
+    in one handle; after four steps both halves of the doubled problem equal
+    the original to rounding (9e-16 in FP64, 4e-16 in FP32-mixed measured)."""
+    nx, ny = (12, 20) if axis == 0 else (24, 12)
+    h = 1.0 / 24
+    walls = [W.BC(), W.BC(), W.BC(), W.BC()]
+    walls[2 * axis] = W.BC("reflect")
+    walls[2 * axis + 1] = W.BC("reflect")
+    P = W.Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=nx * h, y0=0.0, y1=ny * h, gamma=1.4, tau_eps=0.05,
+                  cfl=0.2, recon_vars=1, bc=walls)
+    sP = W.random_perturbed_2d(nx=nx, ny=ny, seed=3 + axis, amp=0.2)[1]
+    if axis == 1:
+        sP.fy[:, 2, 0, :] = 0.0
+        sP.fy[:, 2, ny, :] = 0.0
+        sP.fx[..., nx] = sP.fx[..., 0]
+    else:
+        sP.fx[:, 1, :, 0] = 0.0
+        sP.fx[:, 1, :, nx] = 0.0
+        sP.fy[:, :, ny, :] = sP.fy[:, :, 0, :]
+    D, sD = W.mirror_extension(P, sP, axis)
+    dt = 0.004
+    with G.Solver([P, D], [sP, sD], prec) as S:
+        S.step(4, dt=[dt, dt])
+        gP, _, _ = S.fetch(0)
+        gD, _, _ = S.fetch(1)
+    sign = np.array([1.0, 1.0, 1.0, 1.0])
+    sign[1 + axis] = -1.0
+    if axis == 1:
+        upper, lower = gD.cell[:, ny:], gD.cell[:, :ny][:, ::-1] * sign[:, None, None]
+    else:
+        upper, lower = gD.cell[:, :, nx:], gD.cell[:, :, :nx][:, :, ::-1] * sign[:, None, None]
+    tol = 1e-13
+    d = max(np.abs(upper - gP.cell).max(), np.abs(lower - gP.cell).max())
+    print(f"mirror extension axis {axis} precision {prec}: {d:.1e}", flush=True)
+    assert d < tol
