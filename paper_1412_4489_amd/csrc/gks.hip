@@ -131,8 +131,12 @@ struct Grid {
 
 // The CFL bound is reduced into kDtSlots slots per problem (one atomic per
 // wave into slot wave % kDtSlots), which keeps the atomics on one address few.
-constexpr int kDtSlots = 64;
-constexpr size_t kScalBytes = 64 + kDtSlots * 8;  // t, dt, steps, err (+ padding), slots
+// The slots lie kDtStride words apart, each in a 256-byte block of its own:
+// atomics on one address are serialised in the memory system, so many
+// distinct addresses keep the reduction off the update's critical path.
+constexpr int kDtSlots = 512;
+constexpr int kDtStride = 32;
+constexpr size_t kScalBytes = 64 + kDtSlots * kDtStride * 8;  // t, dt, steps, err (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
 enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_OBST, KK_COUNT };  // boundary, cells+ring, interfaces, cells, step images
@@ -389,22 +393,29 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
 // ctl[2p+1] = end time (0: none; the step is shortened to reach it, later
 // steps are empty); the slots are reset for the update of this step
 // The time step of a problem, taken by the first wave of its boundary launch
-// (all 64 lanes active): lane q reads CFL slot q and resets it, a shuffle
-// minimum gives the bound, lane 0 writes the step (the fixed step if one is
-// set, clipped to the end time if one is set; zero once the problem has a
-// nonphysical state).
-static_assert(kDtSlots == 64, "one CFL slot per lane of a wave");
+// (all 64 lanes active): lane q reads CFL slots q, q + 64, ... and resets
+// them, a shuffle minimum gives the bound, lane 0 writes the step (the fixed
+// step if one is set, clipped to the end time if one is set; zero once the
+// problem has a nonphysical state).
+static_assert(kDtSlots % 64 == 0, "the slots split evenly over the lanes of a wave");
 template <typename TS, typename TP, typename TC>
 __device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ctl, int p, int lane) {
   const Grid<TS, TP> g = Q.g;
   const double fixed = ctl[2 * p], t_end = ctl[2 * p + 1], t = *g.t;
-  unsigned long long m = g.dtmin[lane];
+  unsigned long long m = ~0ull;
+#pragma unroll
+  for (int r = 0; r < kDtSlots / 64; ++r) {  // all loads in flight at once
+    const unsigned long long o = g.dtmin[(lane + 64 * r) * kDtStride];
+    m = o < m ? o : m;
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long o = __shfl_xor(m, off, 64);
     m = o < m ? o : m;
   }
-  g.dtmin[lane] = (unsigned long long)__double_as_longlong(1e300);
+#pragma unroll
+  for (int r = 0; r < kDtSlots / 64; ++r)
+    g.dtmin[(lane + 64 * r) * kDtStride] = (unsigned long long)__double_as_longlong(1e300);
   if (lane == 0) {
     double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
     if (t_end > 0.0) dt = fmin(dt, fmax(t_end - t, 0.0));
@@ -607,7 +618,7 @@ __device__ __forceinline__ double cell_dt_bound_1d(const double* W, const Phys& 
 __device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slots, unsigned wave) {
   if (!(b > 0.0) || !isfinite(b)) b = 1e300;
   for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave % kDtSlots), (unsigned long long)__double_as_longlong(b));
+  if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave % kDtSlots) * kDtStride, (unsigned long long)__double_as_longlong(b));
 }
 
 // ---------------------------------------------------------------------------
@@ -1716,9 +1727,9 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     // the clears above must land before the blocking uploads below
     if (hipStreamSynchronize(h->stream) != hipSuccess) return init_fail(GKS_EDEVICE, "hipStreamSynchronize failed");
     const double scal0[4] = {s.t0, 0.0, 0.0, 0.0};
-    const std::vector<unsigned long long> inf(kDtSlots, 0x7e37e43c8800759cull);  // bits of 1e300
+    const std::vector<unsigned long long> inf(kDtSlots * kDtStride, 0x7e37e43c8800759cull);  // bits of 1e300
     if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * 8, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * kDtStride * 8, hipMemcpyHostToDevice) != hipSuccess)
       return init_fail(GKS_EDEVICE, "upload failed");
     if (dev) continue;
     // upload: host layouts without ghosts -> ghosted device layouts
