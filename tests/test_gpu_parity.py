@@ -135,6 +135,30 @@ def test_cfl_step_matches_oracle(G, oracle):
     _compare(got.cell, ref.cell, 1e-11, "cell")
 
 
+@pytest.mark.parametrize("hot", [(190, 100), (100, 0), (3, 7)])
+def test_cfl_minimum_over_many_waves(G, oracle, hot):
+    """A 256 x 200 grid has 800 waves of cells, more than the CFL slots, so
+    several waves share a slot.  One hot cell (three times the energy) holds
+    the CFL minimum; its wave lands on a high slot, on a shared low slot, or
+    on the first one.  The first step (initial scan) and the second (the
+    update's reduction) equal the oracle's CFL steps."""
+    prob, st = W.vortex_2d(256, ny=200)
+    st.cell[3, hot[0], hot[1]] *= 3.0
+    ref = st.copy()
+    dt1 = oracle.dt(prob, ref)
+    oracle.step(prob, ref, dt1, 0.0)
+    dt2 = oracle.dt(prob, ref)
+    with G.Solver(prob, st) as S:
+        S.step(1)
+        _, t1, _ = S.fetch()
+        S.step(1)
+        _, t2, steps = S.fetch()
+    print(f"hot cell {hot}: dt1 {t1:.17g} vs {dt1:.17g}, dt2 {t2 - t1:.17g} vs {dt2:.17g}", flush=True)
+    assert steps == 2
+    assert t1 == pytest.approx(dt1, rel=1e-14)
+    assert t2 - t1 == pytest.approx(dt2, rel=1e-10)
+
+
 def test_t_end_clips_last_step(G, oracle):
     prob, st = W.vortex_2d(16)
     with G.Solver(prob, st) as S:
