@@ -24,10 +24,12 @@
  * A handle advances any number of independent problems (1D and 2D, both
  * precisions, uneven sizes) together: every step is one launch per phase for
  * all problems of a dimension, precision and (2D) reconstruction kind,
- * replayed from one captured HIP graph.  Where the paper leaves the reconstruction's robustness open, a
- * reconstructed cell polynomial whose density or pressure at an interface
- * centre is nonpositive or more than a factor two outside the range of the
- * neighbouring averages is replaced by the constant average for the step.
+ * replayed from one captured HIP graph.  Where the paper leaves the
+ * reconstruction's robustness open (end of Sec. 3.3), a reconstructed cell
+ * polynomial whose density or pressure at an interface centre is nonpositive
+ * (or, with gks_problem.admissibility = 1, more than a factor two outside the
+ * range of the neighbouring averages) is replaced by the constant average for
+ * the step; gks_fallbacks counts those cells.
  *
  * Every call returns an int status (GKS_OK or a negative GKS_E* code); no C++
  * exception crosses the ABI.  All arrays are plain memory with the layouts
@@ -112,6 +114,13 @@ typedef struct {
    * (and the point values between them) hold slip-wall images of the gas,
    * refreshed every step, the others keep their initial values. */
   int32_t obstacle_i0, obstacle_nj;
+  /* A reconstructed cell polynomial is used only if, at the centre of every
+   * interface of the cell, density and pressure are positive (0: the
+   * interface Maxwellians of Sec. 2.2 exist); 1: and also lie within a factor
+   * two of the range of the averages of the cell and its face neighbours
+   * (needed by the Mach-10 double Mach reflection of Sec. 4.5).  Otherwise
+   * the cell takes its constant average for the step. */
+  int32_t admissibility;
 } gks_problem;
 
 typedef struct gks_handle gks_handle; /* opaque, owned by the library */
@@ -210,6 +219,12 @@ enum { GKS_K_GHOST = 0,  /* boundary images, with the time step */
        GKS_K_RECON = 2, GKS_K_INTERFACE = 3, GKS_K_UPDATE = 4, GKS_K_COUNT = 5 };
 int gks_profile(gks_handle* h, int32_t mode);
 int gks_kernel_time(gks_handle* h, int32_t kernel, double* ms, int64_t* launches);
+
+/* Number of (interior cell, step) pairs of problem `problem` whose
+ * reconstruction fell back to the constant average (see admissibility),
+ * summed over the steps since gks_init.  Waits for the enqueued work.
+ * GKS_EINVAL for a bad index or a NULL pointer. */
+int gks_fallbacks(gks_handle* h, int32_t problem, int64_t* cells);
 
 /* Autotuner of the launch shapes (not part of the method): every kernel class
  * of the handle's launch sequence is timed with 64, 128 and 256 threads per

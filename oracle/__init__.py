@@ -41,7 +41,7 @@ class orc_problem(C.Structure):
         ("weno_eps", C.c_double), ("weno_c", C.c_double), ("recon_vars", C.c_int),
         ("exact_c", C.c_int), ("bc_kind", C.c_int * 4), ("bc_state", (C.c_double * 4) * 4),
         ("bc_alt", (C.c_double * 4) * 4), ("bc_wall", (C.c_double * 3) * 4),
-        ("obst_i0", C.c_int), ("obst_nj", C.c_int),
+        ("obst_i0", C.c_int), ("obst_nj", C.c_int), ("admissibility", C.c_int),
     ]
 
 
@@ -85,6 +85,8 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(orc_problem), _D, _D, _D, C.c_double, C.c_double]
         L.orc_run.argtypes = [C.POINTER(orc_problem), _D, _D, _D, C.c_int, C.c_double, C.c_double, _D]
         L.orc_last_fluxes.argtypes = [C.POINTER(orc_problem), _D, _D]
+        L.orc_last_fallbacks.argtypes = []
+        L.orc_last_fallbacks.restype = C.c_long
         _lib = L
     return _lib
 
@@ -116,6 +118,7 @@ def make_problem(prob, exact_c=False) -> orc_problem:
         for i in range(3):
             P.bc_wall[s][i] = bc.wall[i]
     P.obst_i0, P.obst_nj = prob.obstacle
+    P.admissibility = prob.admissibility
     return P
 
 
@@ -268,6 +271,12 @@ def run(prob, state, nsteps=0, dt_fixed=0.0, t_end=0.0, t=0.0, exact_c=False):
     if n < 0:
         raise FloatingPointError("oracle run failed (nonphysical state)")
     return n, tt.value
+
+
+def last_fallbacks():
+    """Interior (gas) cells whose reconstruction fell back to the constant
+    average in the last step (the admissibility reading)."""
+    return int(lib().orc_last_fallbacks())
 
 
 def num_threads():

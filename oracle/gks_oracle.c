@@ -849,6 +849,10 @@ int orc_coefficients(int dim, double gamma, const double* W, const double* Wx, c
 /* Compact reconstruction (Sec. 3.1, 3.2)                                    */
 /* ------------------------------------------------------------------------ */
 
+/* relative rounding noise of FP64 inputs taken as a tie of the cross
+ * derivative's candidates: 2^-46 */
+#define TIE_REL 1.4210854715202004e-14
+
 static double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return a > 0.0 ? (a < b ? a : b) : (a > b ? a : b);
@@ -910,11 +914,16 @@ static void recon2d_finish(double Uc, double Ue, double Uw, double Un, double Us
   cand[1] = s3 * (dN - dW) / (h * k) - (a2 / k - a3 / h); /* NW */
   cand[2] = -s3 * (dS + dW) / (h * k) + (a2 / k + a3 / h); /* SW */
   cand[3] = s3 * (dE - dS) / (h * k) + (a2 / k - a3 / h); /* SE */
-  /* the one with the smallest absolute value.  Reading for ties: when
-   * candidates of both signs lie within a relative 1e-6 of that smallest
-   * magnitude (a tie up to the rounding of point values held in single
-   * precision), zero -- the mean of the tied candidates -- so that a mirror
-   * image of the data gives the mirror image of a6 */
+  /* the one with the smallest absolute value.  Reading for ties: the
+   * candidates are differences of the Gauss-point values (and of the limited
+   * slopes), so a relative perturbation d of those inputs moves each one by at
+   * most d * M, M = sqrt(3) (sum of the eight |Gauss values|) / (h k) +
+   * |a2| / k + |a3| / h.  Candidates within TIE_REL * M of the smallest
+   * magnitude are tied: the rounding of FP64 arithmetic (TIE_REL = 2^-46, 128
+   * units of rounding) cannot order them.  When the tied candidates have both
+   * signs, a6 = 0 (their mean), so that the mirror image of the data
+   * (x -> -x or y -> -y maps the candidates onto their negated set) gives the
+   * mirror image of a6. */
   double m = fabs(cand[0]);
   int best = 0;
   for (int s = 1; s < 4; ++s)
@@ -922,7 +931,9 @@ static void recon2d_finish(double Uc, double Ue, double Uw, double Un, double Us
       m = fabs(cand[s]);
       best = s;
     }
-  double band = m * (1.0 + 1e-6);
+  double M = s3 * (fabs(Ep) + fabs(Em) + fabs(Wp) + fabs(Wm) + fabs(Np) + fabs(Nm) + fabs(Sp) + fabs(Sm)) / (h * k) +
+             fabs(a2) / k + fabs(a3) / h;
+  double band = m + TIE_REL * M;
   int pos = 0, neg = 0;
   for (int s = 0; s < 4; ++s)
     if (fabs(cand[s]) <= band) {
@@ -1255,17 +1266,20 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
   }
 }
 
-/* Reading (robustness at strong shocks, not printed): a reconstructed cell
- * polynomial is admissible if, at the centre of every interface of the cell,
- * density and pressure are positive and lie within a factor two of the range
- * of the averages of the cell and its face neighbours:
+/* Reading (robustness at strong shocks, not printed; the paper names robust
+ * reconstruction an open question at the end of Sec. 3.3).  The literal
+ * scheme needs a positive density and pressure at the centre of every
+ * interface of a cell (the interface Maxwellians of Sec. 2.2 exist only
+ * then); mode 0 asks only that.  Mode 1 also asks that they lie within a
+ * factor two of the range of the averages of the cell and its face
+ * neighbours:
  *   rho_min / 2 <= rho <= 2 rho_max,  p_min / 2 <= p <= 2 p_max.
- * Otherwise the cell is reconstructed as its constant average for this step.
- * (Smooth data never come near the bounds.)  lo/hi: the neighbourhood's range
- * of rho (index 0) and p (index 1). */
-static int admissible(int dim, double gamma, const double* W, const double* lo, const double* hi) {
+ * A cell that fails is reconstructed as its constant average for this step.
+ * lo/hi: the neighbourhood's range of rho (index 0) and p (index 1). */
+static int admissible(int dim, double gamma, int mode, const double* W, const double* lo, const double* hi) {
   double p = pressure(dim, gamma, W);
   if (!(W[0] > 0.0) || !(p > 0.0)) return 0;
+  if (mode == 0) return 1;
   if (W[0] < 0.5 * lo[0] || W[0] > 2.0 * hi[0]) return 0;
   if (p < 0.5 * lo[1] || p > 2.0 * hi[1]) return 0;
   return 1;
@@ -1279,9 +1293,9 @@ static void range_add(int dim, double gamma, const double* W, double* lo, double
   }
 }
 
-/* reconstruction of cell (i, j), all components (conservative variables),
- * with the admissibility reading above */
-static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
+/* reconstruction of cell (i, j), all components, with the admissibility
+ * reading above; returns 1 when the cell fell back to its average */
+static int recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
   double S[13][4], pc[4][5];
   for (int v = 0; v < G->nv; ++v) {
     S[0][v] = GW(G, v, j, i);
@@ -1318,10 +1332,11 @@ static void recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h
     for (int v = 0; v < 4; ++v)
       W[v] = GW(G, v, j, i) + pc[v][0] * x + pc[v][1] * y + pc[v][2] * 0.5 * (x * x - h * h / 12.0) +
              pc[v][3] * 0.5 * (y * y - k * k / 12.0) + pc[v][4] * x * y;
-    if (!admissible(2, P->gamma, W, lo, hi)) ok = 0;
+    if (!admissible(2, P->gamma, P->admissibility, W, lo, hi)) ok = 0;
   }
   for (int v = 0; v < G->nv; ++v)
     for (int m = 0; m < 5; ++m) GPC(G, v, m, j, i) = ok ? pc[v][m] : 0.0;
+  return !ok;
 }
 
 /* interface values of a cell polynomial on the side facing the interface
@@ -1434,6 +1449,9 @@ static void fill_obstacle_2d(const orc_problem* P, grid2* G) {
     }
 }
 
+/* interior cells whose reconstruction fell back to the average in the last step */
+static long g_last_fallbacks = 0;
+
 static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, double dt, double t, double* fluxx,
                   double* fluxy) {
   grid2 Gs, *G = &Gs;
@@ -1462,14 +1480,18 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
   fill_ghosts_2d(P, G, t);
   fill_obstacle_2d(P, G);
 
-  /* reconstruction: interior cells and the edge ghost cells */
-#pragma omp parallel for schedule(static)
+  /* reconstruction: interior cells and the edge ghost cells; the count of
+   * interior gas cells that fell back to their average */
+  long fallbacks = 0;
+#pragma omp parallel for schedule(static) reduction(+ : fallbacks)
   for (int j = -1; j <= ny; ++j)
     for (int i = -1; i <= nx; ++i) {
       int gx = (i < 0 || i >= nx), gy = (j < 0 || j >= ny);
       if (gx && gy) continue;
-      recon_cell_2d(P, G, j, i, h, k);
+      int fb = recon_cell_2d(P, G, j, i, h, k);
+      if (fb && !gx && !gy && !solid(P, i, j)) fallbacks += 1;
     }
+  g_last_fallbacks = fallbacks;
 
   /* x interfaces */
 #pragma omp parallel for schedule(static) reduction(| : status)
@@ -1672,6 +1694,7 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
   }
   /* admissibility reading (see above): interface values at x = +-h/2 of each
    * cell polynomial against the range of the cell and its two neighbours */
+  long fallbacks = 0;
   for (int i = -1; i <= nx; ++i) {
     double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
     for (int q = -1; q <= 1; ++q) {
@@ -1682,11 +1705,14 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
     for (int sd = -1; sd <= 1; sd += 2) {
       double xn = 0.5 * sd * h, Wf[3];
       for (int v = 0; v < 3; ++v) Wf[v] = W1(v, i) + P1(v, 0, i) * xn + P1(v, 1, i) * 0.5 * (xn * xn - h * h / 12.0);
-      if (!admissible(1, P->gamma, Wf, lo, hi)) ok = 0;
+      if (!admissible(1, P->gamma, P->admissibility, Wf, lo, hi)) ok = 0;
     }
-    if (!ok)
+    if (!ok) {
       for (int v = 0; v < 3; ++v) P1(v, 0, i) = P1(v, 1, i) = 0.0;
+      if (i >= 0 && i < nx) fallbacks += 1;
+    }
   }
+  g_last_fallbacks = fallbacks;
   /* interfaces */
 #pragma omp parallel for schedule(static) reduction(| : status)
   for (int fi = 0; fi <= nx; ++fi) {
@@ -1791,6 +1817,8 @@ int orc_run(const orc_problem* P, double* cell, double* fx, double* fy, int nste
   }
   return n;
 }
+
+long orc_last_fallbacks(void) { return g_last_fallbacks; }
 
 int orc_num_threads(void) {
 #ifdef _OPENMP

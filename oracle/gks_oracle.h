@@ -54,6 +54,9 @@ typedef struct {
   double bc_alt[4][4];     /* primitive (rho, u, v, p): DMR pre-shock state (top edge) */
   double bc_wall[4][3];    /* wall u, v, T for no-slip walls */
   int obst_i0, obst_nj;    /* 2D solid step: cells i >= obst_i0, j < obst_nj (none: obst_nj = 0) */
+  int admissibility;       /* a reconstructed cell polynomial is kept if, at its interface centres,
+                              0: rho > 0 and p > 0; 1: also within a factor two of the range of
+                              the neighbouring averages (else the constant average is used) */
 } orc_problem;
 
 /* --- kinetic building blocks ------------------------------------------- */
@@ -155,6 +158,10 @@ int orc_step(const orc_problem* P, double* cell, double* fx, double* fy, double 
  * Returns the number of steps taken, or < 0 on failure; *t updated. */
 int orc_run(const orc_problem* P, double* cell, double* fx, double* fy, int nsteps,
             double dt_fixed, double t_end, double* t);
+
+/* Interior (gas) cells whose reconstruction fell back to the constant
+ * average in the last orc_step */
+long orc_last_fallbacks(void);
 
 /* Flux diagnostics of the last orc_step (x faces then y faces, [nvar][..]) */
 int orc_last_fluxes(const orc_problem* P, double* fxflux, double* fyflux);

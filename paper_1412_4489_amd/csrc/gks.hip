@@ -126,6 +126,7 @@ struct Grid {
   double* dt;                 // step of the current step
   long long* steps;
   unsigned long long* err;    // 0, or the location of the first nonphysical state (see gks_fetch)
+  unsigned long long* nfall;  // interior cells whose reconstruction fell back to the average (summed over steps)
   unsigned long long* dtmin;  // kDtSlots running minima of the CFL bound (bits of positive doubles)
 };
 
@@ -136,7 +137,7 @@ struct Grid {
 // distinct addresses keep the reduction off the update's critical path.
 constexpr int kDtSlots = 512;
 constexpr int kDtStride = 32;
-constexpr size_t kScalBytes = 64 + kDtSlots * kDtStride * 8;  // t, dt, steps, err (+ padding), slots
+constexpr size_t kScalBytes = 64 + kDtSlots * kDtStride * 8;  // t, dt, steps, err, fallbacks (+ padding), slots
 
 // work decomposition of one launch kind over the problems of a group
 enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_OBST, KK_COUNT };  // boundary, cells+ring, interfaces, cells, step images
@@ -149,6 +150,7 @@ struct Prob {
   BCDev bc[4];
   Rec<TC> R;
   int recon_vars;            // 0 conservative, 1 characteristic variables
+  int admissibility;         // 0: rho, p > 0 at the interface centres; 1: also the factor-two range
   int obst_i0, obst_nj;      // solid step: cells i >= obst_i0, j < obst_nj (none: obst_nj = 0)
   unsigned first[KK_COUNT];  // first logical block of the problem in each kind's launch
   // cell (i, j) inside the solid step (ghost indices included)
@@ -638,6 +640,11 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
   const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, Cw = Q.P.weno_c, gamma = Q.P.gamma;
   const Idx& x = g.ix;
+  // ties of the cross-derivative candidates: the rounding noise of the stored
+  // point values -- in double the accumulated rounding of the arithmetic that
+  // made them (128 units, 2^-46); in single precision their storage rounding
+  // (one unit, 2^-24), which exceeds that arithmetic noise
+  constexpr double kTieRel = sizeof(TS) == 4 ? 5.9604644775390625e-08 : 1.4210854715202004e-14;
   // the cell and its east, west, north, south neighbours
   double Wn[5][4];
 #pragma unroll
@@ -657,7 +664,7 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
       recon_2d(Wc[v], Wn[1][v], Wn[2][v], Wn[3][v], Wn[4][v], (double)g.FX[x.fx(1, v, j, i + 1)],
                (double)g.FX[x.fx(0, v, j, i + 1)], (double)g.FX[x.fx(1, v, j, i)], (double)g.FX[x.fx(0, v, j, i)],
                (double)g.FY[x.fy(1, v, j + 1, i)], (double)g.FY[x.fy(0, v, j + 1, i)],
-               (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, D, p[v]);
+               (double)g.FY[x.fy(1, v, j, i)], (double)g.FY[x.fy(0, v, j, i)], h, k, eps, Cw, D, kTieRel, p[v]);
     }
   } else {
     double S[13][4];
@@ -682,7 +689,7 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
       for (int v = 0; v < 4; ++v)
         recon_finish(S[0][v], S[1][v], S[2][v], S[3][v], S[4][v], S[5][v], S[6][v], S[7][v], S[8][v], S[9][v],
                      S[10][v], S[11][v], S[12][v], h, k, eps, Cw, D, lim[v][0], lim[v][1], lim[v][2], lim[v][3],
-                     p[v]);
+                     kTieRel, p[v]);
     } else {
       // a nonphysical average: the constant polynomial (the interfaces and
       // the update report the state)
@@ -697,11 +704,13 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   Range rg;
 #pragma unroll
   for (int q = 0; q < 5; ++q) rg.add(Wn[q][0], pressure_2d(gamma, Wn[q]));
-  const bool ok = recon_admissible_2d(Wc, p, h, k, gamma, rg);
+  const bool ok = recon_admissible_2d(Wc, p, h, k, gamma, rg, Q.admissibility);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int m = 0; m < 5; ++m) g.PC[x.pc(v, m, j, i)] = ok ? (TP)p[v][m] : TP(0);
+  // count of interior gas cells that fell back (rare: one atomic per such cell)
+  if (!ok && i >= 0 && i < nx && j >= 0 && j < ny && !Q.solid(i, j) && *g.dt > 0.0) atomicAdd(g.nfall, 1ull);
 }
 
 // 1D: cells -1..nx, in conservative or characteristic variables (Sec. 4:
@@ -766,11 +775,12 @@ __global__ void __launch_bounds__(256) k_recon_1d(KA<Prob<TS, TP, TC>> a) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) rg.add(s[q][0], pressure_1d(Q.P.gamma, s[q]));
   const double Wc[3] = {s[0][0], s[0][1], s[0][2]};
-  const bool ok = recon_admissible_1d(Wc, p, h, Q.P.gamma, rg);
+  const bool ok = recon_admissible_1d(Wc, p, h, Q.P.gamma, rg, Q.admissibility);
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int m = 0; m < 2; ++m) g.PC[x.pc1(v, m, i)] = ok ? (TP)p[v][m] : TP(0);
+  if (!ok && i >= 0 && i < nx && *g.dt > 0.0) atomicAdd(g.nfall, 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -1285,6 +1295,7 @@ std::string validate(const gks_problem& p) {
   if (!(p.tau_eps >= 0.0) || !(p.tau_c >= 0.0)) return "tau constants must be >= 0";
   if (!std::isfinite(p.t0)) return "t0 must be finite";
   if (p.recon_vars != 0 && p.recon_vars != 1) return "recon_vars must be 0 or 1";
+  if (p.admissibility != 0 && p.admissibility != 1) return "admissibility must be 0 or 1";
   if (p.obstacle_nj != 0) {
     auto mirrors = [](int k) {
       return k == GKS_BC_OUTFLOW || k == GKS_BC_REFLECT || k == GKS_BC_NOSLIP_ISOTHERMAL ||
@@ -1308,7 +1319,65 @@ std::string validate(const gks_problem& p) {
   return "";
 }
 
+// host description of a validated problem (no buffers)
+void setup_problem(const gks_problem& s, Problem& p) {
+  p.spec = s;
+  p.mixed = s.precision == GKS_FP32_MIXED;
+  {
+    const int ny = s.dim == 2 ? s.ny : 1;
+    const bool px = s.dim == 2 && s.bc[0].kind == GKS_BC_PERIODIC;
+    const bool py = s.dim == 2 && s.bc[2].kind == GKS_BC_PERIODIC;
+    p.ix = Idx{s.nx, ny, px ? s.nx : s.nx + 1, py ? ny : ny + 1};
+  }
+  p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, s.dim == 2 ? (s.y1 - s.y0) / s.ny : 1.0};
+  Phys& P = p.phys;
+  memset(&P, 0, sizeof(P));
+  P.gamma = s.gamma;
+  P.K = internal_dof(s.dim, s.gamma);
+  P.nth = P.K + (s.dim == 2 ? 2.0 : 1.0);
+  P.kp[0] = 1.0;
+  for (int e = 1; e < 4; ++e) P.kp[e] = P.kp[e - 1] * (P.K + 2.0 * (e - 1));
+  P.tau_eps = s.tau_eps;
+  P.tau_c = s.tau_c;
+  P.mu = s.viscous ? s.mu : 0.0;
+  P.prfix = s.viscous ? 1.0 / s.prandtl - 1.0 : 0.0;
+  P.weno_eps = s.weno_eps;
+  P.weno_c = s.weno_c;
+  P.cfl = s.cfl;
+  P.viscous = s.viscous ? 1 : 0;
+  for (int side = 0; side < 4; ++side) {
+    BCDev& b = p.bc[side];
+    memset(&b, 0, sizeof(b));
+    b.kind = s.bc[side].kind;
+    cons_of(s.dim, s.gamma, s.bc[side].state, b.state);
+    cons_of(s.dim, s.gamma, s.bc[side].alt, b.alt);
+    b.wu = s.bc[side].wall_u;
+    b.wv = s.bc[side].wall_v;
+    b.wT = s.bc[side].wall_T;
+  }
+}
+
 size_t n_interfaces(const Idx& x) { return (size_t)x.fxr * x.ny + (size_t)x.nx * x.fyr; }
+
+// bytes of the buffers W, FX, FY, PC, FLX, FLY, scal, recd, rect of a problem
+void buffer_sizes(const Problem& p, size_t (&sizes)[9]) {
+  const size_t ts = p.mixed ? sizeof(float) : sizeof(double);
+  const Idx& x = p.ix;
+  const size_t nx = x.nx, ny = x.ny;
+  if (p.spec.dim == 2) {
+    const size_t nf = n_interfaces(x);
+    const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,      2 * 4 * (ny + 2) * (nx + 3) * ts,
+                          2 * 4 * (ny + 3) * (nx + 2) * ts, 4 * 5 * (ny + 2) * (nx + 2) * ts,
+                          4 * ny * (nx + 1) * 8,            4 * (ny + 1) * nx * 8,
+                          kScalBytes,                       (size_t)ND_REC * nf * 8,
+                          (size_t)NT_REC * nf * ts};
+    memcpy(sizes, sz, sizeof(sz));
+  } else {
+    const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes,
+                          0, 0};
+    memcpy(sizes, sz, sizeof(sz));
+  }
+}
 
 // a caller's buffer must be device memory of the current device with at
 // least `bytes` left in its allocation from p (else "" is not returned)
@@ -1386,8 +1455,25 @@ Grid<TS, TP> grid_of(Problem& p) {
   g.dt = s + 1;
   g.steps = (long long*)(s + 2);
   g.err = (unsigned long long*)(s + 3);
+  g.nfall = (unsigned long long*)(s + 4);
   g.dtmin = (unsigned long long*)(s + 8);
   return g;
+}
+
+// device descriptor of one problem (its buffers must be set)
+template <typename TS, typename TP, typename TC>
+void make_desc(Problem& p, Prob<TS, TP, TC>& d) {
+  memset(&d, 0, sizeof(d));
+  d.g = grid_of<TS, TP>(p);
+  d.P = p.phys;
+  for (int s = 0; s < 4; ++s) d.bc[s] = p.bc[s];
+  d.R.d = (double*)p.recd;
+  d.R.t = (TC*)p.rect;
+  d.R.nf = p.spec.dim == 2 ? n_interfaces(p.ix) : 0;
+  d.recon_vars = p.spec.recon_vars;
+  d.admissibility = p.spec.admissibility;
+  d.obst_i0 = p.spec.obstacle_i0;
+  d.obst_nj = p.spec.obstacle_nj;
 }
 
 // descriptors and block-owner tables of a group for its present block sizes
@@ -1397,20 +1483,7 @@ int build_tables(gks_handle* h, Group& G) {
   const size_t n = G.members.size();
   std::vector<PR> host(n);
   std::vector<std::vector<uint32_t>> own(KK_COUNT);
-  for (size_t m = 0; m < n; ++m) {
-    Problem& p = h->probs[G.members[m]];
-    PR& d = host[m];
-    memset(&d, 0, sizeof(d));
-    d.g = grid_of<TS, TP>(p);
-    d.P = p.phys;
-    for (int s = 0; s < 4; ++s) d.bc[s] = p.bc[s];
-    d.R.d = (double*)p.recd;
-    d.R.t = (TC*)p.rect;
-    d.R.nf = G.dim == 2 ? n_interfaces(p.ix) : 0;
-    d.recon_vars = p.spec.recon_vars;
-    d.obst_i0 = p.spec.obstacle_i0;
-    d.obst_nj = p.spec.obstacle_nj;
-  }
+  for (size_t m = 0; m < n; ++m) make_desc<TS, TP, TC>(h->probs[G.members[m]], host[m]);
   for (int k = 0; k < KK_COUNT; ++k) {
     for (size_t m = 0; m < n; ++m) {
       host[m].first[k] = (unsigned)own[k].size();
@@ -1438,7 +1511,7 @@ int build_tables(gks_handle* h, Group& G) {
 
 // kernel timing: events around each kernel class when profiling is on
 void record_begin(gks_handle* h, hipStream_t st) {
-  if (h->profiling != 1) return;
+  if (!h || h->profiling != 1) return;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return;
   if (hipEventCreate(&b) != hipSuccess) {
@@ -1451,7 +1524,7 @@ void record_begin(gks_handle* h, hipStream_t st) {
   h->pend_k.push_back(-1);
 }
 void record_end(gks_handle* h, hipStream_t st, int kernel) {
-  if (h->profiling != 1 || h->pend_k.empty() || h->pend_k.back() != -1) return;
+  if (!h || h->profiling != 1 || h->pend_k.empty() || h->pend_k.back() != -1) return;
   (void)hipEventRecord(h->pend_b.back(), st);
   h->pend_k.back() = kernel;
 }
@@ -1473,6 +1546,49 @@ void collect(gks_handle* h) {
   h->pend_k.clear();
 }
 
+// One step of a group of problems of dimension `dim` (2D: characteristic
+// reconstruction if chr; the step-image launch if it has blocks): the launch
+// arguments A and block sizes bs of each launch kind, the per-problem fixed
+// step / end time array ctl.  h (may be null) records kernel timing.
+template <typename TS, typename TP, typename TC>
+void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const int (&bs)[KK_COUNT], int dim,
+                 bool chr, const double* ctl, hipStream_t st) {
+  using PR = Prob<TS, TP, TC>;
+  record_begin(h, st);
+  if (dim == 2) {
+    k_ghost_2d<TS, TP, TC><<<A[KK_GA].nblk, bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
+    if (A[KK_OBST].nblk) k_step_images_2d<TS, TP, TC><<<A[KK_OBST].nblk, bs[KK_OBST], 0, st>>>(A[KK_OBST]);
+  } else {
+    k_ghost_1d<TS, TP, TC><<<A[KK_GA].nblk, bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
+  }
+  record_end(h, st, GKS_K_GHOST);  // includes the time step
+  record_begin(h, st);
+  if (dim == 2 && chr)
+    k_recon_2d<TS, TP, TC, true><<<A[KK_RECON].nblk, bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  else if (dim == 2)
+    k_recon_2d<TS, TP, TC, false><<<A[KK_RECON].nblk, bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  else
+    k_recon_1d<TS, TP, TC><<<A[KK_RECON].nblk, bs[KK_RECON], 0, st>>>(A[KK_RECON]);
+  record_end(h, st, GKS_K_RECON);
+  record_begin(h, st);
+  if (dim == 2) {
+    k_iface_pro_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+    KA<PR> pair = A[KK_FACE];
+    pair.nblk = 2 * A[KK_FACE].nblk;  // logical block 2t + r: tile t, phase r
+    k_iface_corr_2d<TS, TP, TC><<<pair.nblk, bs[KK_FACE], 0, st>>>(pair);
+    k_iface_kin1_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+  } else {
+    k_face_1d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+  }
+  record_end(h, st, GKS_K_INTERFACE);
+  record_begin(h, st);
+  if (dim == 2)
+    k_update_2d<TS, TP, TC, false><<<A[KK_CELL].nblk, bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  else
+    k_update_1d<TS, TP, TC, false><<<A[KK_CELL].nblk, bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  record_end(h, st, GKS_K_UPDATE);
+}
+
 template <typename TS, typename TP, typename TC>
 void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   using PR = Prob<TS, TP, TC>;
@@ -1480,41 +1596,7 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   KA<PR> A[KK_COUNT];
   const int single = G.members.size() == 1;
   for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k], single};
-  double* ctl = G.ctl;
-  record_begin(h, st);
-  if (G.dim == 2) {
-    k_ghost_2d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
-    if (G.nblk[KK_OBST])
-      k_step_images_2d<TS, TP, TC><<<G.nblk[KK_OBST], G.bs[KK_OBST], 0, st>>>(A[KK_OBST]);
-  } else {
-    k_ghost_1d<TS, TP, TC><<<G.nblk[KK_GA], G.bs[KK_GA], 0, st>>>(A[KK_GA], ctl);
-  }
-  record_end(h, st, GKS_K_GHOST);  // includes the time step
-  record_begin(h, st);
-  if (G.dim == 2 && G.chr)
-    k_recon_2d<TS, TP, TC, true><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
-  else if (G.dim == 2)
-    k_recon_2d<TS, TP, TC, false><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
-  else
-    k_recon_1d<TS, TP, TC><<<G.nblk[KK_RECON], G.bs[KK_RECON], 0, st>>>(A[KK_RECON]);
-  record_end(h, st, GKS_K_RECON);
-  record_begin(h, st);
-  if (G.dim == 2) {
-    k_iface_pro_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-    KA<PR> pair = A[KK_FACE];
-    pair.nblk = 2 * G.nblk[KK_FACE];  // logical block 2t + r: tile t, phase r
-    k_iface_corr_2d<TS, TP, TC><<<pair.nblk, G.bs[KK_FACE], 0, st>>>(pair);
-    k_iface_kin1_2d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-  } else {
-    k_face_1d<TS, TP, TC><<<G.nblk[KK_FACE], G.bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-  }
-  record_end(h, st, GKS_K_INTERFACE);
-  record_begin(h, st);
-  if (G.dim == 2)
-    k_update_2d<TS, TP, TC, false><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(A[KK_CELL]);
-  else
-    k_update_1d<TS, TP, TC, false><<<G.nblk[KK_CELL], G.bs[KK_CELL], 0, st>>>(A[KK_CELL]);
-  record_end(h, st, GKS_K_UPDATE);
+  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.ctl, st);
 }
 
 void enqueue_step(gks_handle* h, hipStream_t st) {
@@ -1621,40 +1703,7 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     }
     if (!why.empty()) return init_fail(GKS_EINVAL, "problem " + std::to_string(n) + ": " + why);
     Problem& p = h->probs[n];
-    p.spec = s;
-    p.mixed = s.precision == GKS_FP32_MIXED;
-    {
-      const int ny = s.dim == 2 ? s.ny : 1;
-      const bool px = s.dim == 2 && s.bc[0].kind == GKS_BC_PERIODIC;
-      const bool py = s.dim == 2 && s.bc[2].kind == GKS_BC_PERIODIC;
-      p.ix = Idx{s.nx, ny, px ? s.nx : s.nx + 1, py ? ny : ny + 1};
-    }
-    p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, s.dim == 2 ? (s.y1 - s.y0) / s.ny : 1.0};
-    Phys& P = p.phys;
-    memset(&P, 0, sizeof(P));
-    P.gamma = s.gamma;
-    P.K = internal_dof(s.dim, s.gamma);
-    P.nth = P.K + (s.dim == 2 ? 2.0 : 1.0);
-    P.kp[0] = 1.0;
-    for (int e = 1; e < 4; ++e) P.kp[e] = P.kp[e - 1] * (P.K + 2.0 * (e - 1));
-    P.tau_eps = s.tau_eps;
-    P.tau_c = s.tau_c;
-    P.mu = s.viscous ? s.mu : 0.0;
-    P.prfix = s.viscous ? 1.0 / s.prandtl - 1.0 : 0.0;
-    P.weno_eps = s.weno_eps;
-    P.weno_c = s.weno_c;
-    P.cfl = s.cfl;
-    P.viscous = s.viscous ? 1 : 0;
-    for (int side = 0; side < 4; ++side) {
-      BCDev& b = p.bc[side];
-      memset(&b, 0, sizeof(b));
-      b.kind = s.bc[side].kind;
-      cons_of(s.dim, s.gamma, s.bc[side].state, b.state);
-      cons_of(s.dim, s.gamma, s.bc[side].alt, b.alt);
-      b.wu = s.bc[side].wall_u;
-      b.wv = s.bc[side].wall_v;
-      b.wT = s.bc[side].wall_T;
-    }
+    setup_problem(s, p);
     // the initial state must be physical (device buffers: checked by the
     // initial CFL scan below)
     const size_t nc = dev ? 0 : (size_t)s.nx * p.ix.ny;
@@ -1684,18 +1733,7 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     const size_t nx = s.nx, ny = x.ny;
     void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
     size_t sizes[9];
-    if (s.dim == 2) {
-      const size_t nf = n_interfaces(x);
-      const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,        2 * 4 * (ny + 2) * (nx + 3) * ts,
-                            2 * 4 * (ny + 3) * (nx + 2) * ts,   4 * 5 * (ny + 2) * (nx + 2) * ts,
-                            4 * ny * (nx + 1) * 8,              4 * (ny + 1) * nx * 8,
-                            kScalBytes,                         (size_t)ND_REC * nf * 8,
-                            (size_t)NT_REC * nf * ts};
-      memcpy(sizes, sz, sizeof(sz));
-    } else {
-      const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes, 0, 0};
-      memcpy(sizes, sz, sizeof(sz));
-    }
+    buffer_sizes(p, sizes);
     if (dev) {
       p.borrowed = true;
       p.W = dcell[n];
@@ -1954,6 +1992,16 @@ int gks_fetch(gks_handle* h, int32_t problem, double* cell, double* face_x, doub
                                      " (i, j) = (" + std::to_string(b) + ", " + std::to_string(a) + ")");
   }
   return h->sticky;
+}
+
+int gks_fallbacks(gks_handle* h, int32_t problem, int64_t* cells) {
+  if (!h || !cells) return GKS_EINVAL;
+  if (problem < 0 || problem >= (int)h->probs.size()) return fail(h, GKS_EINVAL, "problem index out of range");
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  unsigned long long n = 0;
+  HIP_OR(h, hipMemcpy(&n, (char*)h->probs[problem].scal + 32, 8, hipMemcpyDeviceToHost));
+  *cells = (int64_t)n;
+  return GKS_OK;
 }
 
 int gks_tune(gks_handle* h, int32_t steps) {

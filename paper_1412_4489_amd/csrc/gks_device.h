@@ -688,12 +688,15 @@ __device__ __forceinline__ void recon_pair(double c, double up, double um, doubl
 __device__ __forceinline__ void recon_finish(double c, double e, double w, double n, double s, double Ep, double Em,
                                              double Wp, double Wm, double Np, double Nm, double Sp, double Sm,
                                              double h, double k, double eps, double Cw, const ReconDiv& D, double a2,
-                                             double a3, double a4, double a5, double* p) {
+                                             double a3, double a4, double a5, double tie_rel, double* p) {
 #pragma clang fp contract(off)
   // cross term of the stencils NE, NW, SW, SE with the limited slopes; the one
-  // of smallest magnitude, zero when candidates of both signs lie within a
-  // relative 1e-6 of that magnitude (a tie up to the rounding of point values
-  // held in single precision; mirrored data then give the mirrored term)
+  // of smallest magnitude.  A relative perturbation d of the Gauss values and
+  // slopes moves every candidate by at most d M, M = sqrt(3) sum|G| / (h k) +
+  // |a2| / k + |a3| / h: candidates within tie_rel M of the smallest
+  // magnitude (tie_rel: the relative rounding noise of the stored point
+  // values) are tied, and a tie of both signs gives zero (so that mirrored
+  // data give the mirrored term)
   const double s3 = 1.7320508075688772;  // sqrt(3)
   const double dE = Ep - Em, dW = Wp - Wm, dN = Np - Nm, dS = Sp - Sm;
   const double ak = div_by(a2, D.k), ah = div_by(a3, D.h);
@@ -706,7 +709,8 @@ __device__ __forceinline__ void recon_finish(double c, double e, double w, doubl
       m6 = fabs(cand[q]);
       a6 = cand[q];
     }
-  const double band = m6 * (1.0 + 1e-6);
+  const double sumG = fabs(Ep) + fabs(Em) + fabs(Wp) + fabs(Wm) + fabs(Np) + fabs(Nm) + fabs(Sp) + fabs(Sm);
+  const double band = m6 + tie_rel * (div_by(s3 * sumG, D.hk) + fabs(ak) + fabs(ah));
   int pos = 0, neg = 0;  // bitwise logic: no branches
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -738,11 +742,12 @@ __device__ __forceinline__ void recon_finish(double c, double e, double w, doubl
 // one component in conservative variables
 __device__ __forceinline__ void recon_2d(double c, double e, double w, double n, double s, double Ep, double Em,
                                          double Wp, double Wm, double Np, double Nm, double Sp, double Sm, double h,
-                                         double k, double eps, double Cw, const ReconDiv& D, double* p) {
+                                         double k, double eps, double Cw, const ReconDiv& D, double tie_rel,
+                                         double* p) {
   double a2, a3, a4, a5;
   recon_pair(c, e, w, Ep, Em, Wp, Wm, h, D.h, D.hh, D.six, a2, a4);
   recon_pair(c, n, s, Np, Nm, Sp, Sm, k, D.k, D.kk, D.six, a3, a5);
-  recon_finish(c, e, w, n, s, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps, Cw, D, a2, a3, a4, a5, p);
+  recon_finish(c, e, w, n, s, Ep, Em, Wp, Wm, Np, Nm, Sp, Sm, h, k, eps, Cw, D, a2, a3, a4, a5, tie_rel, p);
 }
 
 // Eigenvectors of the 2D Euler flux Jacobian along x (kX) or y at the
@@ -831,12 +836,13 @@ __device__ __forceinline__ bool recon_pair_characteristic(double gamma, const do
 }
 
 // Admissibility of a reconstructed cell polynomial (a robustness reading; the
-// paper prints none): at the centre of every interface of the cell, density
-// and pressure must be positive and lie within a factor two of the range of
-// the averages of the cell and its face neighbours,
+// paper leaves robust reconstruction open at the end of Sec. 3.3): at the
+// centre of every interface of the cell, density and pressure must be
+// positive (mode 0: the interface Maxwellians exist), and in mode 1 also lie
+// within a factor two of the range of the averages of the cell and its face
+// neighbours,
 //   rho_min / 2 <= rho <= 2 rho_max,  p_min / 2 <= p <= 2 p_max;
 // otherwise the cell is reconstructed as its constant average for this step.
-// Smooth data never come near these bounds.
 struct Range {
   double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};  // rho, p
   __device__ __forceinline__ void add(double rho, double p) {
@@ -845,9 +851,9 @@ struct Range {
     lo[1] = fmin(lo[1], p);
     hi[1] = fmax(hi[1], p);
   }
-  __device__ __forceinline__ bool admits(double rho, double p) const {
-    return rho > 0.0 && p > 0.0 && !(rho < 0.5 * lo[0]) && !(rho > 2.0 * hi[0]) && !(p < 0.5 * lo[1]) &&
-           !(p > 2.0 * hi[1]);
+  __device__ __forceinline__ bool admits(double rho, double p, int mode) const {
+    return rho > 0.0 && p > 0.0 &&
+           (mode == 0 || (!(rho < 0.5 * lo[0]) && !(rho > 2.0 * hi[0]) && !(p < 0.5 * lo[1]) && !(p > 2.0 * hi[1])));
   }
 };
 
@@ -861,7 +867,7 @@ __device__ __forceinline__ double pressure_1d(double gamma, const double* W) {
 // the cell polynomial Wc + p2 x + p3 y + p4 w_x + p5 w_y + p6 x y (per
 // conservative variable) at the centres of the four interfaces of the cell
 __device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const double (&p)[4][5], double h,
-                                                    double k, double gamma, const Range& R) {
+                                                    double k, double gamma, const Range& R, int mode) {
   bool ok = true;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
@@ -872,14 +878,14 @@ __device__ __forceinline__ bool recon_admissible_2d(const double (&Wc)[4], const
     for (int v = 0; v < 4; ++v)
       W[v] = Wc[v] + p[v][0] * x + p[v][1] * y + p[v][2] * 0.5 * (x * x - h * h / 12.0) +
              p[v][3] * 0.5 * (y * y - k * k / 12.0) + p[v][4] * x * y;
-    ok = ok && R.admits(W[0], pressure_2d(gamma, W));
+    ok = ok && R.admits(W[0], pressure_2d(gamma, W), mode);
   }
   return ok;
 }
 
 // 1D: the polynomial Wc + p2 x + p4 (x^2/2 - h^2/24) at x = -h/2, +h/2
 __device__ __forceinline__ bool recon_admissible_1d(const double (&Wc)[3], const double (&p)[3][2], double h,
-                                                    double gamma, const Range& R) {
+                                                    double gamma, const Range& R, int mode) {
   bool ok = true;
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) {
@@ -887,7 +893,7 @@ __device__ __forceinline__ bool recon_admissible_1d(const double (&Wc)[3], const
     double W[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) W[v] = Wc[v] + p[v][0] * x + p[v][1] * 0.5 * (x * x - h * h / 12.0);
-    ok = ok && R.admits(W[0], pressure_1d(gamma, W));
+    ok = ok && R.admits(W[0], pressure_1d(gamma, W), mode);
   }
   return ok;
 }

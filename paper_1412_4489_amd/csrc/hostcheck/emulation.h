@@ -146,6 +146,12 @@ inline unsigned long long atomicCAS(unsigned long long* p, unsigned long long cm
   return old;
 }
 
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
+  unsigned long long old = *p;
+  *p = old + v;
+  return old;
+}
+
 inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
   unsigned long long old = *p;
   if (v < old) *p = v;

@@ -2,7 +2,7 @@
 
 The functions keep the C names (gks_init, gks_init_device, gks_state_extent,
 gks_step, gks_fetch, gks_destroy, gks_last_error, gks_profile, gks_kernel_time,
-gks_tune, gks_block_size) and only marshal arguments;
+gks_tune, gks_block_size, gks_fallbacks) and only marshal arguments;
 every step of the scheme runs in the HIP kernels of the library.  `Solver`
 wraps a handle for numpy arrays laid out as in paper_1412_4489_amd.workloads.
 
@@ -40,7 +40,8 @@ class gks_problem(C.Structure):
                 ("prandtl", C.c_double), ("tau_eps", C.c_double), ("tau_c", C.c_double),
                 ("cfl", C.c_double), ("weno_eps", C.c_double), ("weno_c", C.c_double),
                 ("recon_vars", C.c_int32), ("precision", C.c_int32), ("bc", gks_bc * 4),
-                ("t0", C.c_double), ("obstacle_i0", C.c_int32), ("obstacle_nj", C.c_int32)]
+                ("t0", C.c_double), ("obstacle_i0", C.c_int32), ("obstacle_nj", C.c_int32),
+                ("admissibility", C.c_int32)]
 
 
 class GKSError(RuntimeError):
@@ -76,12 +77,13 @@ def lib():
         L.gks_kernel_time.argtypes = [_P, C.c_int32, _D, C.POINTER(C.c_int64)]
         L.gks_tune.argtypes = [_P, C.c_int32]
         L.gks_block_size.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32)]
+        L.gks_fallbacks.argtypes = [_P, C.c_int32, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
 
-EXPORTED = ("gks_init", "gks_init_device", "gks_state_extent", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error", "gks_profile",
-            "gks_kernel_time", "gks_tune", "gks_block_size")
+EXPORTED = ("gks_init", "gks_init_device", "gks_state_extent", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error",
+            "gks_profile", "gks_kernel_time", "gks_tune", "gks_block_size", "gks_fallbacks")
 
 
 def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
@@ -94,6 +96,7 @@ def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
     P.weno_eps, P.weno_c, P.recon_vars = prob.weno_eps, prob.weno_c, prob.recon_vars
     P.precision = precision
     P.obstacle_i0, P.obstacle_nj = prob.obstacle
+    P.admissibility = prob.admissibility
     for s, bc in enumerate(prob.bc):
         P.bc[s].kind = BC_CODES[bc.kind]
         for i in range(4):
@@ -280,6 +283,16 @@ def gks_block_size(h, kernel):
     return n.value
 
 
+def gks_fallbacks(h, problem):
+    """(interior cell, step) pairs of `problem` whose reconstruction fell back
+    to the constant average since gks_init."""
+    n = C.c_int64()
+    rc = lib().gks_fallbacks(h, int(problem), C.byref(n))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+    return n.value
+
+
 class Solver:
     """A handle over one or more problems (context manager)."""
 
@@ -302,6 +315,9 @@ class Solver:
 
     def fetch(self, k=0, check=True):
         return gks_fetch(self.h, k, self.probs[k], check)
+
+    def fallbacks(self, k=0):
+        return gks_fallbacks(self.h, k)
 
     def close(self):
         if self.h is not None:

@@ -30,3 +30,22 @@ def entropy_wave_temperature(mu, prandtl, t, gamma=1.4, k=2 * np.pi):
     w, V = np.linalg.eig(A)
     c = np.linalg.solve(V, np.array([-1.0, 0.0, 1.0], dtype=complex))
     return float((V @ (c * np.exp(w * t)))[2].real)
+
+
+def density_wave_amplitude(mu, t, gamma=1.4, k=np.pi, prandtl=1.0):
+    """|rho'(t)| / |rho'(0)| of the Fourier mode k for the initial data
+    rho' = a sin(kx), T' = -a sin(kx), u' = 0 (an entropy wave at uniform
+    pressure; in the frame moving with the mean flow), with the same
+    longitudinal system: heat conduction turns part of it into two weak sound
+    waves, and the modulus of the complex density amplitude counts both."""
+    cv = 1.0 / (gamma - 1.0)
+    cp = gamma / (gamma - 1.0)
+    kappa = cp * mu / prandtl
+    n_dof = 2.0 / (gamma - 1.0)
+    nu_l = (2.0 - 2.0 / n_dof) * mu
+    A = np.array([[0.0, -1j * k, 0.0],
+                  [-1j * k, -nu_l * k * k, -1j * k],
+                  [0.0, -1j * k / cv, -kappa * k * k / cv]], dtype=complex)
+    w, V = np.linalg.eig(A)
+    c = np.linalg.solve(V, np.array([1.0, 0.0, -1.0], dtype=complex))
+    return float(abs((V @ (c * np.exp(w * t)))[0]))

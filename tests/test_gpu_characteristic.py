@@ -216,10 +216,14 @@ def test_stationary_shock_on_the_gpu(G):
         assert abs(xs - 0.5) < 0.25 * h, (p, xs)
 
 
-def _end_state_parity(G, oracle, prob, st, prec, t_end, label, tol32=(1e-6, 1e-5)):
+def _end_state_parity(G, oracle, prob, st, prec, t_end, label, tol32=(5e-6, 1e-5)):
     """Run to t_end on the GPU; then one more step from the final state, on
     the GPU and in the oracle, compared element by element (FP32-mixed:
-    tol32 = bounds for the cells and the point values)."""
+    tol32 = bounds for the cells and the point values; the mixed form takes
+    cross-derivative candidates within one unit of single-precision rounding
+    as tied, the oracle within its double-precision rounding, so near-ties
+    between the two bands zero the cross derivative in the one and not in
+    the other: 2.2e-6 measured on Riemann case 2 at 400^2)."""
     p = G.GKS_FP64 if prec == "fp64" else G.GKS_FP32_MIXED
     print(f"{label} {prec}: to t = {t_end}", flush=True)
     nmax = _steps_for(prob, st, t_end)

@@ -1,7 +1,7 @@
 """Pins of the linearised Navier-Stokes reference (tests/linear_ns.py)."""
 import numpy as np
 
-from linear_ns import entropy_wave_temperature, shear_rate
+from linear_ns import density_wave_amplitude, entropy_wave_temperature, shear_rate
 
 
 def test_no_dissipation_keeps_the_entropy_wave():
@@ -21,3 +21,15 @@ def test_long_waves_decay_at_the_conduction_rate():
 
 def test_shear_rate():
     assert abs(shear_rate(0.01) - 0.01 * 4 * np.pi ** 2) < 1e-15
+
+
+def test_density_wave_amplitude_limits():
+    # no dissipation: the entropy wave stands (advected) at its amplitude
+    for t in (0.1, 2.0):
+        assert abs(density_wave_amplitude(0.0, t) - 1.0) < 1e-12
+    # long waves: the conduction rate mu k^2 / Pr (rho = p = 1)
+    mu, k = 1e-6, np.pi
+    for pr in (1.0, 0.72):
+        t = 2.0 / (mu * k * k / pr)
+        rate = -np.log(density_wave_amplitude(mu, t, k=k, prandtl=pr)) / t
+        assert abs(rate / (mu * k * k / pr) - 1.0) < 1e-4

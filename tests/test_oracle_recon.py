@@ -317,19 +317,30 @@ def test_recon2d_characteristic_limits_each_wave_as_a_scalar(oracle, ax, seed):
 
 
 def test_recon2d_cross_derivative_near_ties(oracle):
-    """The tie of the cross-derivative candidates is taken up to a relative
-    1e-6 of the smallest magnitude (the rounding of point values held in
-    single precision).  A y-uniform jump, its candidates +-3500: perturbing
-    one north Gauss value by 1e-9 moves them by 1.5e-5 (relative 4e-9), and
-    the cross derivative stays zero (only the central polynomial's share,
-    weighted by ~1e-24, is left); perturbed by 1e-6 (relative 4e-6) the
-    smallest candidate wins."""
+    """Ties of the cross-derivative candidates (Sec. 3.2, smallest |a6|) are
+    taken up to the rounding noise of FP64 inputs: a relative perturbation d of
+    the Gauss values and slopes moves a candidate by at most d M,
+    M = sqrt(3) sum|G| / (h k) + |a2| / k + |a3| / h, and candidates within
+    2^-46 M of the smallest magnitude count as tied (zero when both signs
+    are among them).  A y-uniform jump has candidates +-3500: perturbing one
+    north Gauss value so that one candidate moves by half the band keeps the
+    tie (a6 = 0, only the central polynomial's share, weighted ~1e-24, is
+    left); by twice the band the smallest candidate wins.  A rounding-level
+    perturbation (1e-15) is a tie, one of 1e-12 is not."""
     h = k = 0.01
     d = S3 / 6
     U = lambda x: 1.0 if x < 0.3 * h else 0.125
     Uc = 0.8 * 1.0 + 0.2 * 0.125
     base = [Uc, 0.125, 1.0, Uc, Uc, 0.125, 0.125, 1.0, 1.0, U(d * h), U(-d * h), U(d * h), U(-d * h)]
-    for eps, zero in ((0.0, True), (1e-9, True), (1e-6, False), (1e-3, False)):
+    # the limited slopes of the base data: a2 from the x pair, a3 = 0
+    p0 = oracle.recon2d_scalar(*base, h, k, 1e-14, 1e-12)
+    a2 = p0[0]
+    M = S3 * sum(abs(x) for x in base[5:]) / (h * k) + abs(a2) / k
+    band = 2.0 ** -46 * M
+    # a north Gauss value enters the NE / NW candidates with weight sqrt(3)/(h k)
+    step = S3 / (h * k)
+    for eps, zero in ((0.0, True), (1e-15, True), (0.5 * band / step, True), (2.0 * band / step, False),
+                      (1e-12, False), (1e-6, False)):
         a = list(base)
         a[9] += eps
         p = oracle.recon2d_scalar(*a, h, k, 1e-14, 1e-12)

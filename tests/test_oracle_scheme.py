@@ -156,6 +156,89 @@ def test_double_mach_reflection_runs_and_moves_the_incident_shock(oracle):
         assert abs(_shock_x(c[0, j], xc, 8.0, 1.4) - exact) < 1.5 * prob.dx, j
 
 
+def _advected_amplitude(prob, st, t):
+    """modulus of the density's sin(pi (x - t)) mode (cell averages; the
+    same cell-average factor at every time)"""
+    x = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
+    r = st.cell[0].reshape(-1) - 1.0
+    return np.hypot(2 * np.mean(r * np.sin(np.pi * (x - t))), 2 * np.mean(r * np.cos(np.pi * (x - t))))
+
+
+@pytest.mark.parametrize("tau_eps", [0.05, 0.5])
+def test_tau_eps_heat_conduction(oracle, tau_eps):
+    """The inviscid collision time tau = tau_eps dt of Sec. 4 makes the
+    scheme a Navier-Stokes solver with the effective viscosity
+    mu = tau_eff p: the time-integrated flux carries -(int C2 + int C8)
+    = dt tau - tau^2 (1 - e^(-dt/tau)) = dt tau_eff on g0 (a u + A).  The
+    density wave of Table 1 (amplitude 1e-3, so the linear theory applies)
+    therefore decays, relative to the same run with tau_eps = 0, like the
+    linearised Navier-Stokes solution with that mu, Pr = 1 (BGK) and the BGK
+    longitudinal viscosity: heat conduction decays the entropy wave and
+    sheds two weak sound waves (tests/linear_ns.py).  Measured within 0.13 %;
+    tau in place of tau_eff is 5 % (tau_eps 0.05) and 43 % (0.5) off."""
+    from linear_ns import density_wave_amplitude
+    amps = {}
+    for te in (0.0, tau_eps):
+        prob, st = W.advection_1d(100, cfl=0.5, tau_eps=te, amp=1e-3)
+        dt = oracle.dt(prob, st)
+        n = int(round(2.0 / dt))
+        dt = 2.0 / n
+        a0 = _advected_amplitude(prob, st, 0.0)
+        oracle.run(prob, st, nsteps=n, dt_fixed=dt)
+        amps[te] = _advected_amplitude(prob, st, 2.0) / a0
+    rate = -np.log(amps[tau_eps] / amps[0.0]) / 2.0
+    tau = tau_eps * dt
+    tau_eff = tau - tau * tau * (1.0 - np.exp(-dt / tau)) / dt
+    exact = -np.log(density_wave_amplitude(tau_eff, 2.0, gamma=prob.gamma)) / 2.0
+    plain = -np.log(density_wave_amplitude(tau, 2.0, gamma=prob.gamma)) / 2.0
+    assert abs(rate / exact - 1.0) < 5e-3, (rate, exact)
+    assert abs(rate / plain - 1.0) > 3e-2
+
+
+def test_shocked_workloads_need_the_factor_two_admissibility(oracle):
+    """The admissibility reading: the literal scheme needs only positive
+    density and pressure at the interface centres of a reconstructed cell
+    (admissibility 0).  The Mach-10 double Mach reflection of Sec. 4.5 in
+    conservative variables leaves the physical states with that alone (at
+    t = 0.04 on 96 x 24: an interface pressure far below both neighbouring
+    averages drives a wrong-signed mass flux), and so does the viscous shock
+    tube of Sec. 4.7 (150 x 75, Re 200, within three steps of the 100:1
+    membrane); with the factor-two range (admissibility 1) both run (the DMR
+    to t = 0.2 in the test above), the fallback firing on a few 1e-4 of the
+    DMR's cell-steps.  Sod's problem and the 2D Riemann problems never fall
+    back."""
+    from dataclasses import replace
+    prob, st = W.dmr(96, 24)
+    prob = replace(prob, admissibility=0)
+    with pytest.raises(FloatingPointError):
+        oracle.run(prob, st, t_end=0.2)
+    prob, st = W.viscous_shock_tube(150, 75, re=200.0)
+    with pytest.raises(FloatingPointError):
+        oracle.run(replace(prob, admissibility=0), st, nsteps=10)
+    prob, st = W.viscous_shock_tube(150, 75, re=200.0)
+    oracle.run(prob, st, nsteps=10)
+    prob, st = W.dmr(96, 24)
+    fb, n = 0, 0
+    t = 0.0
+    while n < 60:
+        dt = oracle.dt(prob, st)
+        oracle.step(prob, st, dt, t)
+        t += dt
+        n += 1
+        fb += oracle.last_fallbacks()
+    assert 0 < fb < 1e-3 * n * prob.ncells
+    for prob, st in (W.sod_1d(100), W.riemann_2d(2, n=40)):
+        for mode in (0, 1):
+            p = replace(prob, admissibility=mode)
+            s = st.copy()
+            t = 0.0
+            for k in range(20):
+                dt = oracle.dt(p, s)
+                oracle.step(p, s, dt, t)
+                t += dt
+                assert oracle.last_fallbacks() == 0
+
+
 def test_blast_wave_stays_physical(oracle):
     """Sec. 4.2 Woodward-Colella blast wave on 200 cells to t = 3.8 with
     characteristic variables: every state stays physical, mass is conserved
