@@ -175,6 +175,40 @@ int gks_init_device(gks_handle** out, int32_t n_problems, const gks_problem* pro
                     void* const* d_cell, void* const* d_face_x, void* const* d_face_y,
                     void* stream);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): nsteps steps of one problem on caller-owned device buffers in
+ * the layouts of gks_init_device (d_cell, d_face_x, d_face_y: stepped in
+ * place; periodic seams overwritten as there), without a handle and without
+ * any allocation.  Every internal buffer lives in one static device array of
+ * 128 MiB per GPU (held by each GPU the library runs on until the process
+ * ends); a problem that needs more is refused with GKS_EINVAL before any
+ * device work (about 1.2 kB per cell in GKS_FP64 and 0.8 kB in
+ * GKS_FP32_MIXED: 320^2 and 400^2 cells fit).  All calls on one GPU share
+ * that array, which keeps the last call's contents (each call initialises
+ * what it reads): calls that overlap on one GPU (other host threads, other
+ * streams) race and must not be made.  The work is enqueued on `stream`
+ * (a borrowed hipStream_t; NULL: the null stream) and the call returns
+ * without waiting, so it may be captured into a graph.  prob->t0 is the
+ * initial time; dt_fixed > 0 fixes the step (0: the CFL condition on the
+ * device every step); t_end > 0 shortens the last step to end there (0:
+ * none).  d_status (device memory, may be NULL) receives after the last step
+ * the time, the step count, the error word (0, or nonzero once a step made a
+ * nonphysical state, or when the initial state is nonphysical; later steps
+ * then leave the problem unchanged) and the fallback count (see
+ * gks_fallbacks).  The same kernels as gks_step give the same results as a
+ * handle made by gks_init_device from the same buffers and stepped with the
+ * same arguments.  Returns GKS_EINVAL (gks_last_error(NULL) says why) or
+ * GKS_EDEVICE. */
+typedef struct {
+  double t;
+  int64_t steps;
+  uint64_t error;
+  int64_t fallbacks;
+} gks_noalloc_status;
+int gks_step_noalloc(const gks_problem* prob, void* d_cell, void* d_face_x, void* d_face_y, int32_t nsteps,
+                     double dt_fixed, double t_end, gks_noalloc_status* d_status, void* stream);
+
 /* Element counts of the three device buffers of gks_init_device for one
  * problem, and the size in bytes of a face element (8 or 4).  Host-only: no
  * device call.  Any output pointer may be NULL.  GKS_EINVAL for an

@@ -39,6 +39,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1857,6 +1858,118 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
   return GKS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free stepping of one problem (gks_step_noalloc): every internal
+// buffer (descriptor, controls, scalars, reconstruction coefficients,
+// fluxes, frame record) lives in one static device array per GPU.  Host code
+// reaches that array only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(128) << 20;  // per GPU, held until the process ends
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch array (looked up once per
+// device)
+int scratch_base(void** out, std::string* why) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *why = "no usable current device";
+    return GKS_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *why = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return GKS_EDEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GKS_OK;
+}
+
+// the descriptor, the controls and the scalars of the step (time t0, no
+// error, no fallbacks, empty CFL slots); one block
+template <class PR>
+__global__ void __launch_bounds__(256) k_noalloc_setup(PR desc, PR* dst, double* ctl, double fixed, double t_end,
+                                                      double t0) {
+  if (threadIdx.x == 0) {
+    *dst = desc;
+    ctl[0] = fixed;
+    ctl[1] = t_end;
+    *desc.g.t = t0;
+    *desc.g.dt = 0.0;
+    *desc.g.steps = 0;
+    *desc.g.err = 0;
+    *desc.g.nfall = 0;
+  }
+  for (int q = threadIdx.x; q < kDtSlots; q += blockDim.x)
+    desc.g.dtmin[q * kDtStride] = (unsigned long long)__double_as_longlong(1e300);
+}
+
+// periodic seams of the caller's point values: the last interface of a row
+// (column) takes the first one's values, over the whole ghosted extent
+template <typename TS>
+__global__ void __launch_bounds__(256) k_noalloc_seams(TS* FX, TS* FY, int nx, int ny, int px, int py) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px && id < 8 * (ny + 2)) {
+    TS* row = FX + (size_t)id * (nx + 3);  // plane (g, v) and padded row of FX
+    row[nx + 1] = row[1];
+  }
+  if (py && id < 8 * (nx + 2)) {
+    const int pl = id / (nx + 2), c = id % (nx + 2);
+    TS* plane = FY + (size_t)pl * (ny + 3) * (nx + 2);
+    plane[(size_t)(ny + 1) * (nx + 2) + c] = plane[(size_t)(nx + 2) + c];
+  }
+}
+
+// time, steps, error word and fallback count after the last step
+template <class PR>
+__global__ void k_noalloc_status(const PR* d, gks_noalloc_status* out) {
+  out->t = *d->g.t;
+  out->steps = (int64_t)*d->g.steps;
+  out->error = (uint64_t)*d->g.err;
+  out->fallbacks = (int64_t)*d->g.nfall;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+template <typename TS, typename TP, typename TC>
+int noalloc_run(Problem& p, char* base, int32_t nsteps, double dt_fixed, double t_end, gks_noalloc_status* status,
+                hipStream_t st) {
+  using PR = Prob<TS, TP, TC>;
+  const int dim = p.spec.dim;
+  PR desc;
+  make_desc<TS, TP, TC>(p, desc);
+  PR* dprob = (PR*)(base);
+  double* ctl = (double*)(base + align256(sizeof(PR)));
+  k_noalloc_setup<PR><<<1, 256, 0, st>>>(desc, dprob, ctl, dt_fixed, t_end, p.spec.t0);
+  if (dim == 2 && (p.ix.fxr == p.ix.nx || p.ix.fyr == p.ix.ny)) {
+    const int n = 8 * ((p.ix.nx > p.ix.ny ? p.ix.nx : p.ix.ny) + 2);
+    k_noalloc_seams<TS><<<cdiv((size_t)n, 256), 256, 0, st>>>((TS*)p.FX, (TS*)p.FY, p.ix.nx, p.ix.ny,
+                                                               p.ix.fxr == p.ix.nx, p.ix.fyr == p.ix.ny);
+  }
+  const int bs[KK_COUNT] = {256, 256, 256, 256, 64};
+  KA<PR> A[KK_COUNT];
+  for (int k = 0; k < KK_COUNT; ++k)
+    A[k] = KA<PR>{dprob, nullptr, cdiv(work_items(p, dim, k), (size_t)bs[k]), 1};
+  // CFL bound of the initial state (and its nonphysical-cell check)
+  if (dim == 2)
+    k_update_2d<TS, TP, TC, true><<<A[KK_CELL].nblk, bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  else
+    k_update_1d<TS, TP, TC, true><<<A[KK_CELL].nblk, bs[KK_CELL], 0, st>>>(A[KK_CELL]);
+  const bool chr = dim == 2 && p.spec.recon_vars == 1;
+  for (int32_t n = 0; n < nsteps; ++n) launch_step<TS, TP, TC>(nullptr, A, bs, dim, chr, ctl, st);
+  if (status) k_noalloc_status<PR><<<1, 1, 0, st>>>(dprob, status);
+  return hipGetLastError() == hipSuccess ? GKS_OK : GKS_EDEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1874,6 +1987,67 @@ int gks_init_device(gks_handle** out, int32_t n_problems, const gks_problem* pro
     return GKS_EINVAL;
   }
   return init_handle(out, n_problems, probs, nullptr, nullptr, nullptr, d_cell, d_face_x, d_face_y, stream);
+}
+
+int gks_step_noalloc(const gks_problem* prob, void* d_cell, void* d_face_x, void* d_face_y, int32_t nsteps,
+                     double dt_fixed, double t_end, gks_noalloc_status* d_status, void* stream) {
+  g_init_msg.clear();
+  if (!prob || !d_cell || !d_face_x || (prob->dim == 2 && !d_face_y)) {
+    g_init_msg = "prob, d_cell, d_face_x (and d_face_y in 2D) must be given";
+    return GKS_EINVAL;
+  }
+  std::string why = validate(*prob);
+  if (why.empty() && nsteps < 0) why = "nsteps < 0";
+  if (why.empty() && !(dt_fixed >= 0.0 && std::isfinite(dt_fixed))) why = "dt_fixed must be >= 0 and finite";
+  if (why.empty() && !(t_end >= 0.0 && std::isfinite(t_end))) why = "t_end must be >= 0 and finite";
+  const size_t fe = prob->precision == GKS_FP32_MIXED ? 4 : 8;
+  size_t e[3] = {0, 0, 0};
+  if (why.empty()) {
+    state_elems(*prob, e);
+    if ((uintptr_t)d_cell % 8 || (uintptr_t)d_face_x % fe || (prob->dim == 2 && (uintptr_t)d_face_y % fe))
+      why = "device buffers must be aligned to their element size";
+  }
+  if (why.empty()) why = check_device_buffer("d_cell", d_cell, e[0] * 8);
+  if (why.empty()) why = check_device_buffer("d_face_x", d_face_x, e[1] * fe);
+  if (why.empty() && prob->dim == 2) why = check_device_buffer("d_face_y", d_face_y, e[2] * fe);
+  if (why.empty() && d_status) why = check_device_buffer("d_status", d_status, sizeof(gks_noalloc_status));
+  if (!why.empty()) {
+    g_init_msg = why;
+    return GKS_EINVAL;
+  }
+  Problem p;
+  setup_problem(*prob, p);
+  p.W = d_cell;
+  p.FX = d_face_x;
+  p.FY = prob->dim == 2 ? d_face_y : nullptr;
+  // the scratch layout: descriptor, controls, then the internal buffers
+  size_t sizes[9];
+  buffer_sizes(p, sizes);
+  const size_t head = align256(sizeof(Prob<double, double, double>)) + 256;
+  size_t need = head;
+  for (int b = 3; b < 9; ++b) need += align256(sizes[b]);
+  if (need > kScratchBytes) {
+    g_init_msg = "the problem needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                 std::to_string(kScratchBytes);
+    return GKS_EINVAL;
+  }
+  void* base = nullptr;
+  const int rc = scratch_base(&base, &why);
+  if (rc != GKS_OK) {
+    g_init_msg = why;
+    return rc;
+  }
+  void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
+  size_t off = head;
+  for (int b = 3; b < 9; ++b) {
+    *bufs[b] = sizes[b] ? (char*)base + off : nullptr;
+    off += align256(sizes[b]);
+  }
+  const hipStream_t st = (hipStream_t)stream;
+  const int r = p.mixed ? noalloc_run<float, float, float>(p, (char*)base, nsteps, dt_fixed, t_end, d_status, st)
+                        : noalloc_run<double, double, double>(p, (char*)base, nsteps, dt_fixed, t_end, d_status, st);
+  if (r != GKS_OK) g_init_msg = "kernel launch failed";
+  return r;
 }
 
 int gks_state_extent(const gks_problem* prob, int64_t* cell_elems, int64_t* face_x_elems, int64_t* face_y_elems,

@@ -2,7 +2,8 @@
 
 The functions keep the C names (gks_init, gks_init_device, gks_state_extent,
 gks_step, gks_fetch, gks_destroy, gks_last_error, gks_profile, gks_kernel_time,
-gks_tune, gks_block_size, gks_fallbacks) and only marshal arguments;
+gks_tune, gks_block_size, gks_fallbacks, gks_step_noalloc) and only marshal
+arguments;
 every step of the scheme runs in the HIP kernels of the library.  `Solver`
 wraps a handle for numpy arrays laid out as in paper_1412_4489_amd.workloads.
 
@@ -44,6 +45,10 @@ class gks_problem(C.Structure):
                 ("admissibility", C.c_int32)]
 
 
+class gks_noalloc_status(C.Structure):
+    _fields_ = [("t", C.c_double), ("steps", C.c_int64), ("error", C.c_uint64), ("fallbacks", C.c_int64)]
+
+
 class GKSError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -78,12 +83,14 @@ def lib():
         L.gks_tune.argtypes = [_P, C.c_int32]
         L.gks_block_size.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32)]
         L.gks_fallbacks.argtypes = [_P, C.c_int32, C.POINTER(C.c_int64)]
+        L.gks_step_noalloc.argtypes = [C.POINTER(gks_problem), _P, _P, _P, C.c_int32, C.c_double, C.c_double, _P,
+                                       _P]
         _lib = L
     return _lib
 
 
 EXPORTED = ("gks_init", "gks_init_device", "gks_state_extent", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error",
-            "gks_profile", "gks_kernel_time", "gks_tune", "gks_block_size", "gks_fallbacks")
+            "gks_profile", "gks_kernel_time", "gks_tune", "gks_block_size", "gks_fallbacks", "gks_step_noalloc")
 
 
 def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
@@ -281,6 +288,19 @@ def gks_block_size(h, kernel):
     if rc != GKS_OK:
         raise GKSError(rc, gks_last_error(h))
     return n.value
+
+
+def gks_step_noalloc(prob, d_cell, d_face_x, d_face_y, nsteps, dt_fixed=0.0, t_end=0.0, d_status=None,
+                     precision=GKS_FP64, stream=None, t0=0.0):
+    """Allocation-free stepping of one problem on device buffers in the
+    layouts of gks_init_device (ints or tensors; d_face_y None in 1D);
+    d_status: None or a device buffer of 32 bytes (gks_noalloc_status).
+    Enqueued on `stream` (None: the null stream); returns at once."""
+    cp = to_c_problem(prob, precision, t0)
+    rc = lib().gks_step_noalloc(C.byref(cp), _addr(d_cell), _addr(d_face_x), _addr(d_face_y), int(nsteps),
+                                float(dt_fixed), float(t_end), _addr(d_status), stream)
+    if rc != GKS_OK:
+        raise GKSError(rc, "gks_step_noalloc: " + lib().gks_last_error(None).decode())
 
 
 def gks_fallbacks(h, problem):

@@ -205,6 +205,33 @@ for name in ("vortex", "dmr", "cavity", "ns_smooth", "advection_1d", "sod_1d_cha
         for q in ptrs:
             if q is not None:
                 L.gks_emu_free(q)
+# the allocation-free entry point on emulated device buffers: bitwise the
+# device-borrow handle form, two calls in a row (the second smaller), then a
+# 1D problem; the scratch array's bounds are checked by ASan
+for mk, nsteps in ((CASES["dmr"], 3), (CASES["vortex"], 2), (CASES["sod_1d_char"], 3)):
+    for prec in (gks.GKS_FP64, gks.GKS_FP32_MIXED):
+        prob, st = mk()
+        host = gks.ghosted(prob, st, prec)
+        pa, pb = emu_buffers(host), emu_buffers(host)
+        status = L.gks_emu_alloc(32)
+        dt = 0.5 * O.dt(prob, st)
+        h = gks.gks_init_device([prob], [pa[0]], [pa[1]], [pa[2]], prec)
+        gks.gks_step(h, nsteps, dt_fixed=[dt])
+        ref, tr, nr = gks.gks_fetch(h, 0, prob)
+        fb = gks.gks_fallbacks(h, 0)
+        gks.gks_destroy(h)
+        gks.gks_step_noalloc(prob, pb[0], pb[1], pb[2], nsteps, dt, 0.0, status, prec)
+        got = gks.unghosted(prob, *[None if q is None else emu_read(q, a) for q, a in zip(pb, host)])
+        raw = np.zeros(4, dtype=np.int64)
+        C.memmove(raw.ctypes.data, status, 32)
+        t = raw[0:1].view(np.float64)[0]
+        same = (np.array_equal(got.cell, ref.cell) and np.array_equal(got.fx, ref.fx) and np.array_equal(got.fy, ref.fy)
+                and t == tr and raw[1] == nr == nsteps and raw[2] == 0 and raw[3] == fb)
+        bad += not same
+        print(f"noalloc {prob.name} {prec}: {'identical' if same else 'DIFFER'}", flush=True)
+        for q in pa + pb + [status]:
+            if q is not None:
+                L.gks_emu_free(q)
 # device-borrow rejections: a nonphysical initial cell (found by the scan), a
 # buffer too small for the extent, host memory
 prob, st = CASES["vortex"]()
