@@ -183,8 +183,8 @@ int gks_init_device(gks_handle** out, int32_t n_problems, const gks_problem* pro
  * any allocation.  Every internal buffer lives in one static device array of
  * 128 MiB per GPU (held by each GPU the library runs on until the process
  * ends); a problem that needs more is refused with GKS_EINVAL before any
- * device work (about 1.2 kB per cell in GKS_FP64 and 0.8 kB in
- * GKS_FP32_MIXED: 320^2 and 400^2 cells fit).  All calls on one GPU share
+ * device work (about 230 B per cell in GKS_FP64 and 150 B in
+ * GKS_FP32_MIXED: 768^2 and 960^2 cells fit).  All calls on one GPU share
  * that array, which keeps the last call's contents (each call initialises
  * what it reads): calls that overlap on one GPU (other host threads, other
  * streams) race and must not be made.  The work is enqueued on `stream`

@@ -10,13 +10,11 @@
 //                                and, in one thread per problem, the CFL
 //                                time step or the fixed step
 //       k_recon_2d               compact reconstruction (Sec. 3.2)
-//       k_iface_pro_2d           interface prologue: U0, equilibrium quadratic,
-//                                tau, time integrals, leading terms (double)
-//       k_iface_corr_2d          eq. dis1 corrections (g0) and the eq. dis2
-//                                corrections of side 0 (g_l on u > 0), one
-//                                launch with the two phases on alternate blocks
-//       k_iface_kin1_2d          eq. dis2 corrections of side 1 (g_r on u < 0),
-//                                summing all corrections
+//       k_iface_2d               every interface: prologue (U0, equilibrium
+//                                quadratic, tau, time integrals, leading terms;
+//                                double), eq. dis1 (g0), eq. dis2 of side 0
+//                                (g_l on u > 0) and side 1 (g_r on u < 0), in
+//                                sections passing the frame record through LDS
 //       k_update_2d              conservative update (eq. finite), nonphysical
 //                                flag, CFL bound of the new state
 //   1D: k_ghost_1d (+ time step), k_recon_1d, k_face_1d (fused interface), k_update_1d
@@ -28,7 +26,6 @@
 //   FY  TS     [2][4][ny+3][nx+2]   y-interface Gauss values, interfaces -1..ny+1, cols -1..nx
 //   PC  TP     [4][5][ny+2][nx+2]   reconstruction coefficients, cells -1..nx
 //   FLX double [4][ny][nx+1], FLY double [4][ny+1][nx]   integrated fluxes
-//   frame record of the interfaces (ND_REC doubles + NT_REC TC each)
 // per 1D problem: W double [3][nx+4], FX TS [3][nx+3] (interfaces -1..nx+1),
 //   PC TP [3][2][nx+2], FLX double [3][nx+1].
 // TS = TP = TC = double (GKS_FP64) or float (GKS_FP32_MIXED).
@@ -149,7 +146,6 @@ struct Prob {
   Grid<TS, TP> g;
   Phys P;
   BCDev bc[4];
-  Rec<TC> R;
   int recon_vars;            // 0 conservative, 1 characteristic variables
   int admissibility;         // 0: rho, p > 0 at the interface centres; 1: also the factor-two range
   int obst_i0, obst_nj;      // solid step: cells i >= obst_i0, j < obst_nj (none: obst_nj = 0)
@@ -854,202 +850,151 @@ __device__ __forceinline__ void load_face_cell(const Grid<TS, TP>& g, const Face
   }
 }
 
+// LDS bytes per thread of k_iface_2d: the frame record of g0 and the
+// accumulated flux and point values (interface frame)
+template <typename TC>
+constexpr unsigned iface_lds_per_thread() {
+  return ND_REC * 8 + nt_rec<TC>() * sizeof(TC) + 12 * 8;
+}
+
+// Section boundary of k_iface_2d: values pass between sections only through
+// the thread's LDS slots (the memory clobber), and the scheduler moves no
+// instruction across, so that each section holds only its own working set.
+__device__ __forceinline__ void section_boundary() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// One thread per 2D interface (x interfaces first, then y interfaces): the
+// prologue, the hydrodynamic part and the kinetic parts of the two sides in
+// sequence, the frame record and the running sums in the thread's slots of
+// LDS, the flux and the point values stored once at the end.  No thread
+// reads another's slots (no barrier).
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_pro_2d(KA<Prob<TS, TP, TC>> a) {
+__global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
   int id;
   const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const double dt = *g.dt;  // tested after the loads below, which do not wait for it
   const Phys P = Q.P;
-  const Rec<TC> R = Q.R;
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
   if (inside_step(Q, F)) return;
-  double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
-  load_face_cell(g, F, 0, Wc[0], pc[0]);
-  load_face_cell(g, F, 1, Wc[1], pc[1]);
-  if (F.isx) {
-    const int j = F.a, fi = F.b;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 3; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ueq[m][n][v] = g.W[x.w(v, j - 1 + n, fi - 1 + m)];
-  } else {
-    const int fj = F.a, i = F.b;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 3; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ueq[m][n][loc(false, v)] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
-  }
-  if (!(dt > 0.0)) return;
+  const unsigned nb = blockDim.x, me = threadIdx.x;
+  const Rec<TC> R{(double*)lds, (TC*)(lds + (size_t)ND_REC * 8 * nb), nb};
+  double* acc = (double*)(lds + (size_t)(ND_REC * 8 + nt_rec<TC>() * sizeof(TC)) * nb);  // [12][nb]
   const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
-  const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, (size_t)id, flux, pv);
-  if (!ok) {
-    R.D(D_RHO0, id) = 0.0;  // marks the record invalid for the later phases
-    atomicCAS(g.err, 0ull,
-              1ull + ((unsigned long long)(F.a + 1) << 32) + (unsigned long long)(F.b + 1) + (F.isx ? 0ull : 1ull << 62));
-#pragma unroll
-    for (int v = 0; v < 4; ++v) flux[v] = pv[v] = 0.0;
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int vl = loc(F.isx, v);
+  // prologue
+  {
+    double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
+    load_face_cell(g, F, 0, Wc[0], pc[0]);
+    load_face_cell(g, F, 1, Wc[1], pc[1]);
     if (F.isx) {
-      g.FLX[x.flx(v, F.a, F.b)] = flux[vl];
-      g.FX[x.fx(0, v, F.a, F.b)] = (TS)pv[vl];
-      g.FX[x.fx(1, v, F.a, F.b)] = (TS)pv[vl];
+      const int j = F.a, fi = F.b;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Ueq[m][n][v] = g.W[x.w(v, j - 1 + n, fi - 1 + m)];
     } else {
-      g.FLY[x.fly(v, F.a, F.b)] = flux[vl];
-      g.FY[x.fy(0, v, F.a, F.b)] = (TS)pv[vl];
-      g.FY[x.fy(1, v, F.a, F.b)] = (TS)pv[vl];
+      const int fj = F.a, i = F.b;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Ueq[m][n][loc(false, v)] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
     }
-  }
-}
-
-// adds interface-frame corrections to the stored flux and point values; with
-// kPart the partial of side 0 left in the record first.  The direction is a
-// template argument so that the interface-frame component of each global
-// component is a constant (the local arrays stay in registers).
-template <bool kPart, bool kX, typename TS, typename TP, typename TC>
-__device__ __forceinline__ void add_corrections_dir(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
-                                                    const double (&flux)[4], const double (&pvm)[4],
-                                                    const double (&pvp)[4]) {
-  const Idx& x = g.ix;
+    if (!(dt > 0.0)) return;  // an empty step (end time reached, or after a nonphysical state)
+    const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, me, flux, pv);
+    if (!ok) {
+      R.D(D_RHO0, me) = 0.0;  // the later sections add nothing
+      atomicCAS(g.err, 0ull,
+                1ull + ((unsigned long long)(F.a + 1) << 32) + (unsigned long long)(F.b + 1) + (F.isx ? 0ull : 1ull << 62));
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int vl = loc(kX, v);
-    double* fl = kX ? &g.FLX[x.flx_late(v, F.a, F.b)] : &g.FLY[x.fly_late(v, F.a, F.b)];
-    TS* a = kX ? &g.FX[x.fx_late(0, v, F.a, F.b)] : &g.FY[x.fy_late(0, v, F.a, F.b)];
-    TS* b = kX ? &g.FX[x.fx_late(1, v, F.a, F.b)] : &g.FY[x.fy_late(1, v, F.a, F.b)];
-    if (kPart) {
-      *fl = (*fl + R.D(D_PF0 + vl, f)) + flux[vl];
-      *a = (TS)(((double)*a + (double)R.T(T_PV0 + vl, f)) + pvm[vl]);
-      *b = (TS)(((double)*b + (double)R.T(T_PV0 + 4 + vl, f)) + pvp[vl]);
-    } else {
-      *fl += flux[vl];
-      *a = (TS)((double)*a + pvm[vl]);
-      *b = (TS)((double)*b + pvp[vl]);
+      for (int v = 0; v < 4; ++v) flux[v] = pv[v] = 0.0;
     }
-  }
-}
-
-template <bool kPart, typename TS, typename TP, typename TC>
-__device__ __forceinline__ void add_corrections(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
-                                                const double (&flux)[4], const double (&pvm)[4],
-                                                const double (&pvp)[4]) {
-  if (F.isx)
-    add_corrections_dir<kPart, true>(g, F, R, f, flux, pvm, pvp);
-  else
-    add_corrections_dir<kPart, false>(g, F, R, f, flux, pvm, pvp);
-}
-
-// Prandtl-number fix on the complete flux of interface f: energy flux +=
-// (1/Pr - 1) q, q the heat flux relative to the velocity of g0 (interface
-// frame); Ed is the complete <psi f> of the interface
-template <bool kX, typename TS, typename TP, typename TC>
-__device__ __forceinline__ void prandtl_fix_dir(const Grid<TS, TP>& g, const Face& F, const Rec<TC>& R, size_t f,
-                                                double prfix, const double (&Ed)[4]) {
-  const Idx& x = g.ix;
-  double Fl[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) Fl[loc(kX, v)] = kX ? g.FLX[x.flx(v, F.a, F.b)] : g.FLY[x.fly(v, F.a, F.b)];
-  const double U0 = R.D(D_U0, f), V0 = R.D(D_V0, f), k2 = 0.5 * (U0 * U0 + V0 * V0);
-  const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
-  if (kX)
-    g.FLX[x.flx(3, F.a, F.b)] += prfix * qh;
-  else
-    g.FLY[x.fly(3, F.a, F.b)] += prfix * qh;
-}
-
-// eq. dis1 terms of interface id, added to the prologue's flux and point values
-template <typename TS, typename TP, typename TC>
-__device__ __forceinline__ void iface_hydro_body(const Prob<TS, TP, TC>& Q, int id) {
-  const Grid<TS, TP> g = Q.g;
-  if (id >= n_faces(g.ix)) return;
-  const Rec<TC> R = Q.R;
-  // the step and the record's validity are tested before the stores only, so
-  // that the record loads need not wait for them (a skipped interface
-  // computes with whatever the record holds and discards it)
-  const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
-  const Phys P = Q.P;
-  const Face F = face_of(g.ix, id);
-  if (inside_step(Q, F)) return;
-  const double hs = F.isx ? g.geo.k : g.geo.h;
-  double flux[4], pvm[4], pvp[4], E[4];
-  iface_hydro_2d<TC>(P, dt, hs, R, (size_t)id, flux, pvm, pvp, E);
-  if (!(dt > 0.0) || !(rho0 > 0.0)) return;
-  add_corrections<false>(g, F, R, (size_t)id, flux, pvm, pvp);
-  if (P.viscous)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) R.D(D_E0 + v, id) += E[v];
-}
-
-// eq. dis2 terms of side `side` of interface id.  Side 0 leaves them in the
-// record's partial fields; side 1 adds the partial and its own terms to the
-// flux and point values, then applies the Prandtl-number fix.
-template <typename TS, typename TP, typename TC>
-__device__ __forceinline__ void iface_kin_body(const Prob<TS, TP, TC>& Q, int id, int side) {
-  const Grid<TS, TP> g = Q.g;
-  if (id >= n_faces(g.ix)) return;
-  const Rec<TC> R = Q.R;
-  // tested before the stores only (as in the hydrodynamic phase)
-  const double dt = *g.dt, rho0 = R.D(D_RHO0, id);
-  const Phys P = Q.P;
-  const Face F = face_of(g.ix, id);
-  if (inside_step(Q, F)) return;
-  const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
-  double Wc[4], pc[4][5];
-  load_face_cell(g, F, side, Wc, pc);
-  double flux[4], pvm[4], pvp[4], E[4];
-  iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, (size_t)id, flux, pvm, pvp, E);
-  if (!(dt > 0.0) || !(rho0 > 0.0)) return;
-  if (side == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      R.D(D_PF0 + v, id) = flux[v];
-      R.T(T_PV0 + v, id) = (TC)pvm[v];
-      R.T(T_PV0 + 4 + v, id) = (TC)pvp[v];
-      if (P.viscous) R.D(D_PE0 + v, id) = E[v];
+      acc[v * nb + me] = flux[v];
+      acc[(4 + v) * nb + me] = pv[v];
+      acc[(8 + v) * nb + me] = pv[v];
     }
-    return;
   }
-  add_corrections<true>(g, F, R, (size_t)id, flux, pvm, pvp);
-  if (P.viscous) {
+  section_boundary();
+  // hydrodynamic part (eq. dis1)
+  {
+    const bool valid = R.D(D_RHO0, me) > 0.0;
+    double flux[4], pvm[4], pvp[4], E[4];
+    iface_hydro_2d<TC>(P, dt, hs, R, me, flux, pvm, pvp, E);
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[v * nb + me] += flux[v];
+        acc[(4 + v) * nb + me] += pvm[v];
+        acc[(8 + v) * nb + me] += pvp[v];
+        if (P.viscous) R.D(D_E0 + v, me) += E[v];
+      }
+    }
+  }
+  // kinetic parts (eq. dis2) of side 0 (g_l on u > 0), then side 1 (g_r on u < 0)
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    section_boundary();
+    const bool valid = R.D(D_RHO0, me) > 0.0;
+    double Wc[4], pc[4][5];
+    load_face_cell(g, F, side, Wc, pc);
+    double flux[4], pvm[4], pvp[4], E[4];
+    iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, me, flux, pvm, pvp, E);
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[v * nb + me] += flux[v];
+        acc[(4 + v) * nb + me] += pvm[v];
+        acc[(8 + v) * nb + me] += pvp[v];
+        if (P.viscous) R.D(D_E0 + v, me) += E[v];
+      }
+    }
+  }
+  section_boundary();
+  // Prandtl-number fix on the complete flux: energy flux += (1/Pr - 1) q, q
+  // the heat flux relative to the velocity of g0 (interface frame), from the
+  // complete <psi f>; then the stores (global components)
+  double Fl[4], Pm[4], Pp[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Fl[v] = acc[v * nb + me];
+    Pm[v] = acc[(4 + v) * nb + me];
+    Pp[v] = acc[(8 + v) * nb + me];
+  }
+  if (P.viscous && R.D(D_RHO0, me) > 0.0) {
+    const double U0 = R.D(D_U0, me), V0 = R.D(D_V0, me), k2 = 0.5 * (U0 * U0 + V0 * V0);
     double Ed[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Ed[v] = (R.D(D_E0 + v, id) + R.D(D_PE0 + v, id)) + E[v];
-    if (F.isx)
-      prandtl_fix_dir<true>(g, F, R, (size_t)id, P.prfix, Ed);
-    else
-      prandtl_fix_dir<false>(g, F, R, (size_t)id, P.prfix, Ed);
+    for (int v = 0; v < 4; ++v) Ed[v] = R.D(D_E0 + v, me);
+    const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
+    Fl[3] += P.prfix * qh;
   }
-}
-
-// the hydrodynamic phase (even logical blocks) and the kinetic phase of
-// side 0 (odd logical blocks) of the same interfaces in one launch of twice
-// the interface blocks; pairs of blocks share a tile, so both phases of an
-// interface run on the same XCD
-template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_corr_2d(KA<Prob<TS, TP, TC>> a) {
-  const unsigned L = logical_block(a.nblk), tile = L >> 1;
-  const Prob<TS, TP, TC>& Q = a.probs[a.single ? 0 : (int)a.owner[tile]];
-  const int id = (int)((tile - Q.first[KK_FACE]) * blockDim.x + threadIdx.x);
-  if (L & 1u)
-    iface_kin_body(Q, id, 0);
-  else
-    iface_hydro_body(Q, id);
-}
-
-template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_kin1_2d(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
-  iface_kin_body(Q, id, 1);
+  if (F.isx) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int vl = loc(true, v);
+      g.FLX[x.flx(v, F.a, F.b)] = Fl[vl];
+      g.FX[x.fx(0, v, F.a, F.b)] = (TS)Pm[vl];
+      g.FX[x.fx(1, v, F.a, F.b)] = (TS)Pp[vl];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int vl = loc(false, v);
+      g.FLY[x.fly(v, F.a, F.b)] = Fl[vl];
+      g.FY[x.fy(0, v, F.a, F.b)] = (TS)Pm[vl];
+      g.FY[x.fy(1, v, F.a, F.b)] = (TS)Pp[vl];
+    }
+  }
 }
 
 // 1D interfaces 0..nx, fused
@@ -1208,8 +1153,8 @@ struct Problem {
   void* FLX = nullptr;
   void* FLY = nullptr;
   void* scal = nullptr;  // t, dt, steps, err, CFL slots (kScalBytes)
-  void* recd = nullptr;  // interface frame record, double fields (2D)
-  void* rect = nullptr;  // interface frame record, compute-type fields (2D)
+  void* recd = nullptr;  // (unused: the interface kernel keeps its frame record in LDS)
+  void* rect = nullptr;
   bool borrowed = false;  // W, FX, FY belong to the caller (gks_init_device)
 };
 
@@ -1366,12 +1311,11 @@ void buffer_sizes(const Problem& p, size_t (&sizes)[9]) {
   const Idx& x = p.ix;
   const size_t nx = x.nx, ny = x.ny;
   if (p.spec.dim == 2) {
-    const size_t nf = n_interfaces(x);
     const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,      2 * 4 * (ny + 2) * (nx + 3) * ts,
                           2 * 4 * (ny + 3) * (nx + 2) * ts, 4 * 5 * (ny + 2) * (nx + 2) * ts,
                           4 * ny * (nx + 1) * 8,            4 * (ny + 1) * nx * 8,
-                          kScalBytes,                       (size_t)ND_REC * nf * 8,
-                          (size_t)NT_REC * nf * ts};
+                          kScalBytes,                       0,
+                          0};
     memcpy(sizes, sz, sizeof(sz));
   } else {
     const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes,
@@ -1468,9 +1412,6 @@ void make_desc(Problem& p, Prob<TS, TP, TC>& d) {
   d.g = grid_of<TS, TP>(p);
   d.P = p.phys;
   for (int s = 0; s < 4; ++s) d.bc[s] = p.bc[s];
-  d.R.d = (double*)p.recd;
-  d.R.t = (TC*)p.rect;
-  d.R.nf = p.spec.dim == 2 ? n_interfaces(p.ix) : 0;
   d.recon_vars = p.spec.recon_vars;
   d.admissibility = p.spec.admissibility;
   d.obst_i0 = p.spec.obstacle_i0;
@@ -1573,11 +1514,7 @@ void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const
   record_end(h, st, GKS_K_RECON);
   record_begin(h, st);
   if (dim == 2) {
-    k_iface_pro_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
-    KA<PR> pair = A[KK_FACE];
-    pair.nblk = 2 * A[KK_FACE].nblk;  // logical block 2t + r: tile t, phase r
-    k_iface_corr_2d<TS, TP, TC><<<pair.nblk, bs[KK_FACE], 0, st>>>(pair);
-    k_iface_kin1_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
+    k_iface_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], bs[KK_FACE] * iface_lds_per_thread<TC>(), st>>>(A[KK_FACE]);
   } else {
     k_face_1d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   }

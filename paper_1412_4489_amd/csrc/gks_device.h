@@ -233,40 +233,34 @@ struct Acc {
 };
 
 // ---------------------------------------------------------------------------
-// One 2D interface is evaluated in three phases (separate kernels), so that
-// each phase holds only its own working set in registers:
+// One 2D interface is evaluated by one thread in four sections, each holding
+// only its own working set in registers; what passes between them (the frame
+// record of g0) lives in the thread's slots of LDS:
 //   prologue  (double)  interface values of the two cell polynomials, their
 //                       half-space moments, U0 (eq. compatibility2), the
 //                       equilibrium quadratic (Sec. 3.3), tau (Sec. 4); the
 //                       leading flux and point values; (TC) the expansion
-//                       coefficients of g0; the record of g0;
-//   hydro     (TC)      the terms of eq. dis1;
+//                       coefficients of g0 (FP32-mixed); the record of g0;
+//   hydro     (TC)      the terms of eq. dis1 (FP64: after solving the
+//                       coefficients of g0 from the recorded targets);
 //   kinetic   (double)  the side's interface state, half-space moments and
 //                       targets again (from its cell, same arithmetic as in
 //                       the prologue), (TC) the coefficients of g_k and the
 //                       terms of eq. dis2 (once per side).
-// The hydrodynamic phase and the kinetic phase of side 0 run in one launch
-// (alternate blocks): the former adds its terms to the prologue's flux and
-// point values, the latter leaves its own in the record (partial fields),
-// and the kinetic phase of side 1 adds both, in the order
-// ((prologue + hydrodynamic) + side 0) + side 1.
-// The record is a structure of arrays indexed by the interface.
+// The sums keep the order ((prologue + hydrodynamic) + side 0) + side 1.
+// The record is a structure of arrays over the threads of a block.
 // ---------------------------------------------------------------------------
 enum HydroW { HW_I2, HW_I3, HW_I4H, HW_I5H, HW_I6, HW_I1Y, HW_C2, HW_C3, HW_C4H, HW_C5H, HW_C6, HW_C1, HW_C1H };
 enum KinW { KW_ICONV, KW_CCONV, KW_IQUAD, KW_CQUAD, KW_IY, KW_C7H, KW_C7, KW_CINNER, KW_AI, KW_AC, KW_TI, KW_TC };
 enum RecD {  // double fields
   D_RHO0, D_U0, D_V0, D_LAM0,
-  D_TAU,                    // collision time (the phases rebuild the time weights)
+  D_TAU,                    // collision time (the sections rebuild the time weights)
   D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
-  D_PF0 = D_E3 + 1,         // side 0's flux (4, interface frame), left for side 1
-  D_PE0 = D_PF0 + 4,        // side 0's <psi f> (4; Navier-Stokes only)
-  ND_REC = D_PE0 + 4
+  ND_REC = D_E3 + 1
 };
 enum RecT {  // compute-type fields
-  T_CG = 0,                 // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar
-                            // frame; in double precision its targets bx, by, bxx, bxy, byy (5 x 4)
-  T_PV0 = 36,               // side 0's point values at the two Gauss points (2 x 4, interface frame)
-  NT_REC = T_PV0 + 8
+  T_CG = 0  // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar frame; in double
+            // precision its targets bx, by, bxx, bxy, byy (5 x 4)
 };
 
 // Where the coefficient systems of g0 are solved: in the prologue for a
@@ -276,6 +270,11 @@ enum RecT {  // compute-type fields
 template <typename TC>
 constexpr bool g0_solved_in_prologue() {
   return sizeof(TC) == 4;
+}
+// compute-type fields of the record: 36 coefficients or 20 targets
+template <typename TC>
+constexpr int nt_rec() {
+  return g0_solved_in_prologue<TC>() ? 36 : 20;
 }
 
 // weights of the terms of eq. dis1 (hydro) and eq. dis2 (kinetic) from the
@@ -313,13 +312,15 @@ __device__ __forceinline__ void kinetic_weights(const TimeWeights& w, double tau
   kw[KW_TC] = -tau * w.C[8];
 }
 
+// the frame record of the threads of a block (structure of arrays: field k
+// of thread f at k * nf + f)
 template <typename TC>
 struct Rec {
   double* d;
   TC* t;
-  size_t nf;
-  __device__ __forceinline__ double& D(int k, size_t f) const { return d[(size_t)k * nf + f]; }
-  __device__ __forceinline__ TC& T(int k, size_t f) const { return t[(size_t)k * nf + f]; }
+  unsigned nf;
+  __device__ __forceinline__ double& D(int k, unsigned f) const { return d[(unsigned)k * nf + f]; }
+  __device__ __forceinline__ TC& T(int k, unsigned f) const { return t[(unsigned)k * nf + f]; }
 };
 
 // coefficient-set arrays of one Maxwellian (peculiar frame)
@@ -398,7 +399,7 @@ __device__ __forceinline__ void side_targets_2d(int s, double hn, const Side& S,
 template <typename TC>
 __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, double hn, double hs,
                                                   const double (&Wc)[2][4], const double (&pc)[2][4][5],
-                                                  const double (&Ueq)[2][3][4], const Rec<TC>& R, size_t f,
+                                                  const double (&Ueq)[2][3][4], const Rec<TC>& R, unsigned f,
                                                   double (&flux)[4], double (&pv)[4]) {
   const double g1 = P.gamma - 1.0;
   Side S[2];
@@ -496,7 +497,7 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
 // Hydrodynamic phase of interface f: corrections to flux, point values and
 // the integrated density (lab frame, interface frame components).
 template <typename TC>
-__device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double hs, const Rec<TC>& R, size_t f,
+__device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double hs, const Rec<TC>& R, unsigned f,
                                                double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                double (&E)[4]) {
   const double rho0 = R.D(D_RHO0, f), U0 = R.D(D_U0, f), V0 = R.D(D_V0, f), lam0 = R.D(D_LAM0, f);
@@ -574,7 +575,7 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double 
 template <typename TC>
 __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, double hn, double hs, int s,
                                                  const double (&Wc)[4], const double (&pc)[4][5], const Rec<TC>& R,
-                                                 size_t f, double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
+                                                 unsigned f, double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                  double (&E)[4]) {
   Side S;
   side_state_2d(P, s, hn, hs, Wc, pc, S);  // physical: the prologue checked it

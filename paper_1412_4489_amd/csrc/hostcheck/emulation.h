@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <functional>
+#include <memory>
 #include <vector>
 
 using std::erfc;
@@ -38,6 +39,7 @@ using std::sqrt;
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
 
 struct dim3 {
   unsigned x, y, z;
@@ -297,10 +299,19 @@ inline hipError_t hipGraphDestroy(hipGraph_t g) {
   return hipSuccess;
 }
 
+// dynamic LDS of the running launch (one block at a time): allocated at its
+// exact size per launch, so that an access beyond it is caught
+inline std::unique_ptr<unsigned char[]>& emu_lds_buffer() {
+  static std::unique_ptr<unsigned char[]> b;
+  return b;
+}
+inline unsigned char* emu_dynamic_lds() { return emu_lds_buffer().get(); }
+
 template <class F>
-inline void gks_emulated_run(dim3 grid, dim3 block, const F& body) {
+inline void gks_emulated_run(dim3 grid, dim3 block, const F& body, size_t shmem = 0) {
   gridDim = grid;
   blockDim = block;
+  emu_lds_buffer().reset(new unsigned char[shmem ? shmem : 1]);
   EmuFibers& E = emu_fibers();
   const int n = (int)(block.x * block.y * block.z);
   while ((int)E.stacks.size() < n) {
@@ -354,10 +365,10 @@ inline void gks_emulated_run(dim3 grid, dim3 block, const F& body) {
 }
 
 template <class F>
-inline void gks_emulated_launch(dim3 grid, dim3 block, F body) {
+inline void gks_emulated_launch(dim3 grid, dim3 block, F body, size_t shmem = 0) {
   if (g_emu_capture) {
-    g_emu_capture->ops.push_back([=]() { gks_emulated_run(grid, block, body); });
+    g_emu_capture->ops.push_back([=]() { gks_emulated_run(grid, block, body, shmem); });
     return;
   }
-  gks_emulated_run(grid, block, body);
+  gks_emulated_run(grid, block, body, shmem);
 }

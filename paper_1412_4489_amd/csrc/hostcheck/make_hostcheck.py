@@ -46,7 +46,8 @@ def rewrite_launches(src):
             q += 1
         args = src[e + 4:q]
         out.append(src[pos:start])
-        out.append(f"gks_emulated_launch(dim3({cfg[0]}), dim3({cfg[1]}), [=]() {{ {kernel}({args}); }})")
+        shm = cfg[2] if len(cfg) > 2 else "0"
+        out.append(f"gks_emulated_launch(dim3({cfg[0]}), dim3({cfg[1]}), [=]() {{ {kernel}({args}); }}, (size_t)({shm}))")
         pos = q + 1
 
 
@@ -80,6 +81,10 @@ def main(outdir=None):
     # in the wave minimum's atomic directly, which gives the same minimum
     s, n = re.subn(r"if \(\(threadIdx\.x & 63\) == 0\) (atomicMin\()", r"\1", s)
     assert n == 1, "wave-minimum pattern not found"
+    # dynamic LDS: the emulation's per-launch buffer
+    s, n = re.subn(r"extern __shared__ (?:__align__\(\d+\) )?unsigned char (\w+)\[\];",
+                   r"unsigned char* \1 = emu_dynamic_lds();", s)
+    assert n >= 1, "dynamic LDS declaration not found"
     s = rewrite_launches(s)
     # the correctly rounded division helper of the device code, for a host test
     s += ('\nextern "C" double gks_emu_div_by(double a, double b) { return gks::div_by(a, gks::divisor(b)); }\n')

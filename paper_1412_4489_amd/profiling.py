@@ -5,8 +5,8 @@ and of `rocprofv3 --pmc <counters> --output-format csv` runs and writes short
 Markdown / JSON summaries:
 
   * kernel_table: per kernel and launch size, calls and average / min / max
-    duration (selected by grid size: one workload of a run);
-  * traffic: HBM bytes per dispatch of the interface kernels from FETCH_SIZE and
+    duration;
+  * traffic: HBM bytes per dispatch of the interface kernel from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by the factor a plain device copy
     of known size needs (the 256 MiB copies at the start of `bench.py
     --pmc-probe`: bytes read and written = 256 MiB each);
@@ -15,8 +15,8 @@ Markdown / JSON summaries:
     python -m paper_1412_4489_amd.profiling --trace T.csv --fetch F.csv \\
         --write W.csv --sq S.csv --out profiles/
 
-writes kernels_vortex256_fp32mixed_fp64.md, kernels_batch96_fp32mixed.md,
-counters_iface_vortex256_fp32mixed.md and traffic_iface_vortex256_fp32mixed.json
+writes kernels_batch96.md (both forms of the 96-grid batch),
+counters_iface_batch96_fp32mixed.md and traffic_iface_batch96_fp32mixed.json
 (the record bench.py reads while the kernel sources still hash to the same
 value).
 
@@ -32,10 +32,11 @@ import os
 import re
 
 COPY_BYTES = 256 << 20  # the calibration copies of bench.py --pmc-probe
-IFACE = ("k_iface_pro_2d", "k_iface_corr_2d", "k_iface_kin1_2d")
-FACES_256 = 131072  # interface threads of the periodic 256 x 256 grid
+IFACE = "k_iface_2d"
 CUS, CLOCK_MHZ = 256, 2400  # MI355X compute units and clock (VALUBusy below)
-BATCH_MIN_GRID = 400000  # launches of the 96-grid batch are larger than this
+BATCH_MIN_GRID = 400000  # interface launches of the 96-grid batch are larger than this
+BATCH_CELLS = 4130816
+BATCH_ALG_BYTES = BATCH_CELLS * 192  # state read once and written once per step, FP32-mixed
 KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -79,19 +80,17 @@ def kernel_markdown(agg, title, command):
     return "\n".join(lines) + "\n"
 
 
-def threads(kernel, faces):
-    """Launch size of an interface kernel: the combined hydrodynamic / kinetic
-    side 0 launch has two blocks per tile."""
-    return 2 * faces if kernel == "k_iface_corr_2d" else faces
-
-
 def _counter_rows(path):
     with open(path) as fh:
         return list(csv.DictReader(fh))
 
 
-def traffic(fetch_csv, write_csv, faces, ttype="float"):
-    """Scaled HBM bytes per dispatch of the interface kernels."""
+def _batch_iface_rows(rows, ttype="float"):
+    return [r for r in rows if _short(r["Kernel_Name"]) == (IFACE, ttype) and int(r["Grid_Size"]) >= BATCH_MIN_GRID]
+
+
+def traffic(fetch_csv, write_csv):
+    """Scaled HBM bytes per dispatch of the interface kernel on the batch."""
     out = {}
     for name, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _counter_rows(path)
@@ -99,35 +98,24 @@ def traffic(fetch_csv, write_csv, faces, ttype="float"):
         if len(copies) < 3:
             raise ValueError(f"{path}: the three calibration copies are missing")
         factor = (COPY_BYTES / 1024.0) / (sum(copies) / 3)
-        per = collections.defaultdict(list)
-        for r in rows:
-            k, t = _short(r["Kernel_Name"])
-            if k in IFACE and t == ttype and int(r["Grid_Size"]) == threads(k, faces):
-                per[k].append(float(r["Counter_Value"]))
-        out[name] = {"factor": factor, "copy_kib": sum(copies) / 3,
-                     "kib_per_dispatch": {k: sum(v) / len(v) for k, v in per.items()}}
-    per_set = 0.0
-    for name in ("fetch", "write"):
-        d = out[name]
-        for k, kib in d["kib_per_dispatch"].items():
-            per_set += kib * 1024.0 * d["factor"]
-    out["bytes_per_launch_set"] = per_set
+        per = collections.defaultdict(float)
+        for n, r in enumerate(_batch_iface_rows(rows)):
+            per[r.get("Dispatch_Id", n)] += float(r["Counter_Value"])
+        vals = list(per.values())
+        out[name] = {"factor": factor, "copy_kib": sum(copies) / 3, "kib_per_dispatch": sum(vals) / len(vals),
+                     "dispatches": len(vals)}
+    out["bytes_per_launch"] = sum(out[n]["kib_per_dispatch"] * 1024.0 * out[n]["factor"] for n in ("fetch", "write"))
     return out
 
 
-def sq_summary(sq_csv, faces, ttype="float"):
-    per = collections.defaultdict(lambda: collections.defaultdict(list))
-    for r in _counter_rows(sq_csv):
-        k, t = _short(r["Kernel_Name"])
-        if k.startswith("k_") and t == ttype:
-            per[(k, int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    res = {}
-    for key, d in per.items():
-        m = {c: sum(v) / len(v) for c, v in d.items()}
-        if m.get("SQ_WAVES"):
-            res[key] = {"waves": m["SQ_WAVES"], "valu_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
-                        "valu_quad_cycles": m.get("SQ_ACTIVE_INST_VALU", 0.0)}
-    return res
+def sq_summary(sq_csv):
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for n, r in enumerate(_batch_iface_rows(_counter_rows(sq_csv))):
+        per[r.get("Dispatch_Id", n)][r["Counter_Name"]] += float(r["Counter_Value"])
+    d = list(per.values())
+    m = {c: sum(x.get(c, 0.0) for x in d) / len(d) for c in d[0]}
+    return {"waves": m["SQ_WAVES"], "valu_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+            "valu_quad_cycles": m.get("SQ_ACTIVE_INST_VALU", 0.0)}
 
 
 def valu_busy(quad_cycles, duration_us):
@@ -139,7 +127,8 @@ def valu_busy(quad_cycles, duration_us):
 
 
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $O/prof_bench "
-             "-o bench --output-format csv -- python -u $R/bench.py --steps 50 --warmup 5 --no-cpu --no-configs")
+             "-o bench --output-format csv -- python -u $R/bench.py --steps 20 --warmup 5 --long-steps 0 "
+             "--no-cpu --no-configs")
 PMC_PASSES = (("FETCH_SIZE", "pmc_fetch", "f"), ("WRITE_SIZE", "pmc_write", "w"),
               ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
                "pmc_sq", "s"))
@@ -157,62 +146,54 @@ def _averages(agg):
 
 
 def _step_line(d):
-    iface = d["k_iface_pro_2d"] + d["k_iface_corr_2d"] + d["k_iface_kin1_2d"]
-    tot = iface + d["k_recon_2d"] + d["k_update_2d"] + d["k_ghost_2d"]
-    return (f"interface phases {d['k_iface_pro_2d']:.1f} + {d['k_iface_corr_2d']:.1f} + "
-            f"{d['k_iface_kin1_2d']:.1f} = {iface:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
+    tot = d[IFACE] + d["k_recon_2d"] + d["k_update_2d"] + d["k_ghost_2d"]
+    return (f"interface {d[IFACE]:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
             f"{d['k_update_2d']:.1f}, boundary (+ time step) {d['k_ghost_2d']:.1f}; sum {tot:.1f} us")
 
 
+def batch_iface_duration(trace_csv, ttype="float"):
+    """average duration (us) of the interface kernel's batch launches"""
+    v = [x for (k, t, g), d in kernel_table(trace_csv).items() if k == IFACE and t == ttype and g >= BATCH_MIN_GRID
+         for x in d]
+    return sum(v) / len(v) if v else None
+
+
 def write_kernel_summaries(trace_csv, out):
-    agg = kernel_table(trace_csv)
-    small = {k: v for k, v in agg.items() if k[2] < BATCH_MIN_GRID}
-    big = {k: v for k, v in agg.items() if k[2] >= BATCH_MIN_GRID}
-    avg = _averages(small)
-    md = kernel_markdown(small, "Kernel trace: isentropic vortex 256 x 256, GKS_FP32_MIXED and GKS_FP64", TRACE_CMD)
-    md += ("\nPer step (averages over the launch sizes of a kernel):\n\n"
-           f"* FP32-mixed: {_step_line(avg['float'])}\n* FP64: {_step_line(avg['double'])}\n\n"
-           f"{FACES_256} interface threads: on the periodic grid the last interface of each row and column is "
-           "the first.\nThe same run also holds the 96-grid batch (kernels_batch96_fp32mixed.md).\n")
-    with open(os.path.join(out, "kernels_vortex256_fp32mixed_fp64.md"), "w") as fh:
+    agg = {k: v for k, v in kernel_table(trace_csv).items() if k[0] != IFACE or k[2] >= BATCH_MIN_GRID}
+    avg = _averages(agg)
+    md = kernel_markdown(agg, f"Kernel trace: 96-grid batch ({BATCH_CELLS} cells), GKS_FP32_MIXED and GKS_FP64",
+                         TRACE_CMD)
+    md += "\nPer step (averages over the launch sizes of a kernel; each launch covers all 96 grids):\n\n"
+    for t, name in (("float", "FP32-mixed"), ("double", "FP64")):
+        if t in avg and IFACE in avg[t]:
+            md += f"* {name}: {_step_line(avg[t])}\n"
+    md += ("\nThe tuner's timing steps (64, 128, 256 threads per block) add launches of other sizes to the "
+           "smaller kernels' rows.\n")
+    with open(os.path.join(out, "kernels_batch96.md"), "w") as fh:
         fh.write(md)
-    if big:
-        d = _averages(big)["float"]
-        md = kernel_markdown(big, "Kernel trace: 96-grid batch (4 130 816 cells), GKS_FP32_MIXED", TRACE_CMD)
-        md += (f"\nPer step: {_step_line(d)}; each launch covers all 96 grids (the launch sizes of a "
-               "kind differ with the tuned block size).\n")
-        with open(os.path.join(out, "kernels_batch96_fp32mixed.md"), "w") as fh:
-            fh.write(md)
 
 
 def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
-    tr = traffic(fetch_csv, write_csv, FACES_256)
-    sq = sq_summary(sq_csv, FACES_256) if sq_csv else {}
-    # kernel durations of the same workload (FP32-mixed, 256 x 256) from the trace
-    dur = {}
-    if trace_csv:
-        for (k, t, g), v in kernel_table(trace_csv).items():
-            if t == "float" and k in IFACE and g == threads(k, FACES_256):
-                dur[k] = sum(v) / len(v)
-    busy = {k: valu_busy(sq[(k, threads(k, FACES_256))]["valu_quad_cycles"], dur[k])
-            for k in IFACE if k in dur and (k, threads(k, FACES_256)) in sq}
-    busy_set = None
-    if len(busy) == len(IFACE):
-        busy_set = (sum(sq[(k, threads(k, FACES_256))]["valu_quad_cycles"] for k in IFACE) / CUS
-                    / (sum(dur[k] for k in IFACE) * CLOCK_MHZ))
+    tr = traffic(fetch_csv, write_csv)
+    sq = sq_summary(sq_csv) if sq_csv else {}
+    dur = batch_iface_duration(trace_csv) if trace_csv else None
+    busy = valu_busy(sq["valu_quad_cycles"], dur) if sq and dur else None
     rec = {"source_hash": source_hash(),
-           "workload": "isentropic vortex 256x256, GKS_FP32_MIXED, tuned launch shapes",
-           "bytes_per_launch_set": round(tr["bytes_per_launch_set"]),
+           "workload": "96-grid batch, GKS_FP32_MIXED, tuned launch shapes",
+           "bytes_per_launch": round(tr["bytes_per_launch"]),
+           "algorithmic_bytes_per_step": BATCH_ALG_BYTES,
+           "traffic_per_algorithmic_bytes": round(tr["bytes_per_launch"] / BATCH_ALG_BYTES, 3),
            "fetch_factor": tr["fetch"]["factor"], "write_factor": tr["write"]["factor"],
            "fetch_kib_per_dispatch": tr["fetch"]["kib_per_dispatch"],
            "write_kib_per_dispatch": tr["write"]["kib_per_dispatch"],
-           "valu_busy": {k: round(v, 4) for k, v in busy.items()},
-           "valu_busy_launch_set": None if busy_set is None else round(busy_set, 4)}
-    with open(os.path.join(out, "traffic_iface_vortex256_fp32mixed.json"), "w") as fh:
+           "waves": sq.get("waves"), "valu_instructions_per_wave": sq.get("valu_per_wave"),
+           "duration_us": dur, "valu_busy": None if busy is None else round(busy, 4)}
+    with open(os.path.join(out, "traffic_iface_batch96_fp32mixed.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
-    t = ["# Counters: interface kernels, isentropic vortex 256 x 256, GKS_FP32_MIXED", "",
-         "Commands (on the machine with the GPU, from /tmp with TMPDIR=/tmp, repository root R, output directory O), one counter pass per run:", ""]
+    t = ["# Counters: interface kernel k_iface_2d, 96-grid batch, GKS_FP32_MIXED", "",
+         "Commands (on the machine with the GPU, from /tmp with TMPDIR=/tmp, repository root R, output directory O), "
+         "one counter pass per run:", ""]
     t += [f"    timeout -s KILL 120 rocprofv3 --pmc {c} -d $O/{d} -o {o} --output-format csv "
           "-- python -u $R/bench.py --pmc-probe" for c, d, o in PMC_PASSES]
     t += ["", "Summary:", "", "    " + SUMMARY_CMD, "",
@@ -221,27 +202,18 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
           f"WRITE_SIZE {tr['write']['copy_kib']:.0f} KiB (factor {tr['write']['factor']:.4f}).", "",
           "VALUBusy = SQ_ACTIVE_INST_VALU (quad-cycles, all CUs) / 256 CUs / kernel cycles (the kernel's mean "
           "duration in the kernel trace x 2.4 GHz).", "",
-          "| kernel | FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) | HBM bytes/dispatch (scaled) | waves "
-          "| VALU instr./wave | duration (us) | VALUBusy |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
-    for k in IFACE:
-        f_, w_ = tr["fetch"]["kib_per_dispatch"][k], tr["write"]["kib_per_dispatch"][k]
-        b = (f_ * tr["fetch"]["factor"] + w_ * tr["write"]["factor"]) * 1024
-        s_ = sq.get((k, threads(k, FACES_256)), {})
-        t.append(f"| {k} | {f_:.0f} | {w_:.0f} | {b / 1e6:.1f} MB | {s_.get('waves', 0):.0f} "
-                 f"| {s_.get('valu_per_wave', 0):.0f} | {dur.get(k, 0):.2f} | {100 * busy.get(k, 0):.0f} % |")
-    t += ["", f"Interface launch set (prologue, hydrodynamic + kinetic side 0, kinetic side 1): "
-          f"{tr['bytes_per_launch_set'] / 1e6:.1f} MB "
-          "of HBM traffic per step; the algorithmic bytes of the whole step are 12.6 MB (65536 cells x 192 B).",
-          "Most of the difference is the frame record: the prologue writes 9 doubles + 36 coefficients per "
-          "interface, kinetic side 0 leaves 4 doubles + 8 point values for side 1, and the phases "
-          "read-modify-write the fluxes and point values.",
-          "" if busy_set is None else f"VALUBusy of the launch set: {100 * busy_set:.0f} %.", "",
-          "traffic_iface_vortex256_fp32mixed.json holds these figures with the hash of the kernel sources they "
+          "| FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) | HBM bytes/dispatch (scaled) | waves "
+          "| VALU instr./wave | duration (us) | VALUBusy |", "|---:|---:|---:|---:|---:|---:|---:|",
+          f"| {tr['fetch']['kib_per_dispatch']:.0f} | {tr['write']['kib_per_dispatch']:.0f} "
+          f"| {tr['bytes_per_launch'] / 1e6:.1f} MB | {sq.get('waves', 0):.0f} | {sq.get('valu_per_wave', 0):.0f} "
+          f"| {dur or 0:.1f} | {100 * (busy or 0):.0f} % |", "",
+          f"Algorithmic bytes of the whole step: {BATCH_ALG_BYTES / 1e6:.0f} MB ({BATCH_CELLS} cells x 192 B: four "
+          "double averages and sixteen single-precision point values read once and written once); the interface "
+          f"launch moves {tr['bytes_per_launch'] / BATCH_ALG_BYTES:.2f} times that.", "",
+          "traffic_iface_batch96_fp32mixed.json holds these figures with the hash of the kernel sources they "
           "were taken from (bench.py reports `traffic` only while the sources match)."]
-    with open(os.path.join(out, "counters_iface_vortex256_fp32mixed.md"), "w") as fh:
+    with open(os.path.join(out, "counters_iface_batch96_fp32mixed.md"), "w") as fh:
         fh.write("\n".join(t) + "\n")
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace")
