@@ -108,17 +108,43 @@ def pmc_probe():
     print("pmc probe done", flush=True)
 
 
-def run_gpu(items, precision, steps, warmup, long_steps=0):
+def launch_forms(S, steps):
+    """Interface kernel time per launch (HIP events) at the tuned block size
+    in the one-block-per-tile form and in the persistent form (the tuner's
+    grid, else four waves per compute unit); the tuned shape is restored."""
+    import torch
+    from paper_1412_4489_amd import gks
+    bs, grid = S.launch_shape("interface")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for name, g in (("per_tile", 0), ("persistent", grid or cus * 256 // bs)):
+        S.set_launch("interface", bs, g)
+        S.step(2)
+        torch.cuda.synchronize()
+        gks.gks_profile(S.h, 1)
+        gks.gks_profile(S.h, 2)
+        S.step(steps)
+        torch.cuda.synchronize()
+        gks.gks_profile(S.h, 0)
+        ms, n = gks.gks_kernel_time(S.h, "interface")
+        out[name] = {"threads": bs, "grid": g, "interface_ms": round(ms / max(n, 1), 5)}
+    S.set_launch("interface", bs, grid)
+    out["tuned"] = "persistent" if grid else "per_tile"
+    return out
+
+
+def run_gpu(items, precision, steps, warmup, long_steps=0, forms=False):
     """Times `steps` graph-replayed steps after `warmup` (tuned launch shapes)
     and, in an eager run of the same number of steps, every kernel class with
     HIP events on the library's stream.  Returns (wall, kernel times, probs,
-    block sizes, long-window wall)."""
+    launch shapes, long-window wall, interface launch forms or None)."""
     import torch
     from paper_1412_4489_amd import gks
     probs, states = [p for p, _ in items], [s for _, s in items]
     side = torch.cuda.Stream()  # a torch stream the library borrows
     S = gks.Solver(probs, states, precision, stream=side.cuda_stream)
-    sizes = S.tune(3)
+    S.tune(3)
+    sizes = {k: S.launch_shape(k) for k in ("ghost", "recon", "interface", "update")}
     S.step(warmup)
     torch.cuda.synchronize()
     gks.gks_profile(S.h, 1)
@@ -140,10 +166,11 @@ def run_gpu(items, precision, steps, warmup, long_steps=0):
         S.step(long_steps)
         torch.cuda.synchronize()
         wall_long = time.perf_counter() - t0
+    lf = launch_forms(S, steps) if forms else None
     for k in range(len(probs)):
         S.fetch(k)  # raises if a grid produced a nonphysical state
     S.close()
-    return wall, kt, probs, sizes, wall_long
+    return wall, kt, probs, sizes, wall_long, lf
 
 
 def config_rates(steps=20, warmup=3):
@@ -237,21 +264,22 @@ def main():
     from paper_1412_4489_amd import workloads as W
 
     items = W.batch()
-    wall, kt, probs, sizes, wall_long = run_gpu(items, gks.GKS_FP32_MIXED, a.steps, a.warmup, a.long_steps)
+    wall, kt, probs, sizes, wall_long, forms = run_gpu(items, gks.GKS_FP32_MIXED, a.steps, a.warmup, a.long_steps,
+                                                       forms=True)
     cells = sum(p.ncells for p in probs)
     value = cells * a.steps / wall / 1e6
-    print(f"# batch fp32_mixed: {a.steps} steps in {wall * 1e3:.2f} ms; block sizes {sizes}; kernel ms: "
+    print(f"# batch fp32_mixed: {a.steps} steps in {wall * 1e3:.2f} ms; launch shapes {sizes}; kernel ms: "
           + ", ".join(f"{k} {v[0]:.2f} ({v[1]})" for k, v in kt.items()), file=sys.stderr, flush=True)
     ms_if, nl = kt["interface"]
     t_if = ms_if / 1e3 / max(nl, 1)
     fl = interface_flops(probs, "fp32_mixed")
     achieved = fl / t_if
 
-    wall64, kt64, _, sizes64, _ = run_gpu(items, gks.GKS_FP64, a.steps, a.warmup)
+    wall64, kt64, _, sizes64, _, _ = run_gpu(items, gks.GKS_FP64, a.steps, a.warmup)
     ms64, nl64 = kt64["interface"]
     t_if64 = ms64 / 1e3 / max(nl64, 1)
     achieved64 = interface_flops(probs, "fp64") / t_if64
-    print(f"# batch fp64: {a.steps} steps in {wall64 * 1e3:.2f} ms; block sizes {sizes64}", file=sys.stderr, flush=True)
+    print(f"# batch fp64: {a.steps} steps in {wall64 * 1e3:.2f} ms; launch shapes {sizes64}", file=sys.stderr, flush=True)
 
     rec = counter_record()
     ops = json.load(open(OPCOUNTS))
@@ -271,6 +299,7 @@ def main():
         "config": {"workload": BATCH_WORKLOAD, "form": "GKS_FP32_MIXED", "problems": len(probs), "cells": cells,
                    "interfaces": sum(n_interfaces(p) for p in probs),
                    "viscous_grids": sum(bool(p.viscous) for p in probs)},
+        "launch": {"fp32_mixed": sizes, "fp64": sizes64, "interface_forms_fp32_mixed": forms},
         "long_window": None if wall_long is None else {
             "steps": a.long_steps, "value": round(cells * a.long_steps / wall_long / 1e6, 3),
             "ms_per_step": round(wall_long / a.long_steps * 1e3, 5)},
@@ -280,7 +309,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": PEAK_ALU / 1e12,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU, 5),
                      "traffic": rec.get("bytes_per_launch"),
-                     "kernel": "k_iface_2d<float> (one launch per step for all 96 grids)",
+                     "kernel": (f"k_iface_2d_loop<float> (persistent, {sizes['interface'][1]} blocks of "
+                                f"{sizes['interface'][0]}; one launch per step for all 96 grids)"
+                                if sizes["interface"][1] else
+                                f"k_iface_2d<float> (blocks of {sizes['interface'][0]}; one launch per step for all "
+                                "96 grids)"),
                      "interface_ms": round(t_if * 1e3, 5), "flops_per_launch": fl,
                      "flops_per_interface": {"euler": ops["interface_euler_fp32_mixed"]["total"],
                                              "navier_stokes": ops["interface_ns_fp32_mixed"]["total"]},

@@ -125,17 +125,27 @@ struct Grid {
   long long* steps;
   unsigned long long* err;    // 0, or the location of the first nonphysical state (see gks_fetch)
   unsigned long long* nfall;  // interior cells whose reconstruction fell back to the average (summed over steps)
-  unsigned long long* dtmin;  // kDtSlots running minima of the CFL bound (bits of positive doubles)
+  unsigned long long* dtmin;  // dtmask + 1 running minima of the CFL bound (bits of positive doubles)
+  unsigned dtmask;            // slots of the problem - 1 (a power of two minus one)
 };
 
-// The CFL bound is reduced into kDtSlots slots per problem (one atomic per
-// wave into slot wave % kDtSlots), which keeps the atomics on one address few.
-// The slots lie kDtStride words apart, each in a 256-byte block of its own:
-// atomics on one address are serialised in the memory system, so many
-// distinct addresses keep the reduction off the update's critical path.
+// The CFL bound is reduced into slots per problem (one atomic per wave of
+// cells, into slot (wave within the problem) & dtmask), which keeps the atomics
+// on one address few.  A problem has one slot per wave of its cells, rounded
+// up to a power of two within [64, kDtSlots]: up to kDtSlots waves no two
+// share a slot.  The slots lie kDtStride words apart, each in a 256-byte
+// block of its own: atomics on one address are serialised in the memory
+// system, so many distinct addresses keep the reduction off the update's
+// critical path.
 constexpr int kDtSlots = 512;
 constexpr int kDtStride = 32;
-constexpr size_t kScalBytes = 64 + kDtSlots * kDtStride * 8;  // t, dt, steps, err, fallbacks (+ padding), slots
+constexpr size_t kScalHead = 64;  // t, dt, steps, err, fallbacks (+ padding); the slots follow
+inline unsigned dt_slots(size_t cells) {
+  unsigned n = 64;
+  while (n < kDtSlots && (size_t)n * 64 < cells) n *= 2;
+  return n;
+}
+inline size_t scal_bytes(size_t cells) { return kScalHead + (size_t)dt_slots(cells) * kDtStride * 8; }
 
 // work decomposition of one launch kind over the problems of a group
 enum Kind { KK_GA = 0, KK_RECON, KK_FACE, KK_CELL, KK_OBST, KK_COUNT };  // boundary, cells+ring, interfaces, cells, step images
@@ -167,9 +177,22 @@ struct KA {
 // L2); logical blocks are assigned so that every XCD works on a contiguous
 // range of tiles (neighbouring rows share stencil data in its L2).  The map
 // is a bijection of [0, nblk).
-__device__ __forceinline__ unsigned logical_block(unsigned nblk) {
-  const unsigned b = blockIdx.x, per = nblk >> 3, rem = nblk & 7u, xcd = b & 7u, idx = b >> 3;
+// A persistent launch (a grid of a multiple of eight blocks, each taking
+// blocks b, b + gridDim.x, ...) keeps every block on its XCD's range.
+__device__ __forceinline__ unsigned logical_of(unsigned b, unsigned nblk) {
+  const unsigned per = nblk >> 3, rem = nblk & 7u, xcd = b & 7u, idx = b >> 3;
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+__device__ __forceinline__ unsigned logical_block(unsigned nblk) { return logical_of(blockIdx.x, nblk); }
+
+// the problem and the item index (local) of thread threadIdx.x of logical block L
+template <class PR>
+__device__ __forceinline__ const PR& locate_at(const KA<PR>& a, unsigned L, int kind, int& local, int* problem = nullptr) {
+  const int p = a.single ? 0 : (int)a.owner[L];
+  const PR& Q = a.probs[p];
+  local = (int)((L - Q.first[kind]) * blockDim.x + threadIdx.x);
+  if (problem) *problem = p;
+  return Q;
 }
 
 template <class PR>
@@ -392,8 +415,8 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
 // ctl[2p+1] = end time (0: none; the step is shortened to reach it, later
 // steps are empty); the slots are reset for the update of this step
 // The time step of a problem, taken by the first wave of its boundary launch
-// (all 64 lanes active): lane q reads CFL slots q, q + 64, ... and resets
-// them, a shuffle minimum gives the bound, lane 0 writes the step (the fixed
+// (all 64 lanes active): lane q reads the problem's CFL slots q, q + 64, ...
+// and resets them, a shuffle minimum gives the bound, lane 0 writes the step (the fixed
 // step if one is set, clipped to the end time if one is set; zero once the
 // problem has a nonphysical state).
 static_assert(kDtSlots % 64 == 0, "the slots split evenly over the lanes of a wave");
@@ -404,7 +427,8 @@ __device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ct
   unsigned long long m = ~0ull;
 #pragma unroll
   for (int r = 0; r < kDtSlots / 64; ++r) {  // all loads in flight at once
-    const unsigned long long o = g.dtmin[(lane + 64 * r) * kDtStride];
+    const unsigned q = lane + 64 * r;
+    const unsigned long long o = q <= g.dtmask ? g.dtmin[q * kDtStride] : ~0ull;
     m = o < m ? o : m;
   }
 #pragma unroll
@@ -414,7 +438,7 @@ __device__ void step_dt(const Prob<TS, TP, TC>& Q, const double* __restrict__ ct
   }
 #pragma unroll
   for (int r = 0; r < kDtSlots / 64; ++r)
-    g.dtmin[(lane + 64 * r) * kDtStride] = (unsigned long long)__double_as_longlong(1e300);
+    if (lane + 64 * r <= g.dtmask) g.dtmin[(lane + 64 * r) * kDtStride] = (unsigned long long)__double_as_longlong(1e300);
   if (lane == 0) {
     double dt = fixed > 0.0 ? fixed : Q.P.cfl * __longlong_as_double((long long)m);
     if (t_end > 0.0) dt = fmin(dt, fmax(t_end - t, 0.0));
@@ -612,12 +636,12 @@ __device__ __forceinline__ double cell_dt_bound_1d(const double* W, const Phys& 
 }
 
 // wave minimum of a positive bound, one atomic per wave into slot
-// (wave index) % kDtSlots (NaN bounds of a nonphysical cell are skipped; the
-// update flags that cell).  Every lane of the wave takes part.
-__device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slots, unsigned wave) {
+// (wave within the problem) & mask (NaN bounds of a nonphysical cell are
+// skipped; the update flags that cell).  Every lane of the wave takes part.
+__device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* slots, unsigned wave, unsigned mask) {
   if (!(b > 0.0) || !isfinite(b)) b = 1e300;
   for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_down(b, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave % kDtSlots) * kDtStride, (unsigned long long)__double_as_longlong(b));
+  if ((threadIdx.x & 63) == 0) atomicMin(slots + (wave & mask) * kDtStride, (unsigned long long)__double_as_longlong(b));
 }
 
 // ---------------------------------------------------------------------------
@@ -869,12 +893,12 @@ __device__ __forceinline__ void section_boundary() {
 // prologue, the hydrodynamic part and the kinetic parts of the two sides in
 // sequence, the frame record and the running sums in the thread's slots of
 // LDS, the flux and the point values stored once at the end.  No thread
-// reads another's slots (no barrier).
+// reads another's slots (no barrier), so a block may take several logical
+// blocks in turn.
 template <typename TS, typename TP, typename TC>
-__global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
-  extern __shared__ __align__(16) unsigned char lds[];
+__device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, unsigned L, unsigned char* lds) {
   int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_FACE, id);
+  const Prob<TS, TP, TC>& Q = locate_at(a, L, KK_FACE, id);
   const Grid<TS, TP> g = Q.g;
   if (id >= n_faces(g.ix)) return;
   const double dt = *g.dt;  // tested after the loads below, which do not wait for it
@@ -997,6 +1021,21 @@ __global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
   }
 }
 
+// one logical block per block
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  iface_2d_block(a, logical_block(a.nblk), lds);
+}
+
+// persistent form: gridDim.x (a multiple of 8) blocks take the logical
+// blocks in turn
+template <typename TS, typename TP, typename TC>
+__global__ void __launch_bounds__(256) k_iface_2d_loop(KA<Prob<TS, TP, TC>> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  for (unsigned b = blockIdx.x; b < a.nblk; b += gridDim.x) iface_2d_block(a, logical_of(b, a.nblk), lds);
+}
+
 // 1D interfaces 0..nx, fused
 template <typename TS, typename TP, typename TC>
 __global__ void __launch_bounds__(256) k_face_1d(KA<Prob<TS, TP, TC>> a) {
@@ -1096,7 +1135,7 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
     }
     bound = cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
   }
-  reduce_dt_bound(bound, g.dtmin, (blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  reduce_dt_bound(bound, g.dtmin, (unsigned)id >> 6, g.dtmask);
 }
 
 template <typename TS, typename TP, typename TC, bool kScan>
@@ -1132,12 +1171,15 @@ __global__ void __launch_bounds__(256) k_update_1d(KA<Prob<TS, TP, TC>> a) {
     }
     bound = cell_dt_bound_1d(W, Q.P, g.geo.h);
   }
-  reduce_dt_bound(bound, g.dtmin, (blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  reduce_dt_bound(bound, g.dtmin, (unsigned)id >> 6, g.dtmask);
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+
+struct Problem;
+size_t cells_of(const Problem& p);
 
 struct Problem {
   gks_problem spec;
@@ -1152,7 +1194,7 @@ struct Problem {
   void* PC = nullptr;
   void* FLX = nullptr;
   void* FLY = nullptr;
-  void* scal = nullptr;  // t, dt, steps, err, CFL slots (kScalBytes)
+  void* scal = nullptr;  // t, dt, steps, err, fallbacks, CFL slots (scal_bytes of the cells)
   void* recd = nullptr;  // (unused: the interface kernel keeps its frame record in LDS)
   void* rect = nullptr;
   bool borrowed = false;  // W, FX, FY belong to the caller (gks_init_device)
@@ -1169,6 +1211,7 @@ struct Group {
   unsigned nblk[KK_COUNT] = {};
   unsigned cap[KK_COUNT] = {};             // allocated owner entries
   int bs[KK_COUNT] = {256, 256, 256, 256, 64};  // block size of each kind
+  unsigned face_grid = 0;  // 2D interfaces: 0 one block per logical block, else a persistent grid of this many
   double* ctl = nullptr;                   // device [members][2]: fixed step, end time
   std::vector<double> ctl_host;            // values last uploaded
 };
@@ -1303,6 +1346,8 @@ void setup_problem(const gks_problem& s, Problem& p) {
   }
 }
 
+size_t cells_of(const Problem& p) { return p.spec.dim == 2 ? (size_t)p.ix.nx * p.ix.ny : (size_t)p.ix.nx; }
+
 size_t n_interfaces(const Idx& x) { return (size_t)x.fxr * x.ny + (size_t)x.nx * x.fyr; }
 
 // bytes of the buffers W, FX, FY, PC, FLX, FLY, scal, recd, rect of a problem
@@ -1314,11 +1359,12 @@ void buffer_sizes(const Problem& p, size_t (&sizes)[9]) {
     const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,      2 * 4 * (ny + 2) * (nx + 3) * ts,
                           2 * 4 * (ny + 3) * (nx + 2) * ts, 4 * 5 * (ny + 2) * (nx + 2) * ts,
                           4 * ny * (nx + 1) * 8,            4 * (ny + 1) * nx * 8,
-                          kScalBytes,                       0,
+                          scal_bytes(cells_of(p)),          0,
                           0};
     memcpy(sizes, sz, sizeof(sz));
   } else {
-    const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0, kScalBytes,
+    const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0,
+                          scal_bytes(cells_of(p)),
                           0, 0};
     memcpy(sizes, sz, sizeof(sz));
   }
@@ -1401,7 +1447,8 @@ Grid<TS, TP> grid_of(Problem& p) {
   g.steps = (long long*)(s + 2);
   g.err = (unsigned long long*)(s + 3);
   g.nfall = (unsigned long long*)(s + 4);
-  g.dtmin = (unsigned long long*)(s + 8);
+  g.dtmin = (unsigned long long*)((char*)p.scal + kScalHead);
+  g.dtmask = dt_slots(cells_of(p)) - 1;
   return g;
 }
 
@@ -1490,11 +1537,12 @@ void collect(gks_handle* h) {
 
 // One step of a group of problems of dimension `dim` (2D: characteristic
 // reconstruction if chr; the step-image launch if it has blocks): the launch
-// arguments A and block sizes bs of each launch kind, the per-problem fixed
-// step / end time array ctl.  h (may be null) records kernel timing.
+// arguments A and block sizes bs of each launch kind, the persistent grid of
+// the 2D interface launch (0: one block per logical block), the per-problem
+// fixed step / end time array ctl.  h (may be null) records kernel timing.
 template <typename TS, typename TP, typename TC>
 void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const int (&bs)[KK_COUNT], int dim,
-                 bool chr, const double* ctl, hipStream_t st) {
+                 bool chr, unsigned face_grid, const double* ctl, hipStream_t st) {
   using PR = Prob<TS, TP, TC>;
   record_begin(h, st);
   if (dim == 2) {
@@ -1514,7 +1562,11 @@ void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const
   record_end(h, st, GKS_K_RECON);
   record_begin(h, st);
   if (dim == 2) {
-    k_iface_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], bs[KK_FACE] * iface_lds_per_thread<TC>(), st>>>(A[KK_FACE]);
+    const size_t lds = bs[KK_FACE] * iface_lds_per_thread<TC>();
+    if (face_grid)
+      k_iface_2d_loop<TS, TP, TC><<<face_grid, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
+    else
+      k_iface_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
   } else {
     k_face_1d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   }
@@ -1534,7 +1586,7 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   KA<PR> A[KK_COUNT];
   const int single = G.members.size() == 1;
   for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k], single};
-  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.ctl, st);
+  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.dim == 2 ? G.face_grid : 0u, G.ctl, st);
 }
 
 void enqueue_step(gks_handle* h, hipStream_t st) {
@@ -1703,9 +1755,10 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     // the clears above must land before the blocking uploads below
     if (hipStreamSynchronize(h->stream) != hipSuccess) return init_fail(GKS_EDEVICE, "hipStreamSynchronize failed");
     const double scal0[4] = {s.t0, 0.0, 0.0, 0.0};
-    const std::vector<unsigned long long> inf(kDtSlots * kDtStride, 0x7e37e43c8800759cull);  // bits of 1e300
+    const size_t slot_words = (size_t)dt_slots(cells_of(p)) * kDtStride;
+    const std::vector<unsigned long long> inf(slot_words, 0x7e37e43c8800759cull);  // bits of 1e300
     if (hipMemcpy(p.scal, scal0, sizeof(scal0), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy((char*)p.scal + 64, inf.data(), kDtSlots * kDtStride * 8, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy((char*)p.scal + kScalHead, inf.data(), slot_words * 8, hipMemcpyHostToDevice) != hipSuccess)
       return init_fail(GKS_EDEVICE, "upload failed");
     if (dev) continue;
     // upload: host layouts without ghosts -> ghosted device layouts
@@ -1846,7 +1899,7 @@ __global__ void __launch_bounds__(256) k_noalloc_setup(PR desc, PR* dst, double*
     *desc.g.err = 0;
     *desc.g.nfall = 0;
   }
-  for (int q = threadIdx.x; q < kDtSlots; q += blockDim.x)
+  for (unsigned q = threadIdx.x; q <= desc.g.dtmask; q += blockDim.x)
     desc.g.dtmin[q * kDtStride] = (unsigned long long)__double_as_longlong(1e300);
 }
 
@@ -1902,12 +1955,31 @@ int noalloc_run(Problem& p, char* base, int32_t nsteps, double dt_fixed, double 
   else
     k_update_1d<TS, TP, TC, true><<<A[KK_CELL].nblk, bs[KK_CELL], 0, st>>>(A[KK_CELL]);
   const bool chr = dim == 2 && p.spec.recon_vars == 1;
-  for (int32_t n = 0; n < nsteps; ++n) launch_step<TS, TP, TC>(nullptr, A, bs, dim, chr, ctl, st);
+  for (int32_t n = 0; n < nsteps; ++n) launch_step<TS, TP, TC>(nullptr, A, bs, dim, chr, 0u, ctl, st);
   if (status) k_noalloc_status<PR><<<1, 1, 0, st>>>(dprob, status);
   return hipGetLastError() == hipSuccess ? GKS_OK : GKS_EDEVICE;
 }
 
 }  // namespace
+
+// the persistent grid of a 2D group's interface launch: the blocks of its
+// present size that fit on the device at once, a multiple of 8
+template <typename TS, typename TP, typename TC>
+int persistent_grid_of(gks_handle* h, int bs, unsigned* grid) {
+  int per_cu = 0, cus = 0, dev = 0;
+  HIP_OR(h, hipGetDevice(&dev));
+  HIP_OR(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OR(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iface_2d_loop<TS, TP, TC>, bs,
+                                                         (size_t)bs * iface_lds_per_thread<TC>()));
+  const unsigned n = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(cus > 0 ? cus : 8);
+  *grid = n < 8 ? 8u : n & ~7u;
+  return GKS_OK;
+}
+
+int persistent_face_grid(gks_handle* h, const Group& G, unsigned* grid) {
+  return G.mixed ? persistent_grid_of<float, float, float>(h, G.bs[KK_FACE], grid)
+                 : persistent_grid_of<double, double, double>(h, G.bs[KK_FACE], grid);
+}
 
 extern "C" {
 
@@ -2135,7 +2207,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
     const Saved s[4] = {{p.W, nullptr, (two ? 4 * (ny + 4) : 3) * (nx + 4) * 8},
                         {p.FX, nullptr, (two ? 2 * 4 * (ny + 2) : 3) * (nx + 3) * ts},
                         {p.FY, nullptr, two ? 2 * 4 * (ny + 3) * (nx + 2) * ts : 0},
-                        {p.scal, nullptr, kScalBytes}};
+                        {p.scal, nullptr, scal_bytes(cells_of(p))}};
     for (const Saved& x : s) {
       if (!x.bytes) continue;
       Saved y = x;
@@ -2173,44 +2245,53 @@ int gks_tune(gks_handle* h, int32_t steps) {
   collect(h);
   memcpy(saved_time, h->ktime, sizeof(saved_time));
   memcpy(saved_launch, h->klaunch, sizeof(saved_launch));
+  // one warm-up step, then `steps` timed steps (kernel times in h->ktime),
+  // then the saved state back
+  auto time_steps = [&]() -> int {
+    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
+    h->profiling = 1;
+    enqueue_step(h, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, GKS_EDEVICE, "tuning step failed");
+    collect(h);
+    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
+    for (int s = 0; s < steps; ++s) enqueue_step(h, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, GKS_EDEVICE, "tuning step failed");
+    collect(h);
+    return restore();
+  };
+  for (Group& G : h->groups) G.face_grid = 0;
   for (int c = 0; c < 3 && rc == GKS_OK; ++c) {
     for (Group& G : h->groups) {
       for (int k = 0; k < KK_COUNT; ++k) G.bs[k] = cand[c];
       if ((rc = build_tables(h, G)) != GKS_OK) break;
     }
-    if (rc != GKS_OK) break;
-    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
-    h->profiling = 1;
-    enqueue_step(h, h->stream);  // warm-up
-    if (hipStreamSynchronize(h->stream) != hipSuccess) {
-      rc = fail(h, GKS_EDEVICE, "tuning step failed");
-      break;
-    }
-    collect(h);
-    for (int k = 0; k < GKS_K_COUNT; ++k) h->ktime[k] = 0.0;
-    for (int s = 0; s < steps; ++s) enqueue_step(h, h->stream);
-    if (hipStreamSynchronize(h->stream) != hipSuccess) {
-      rc = fail(h, GKS_EDEVICE, "tuning step failed");
-      break;
-    }
-    collect(h);
+    if (rc != GKS_OK || (rc = time_steps()) != GKS_OK) break;
     for (int k = 0; k < GKS_K_COUNT; ++k)
       if (k != GKS_K_DT && h->ktime[k] < best_t[k]) {
         best_t[k] = h->ktime[k];
         best_bs[k] = cand[c];
       }
-    if ((rc = restore()) != GKS_OK) break;
   }
-  h->profiling = saved_prof;
-  memcpy(h->ktime, saved_time, sizeof(saved_time));
-  memcpy(h->klaunch, saved_launch, sizeof(saved_launch));
   if (rc == GKS_OK) {
     for (Group& G : h->groups) {
       for (int k = 0; k < KK_COUNT; ++k) G.bs[k] = best_bs[cls[k]];
       if ((rc = build_tables(h, G)) != GKS_OK) break;
     }
   }
-  drop_graph(h);
+  // then the persistent form of the 2D interface launch at that block size:
+  // as many blocks as fit on the device at once (a multiple of 8)
+  bool any2d = false;
+  for (Group& G : h->groups) any2d |= G.dim == 2;
+  if (rc == GKS_OK && any2d) {
+    for (Group& G : h->groups)
+      if (G.dim == 2 && (rc = persistent_face_grid(h, G, &G.face_grid)) != GKS_OK) break;
+    if (rc == GKS_OK) rc = time_steps();
+    if (rc == GKS_OK && !(h->ktime[GKS_K_INTERFACE] < best_t[GKS_K_INTERFACE]))
+      for (Group& G : h->groups) G.face_grid = 0;
+  }
+  h->profiling = saved_prof;
+  memcpy(h->ktime, saved_time, sizeof(saved_time));
+  memcpy(h->klaunch, saved_launch, sizeof(saved_launch));
   if (rc == GKS_OK) rc = restore();
   for (const Saved& y : saved) (void)hipFree(y.copy);
   if (rc != GKS_OK) h->sticky = rc;
@@ -2221,6 +2302,38 @@ int gks_block_size(gks_handle* h, int32_t kernel, int32_t* threads) {
   if (!h || !threads || kernel < 0 || kernel >= GKS_K_COUNT) return GKS_EINVAL;
   static const int kind_of[GKS_K_COUNT] = {KK_GA, -1, KK_RECON, KK_FACE, KK_CELL};
   *threads = kind_of[kernel] < 0 ? 64 : h->groups[0].bs[kind_of[kernel]];
+  return GKS_OK;
+}
+
+int gks_launch_shape(gks_handle* h, int32_t kernel, int32_t* threads, int32_t* grid) {
+  if (!h || !threads || !grid || kernel < 0 || kernel >= GKS_K_COUNT) return GKS_EINVAL;
+  int rc = gks_block_size(h, kernel, threads);
+  *grid = 0;
+  if (kernel == GKS_K_INTERFACE)
+    for (const Group& G : h->groups)
+      if (G.dim == 2) *grid = (int32_t)G.face_grid;
+  return rc;
+}
+
+int gks_set_launch(gks_handle* h, int32_t kernel, int32_t threads, int32_t grid) {
+  if (!h) return GKS_EINVAL;
+  if (h->sticky != GKS_OK) return fail(h, GKS_ESTATE, "handle in error state: " + h->msg);
+  if (kernel < 0 || kernel >= GKS_K_COUNT || kernel == GKS_K_DT)
+    return fail(h, GKS_EINVAL, "no such kernel class");
+  if (threads != 64 && threads != 128 && threads != 256) return fail(h, GKS_EINVAL, "threads must be 64, 128 or 256");
+  if (grid != 0 && (kernel != GKS_K_INTERFACE || grid < 8 || grid > 65536 || grid % 8))
+    return fail(h, GKS_EINVAL, "a persistent grid (a multiple of 8 in [8, 65536]) exists for the interface kernel only");
+  HIP_OR(h, hipStreamSynchronize(h->stream));
+  for (Group& G : h->groups) {
+    for (int k = 0; k < KK_COUNT; ++k) {
+      static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE, GKS_K_GHOST};
+      if (cls[k] == kernel) G.bs[k] = threads;
+    }
+    if (kernel == GKS_K_INTERFACE) G.face_grid = G.dim == 2 ? (unsigned)grid : 0u;
+    int rc = build_tables(h, G);
+    if (rc != GKS_OK) return rc;
+  }
+  drop_graph(h);
   return GKS_OK;
 }
 

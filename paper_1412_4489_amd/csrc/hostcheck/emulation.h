@@ -211,6 +211,17 @@ inline hipError_t hipGetDevice(int* d) {
   *d = 0;
   return hipSuccess;
 }
+// a small device: 2 compute units, 2 blocks of any shape per unit
+enum { hipDeviceAttributeMultiprocessorCount = 1 };
+inline hipError_t hipDeviceGetAttribute(int* v, int attr, int) {
+  *v = attr == hipDeviceAttributeMultiprocessorCount ? 2 : 0;
+  return hipSuccess;
+}
+template <typename F>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, F, int, size_t) {
+  *n = 2;
+  return hipSuccess;
+}
 inline hipError_t hipMemGetAddressRange(void** base, size_t* size, void* p) {
   const char* b;
   if (!emu_find(p, &b, size)) return 1;

@@ -2,8 +2,8 @@
 
 The functions keep the C names (gks_init, gks_init_device, gks_state_extent,
 gks_step, gks_fetch, gks_destroy, gks_last_error, gks_profile, gks_kernel_time,
-gks_tune, gks_block_size, gks_fallbacks, gks_step_noalloc) and only marshal
-arguments;
+gks_tune, gks_block_size, gks_set_launch, gks_launch_shape, gks_fallbacks,
+gks_step_noalloc) and only marshal arguments;
 every step of the scheme runs in the HIP kernels of the library.  `Solver`
 wraps a handle for numpy arrays laid out as in paper_1412_4489_amd.workloads.
 
@@ -82,6 +82,8 @@ def lib():
         L.gks_kernel_time.argtypes = [_P, C.c_int32, _D, C.POINTER(C.c_int64)]
         L.gks_tune.argtypes = [_P, C.c_int32]
         L.gks_block_size.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32)]
+        L.gks_set_launch.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
+        L.gks_launch_shape.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.gks_fallbacks.argtypes = [_P, C.c_int32, C.POINTER(C.c_int64)]
         L.gks_step_noalloc.argtypes = [C.POINTER(gks_problem), _P, _P, _P, C.c_int32, C.c_double, C.c_double, _P,
                                        _P]
@@ -90,7 +92,8 @@ def lib():
 
 
 EXPORTED = ("gks_init", "gks_init_device", "gks_state_extent", "gks_step", "gks_fetch", "gks_destroy", "gks_last_error",
-            "gks_profile", "gks_kernel_time", "gks_tune", "gks_block_size", "gks_fallbacks", "gks_step_noalloc")
+            "gks_profile", "gks_kernel_time", "gks_tune", "gks_block_size", "gks_set_launch", "gks_launch_shape",
+            "gks_fallbacks", "gks_step_noalloc")
 
 
 def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
@@ -290,6 +293,23 @@ def gks_block_size(h, kernel):
     return n.value
 
 
+def gks_set_launch(h, kernel, threads, grid=0):
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    rc = lib().gks_set_launch(h, k, int(threads), int(grid))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+
+
+def gks_launch_shape(h, kernel):
+    """(threads per block, persistent grid or 0) of a kernel class"""
+    n, g = C.c_int32(), C.c_int32()
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    rc = lib().gks_launch_shape(h, k, C.byref(n), C.byref(g))
+    if rc != GKS_OK:
+        raise GKSError(rc, gks_last_error(h))
+    return n.value, g.value
+
+
 def gks_step_noalloc(prob, d_cell, d_face_x, d_face_y, nsteps, dt_fixed=0.0, t_end=0.0, d_status=None,
                      precision=GKS_FP64, stream=None, t0=0.0):
     """Allocation-free stepping of one problem on device buffers in the
@@ -332,6 +352,12 @@ class Solver:
     def tune(self, steps=3):
         gks_tune(self.h, steps)
         return {k: gks_block_size(self.h, k) for k in KERNELS}
+
+    def set_launch(self, kernel, threads, grid=0):
+        gks_set_launch(self.h, kernel, threads, grid)
+
+    def launch_shape(self, kernel):
+        return gks_launch_shape(self.h, kernel)
 
     def fetch(self, k=0, check=True):
         return gks_fetch(self.h, k, self.probs[k], check)

@@ -153,6 +153,16 @@ for tune in (False, True):
 same = all(np.array_equal(a, b) for a, b in zip(*outs))
 bad += not same
 print(f"tuned block sizes {sizes}: results {'identical' if same else 'DIFFER'}", flush=True)
+# the persistent interface launch (8 blocks taking the tiles in turn)
+with gks.Solver([q[0] for q in pair], [q[1] for q in pair],
+                precision=[gks.GKS_FP64, gks.GKS_FP32_MIXED, gks.GKS_FP64]) as S:
+    S.set_launch("interface", 64, 8)
+    shape = S.launch_shape("interface")
+    S.step(2, dt=[1e-3, 1e-3, 1e-3])
+    pers = [S.fetch(k)[0].cell for k in range(3)]
+same = shape == (64, 8) and all(np.array_equal(a, b) for a, b in zip(outs[0], pers))
+bad += not same
+print(f"persistent interface launch {shape}: results {'identical' if same else 'DIFFER'}", flush=True)
 # device-borrow form: the caller's buffers (emulated device memory) with NaN in
 # every ghost entry, stepped in place; bitwise the host-copy form's results
 import ctypes as C  # noqa: E402

@@ -120,3 +120,27 @@ def test_full_batch_96_grids_sampled(G, oracle):
         if _smooth(p):
             oracle.step(p, r, dts[k], dts[k])
             assert _rel(second[k].cell, r.cell) < 5e-6, p.name
+
+
+@pytest.mark.parametrize("grid", [8, 256, 2048])
+def test_persistent_interface_launch_is_bitwise_neutral(G, grid):
+    """The persistent form of the interface launch (grid blocks taking the
+    tiles in turn) gives the one-block-per-tile results bitwise, in both
+    forms; bad shapes are refused."""
+    items = _mini_batch()
+    probs, states = [p for p, _ in items], [s for _, s in items]
+    for prec in (G.GKS_FP64, G.GKS_FP32_MIXED):
+        out = []
+        for pers in (False, True):
+            with G.Solver(probs, states, precision=prec) as S:
+                if pers:
+                    S.set_launch("interface", 128, grid)
+                    assert S.launch_shape("interface") == (128, grid)
+                S.step(3)
+                out.append([S.fetch(k)[0] for k in range(len(probs))])
+        for a, b in zip(*out):
+            assert np.array_equal(a.cell, b.cell) and np.array_equal(a.fx, b.fx) and np.array_equal(a.fy, b.fy)
+    with G.Solver(probs, states) as S:
+        for kernel, threads, g in (("interface", 128, 12), ("recon", 128, 8), ("interface", 96, 0)):
+            with pytest.raises(G.GKSError):
+                S.set_launch(kernel, threads, g)

@@ -32,3 +32,4 @@ def test_kernels_in_bounds_under_asan(tmp_path):
     assert "ERROR: AddressSanitizer" not in r.stderr
     assert "batch ok" in r.stdout
     assert "division ok" in r.stdout
+    assert "persistent interface launch (64, 8): results identical" in r.stdout
