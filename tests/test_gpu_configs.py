@@ -1,0 +1,232 @@
+"""The full-size configurations at their stated tolerances against the FP64
+oracle, through the C ABI.
+
+* Batch (96 grids, the benchmark's workload, advanced together in one
+  handle): every grid is compared with the oracle run alone.  The
+  isentropic-vortex grids (smooth, Euler and Navier-Stokes) run free for 20
+  fixed steps: relative L1 of rho and of the energy <= 1e-5 (FP32-mixed) and
+  <= 1e-11 (FP64).  The Riemann grids (discontinuous: a limiter branch may
+  flip on a rounding-level difference, so free-running states part) are
+  compared step by step: the first step, and one step from the GPU's state
+  after 20, each element by element against the oracle's step from the same
+  state; the two forms' states after 20 steps stay within 1e-3 relative L1
+  of each other.
+* Lid-driven cavity 512^2, Re 1000 (Sec. 4.8): 200 fixed steps from rest
+  against the oracle's 200 steps (tests/golden/make_cavity512.py writes
+  them): relative L1 of every component <= 1e-11 (FP64); of rho and the
+  energy <= 1e-5, of the momenta on the lid-momentum scale <= 1e-5
+  (FP32-mixed).
+* Double Mach reflection 1920 x 480 (Sec. 4.5): the GPU runs to t = 0.05,
+  0.1 and 0.2; from each of those states one more step on the GPU and in
+  the oracle, element by element.
+Element by element means: FP64 1e-11 (cells) and 1e-10 (point values) of
+each component's magnitude; FP32-mixed 5e-6 and 1e-5 relative L1 per
+component, and 1e-3 for any single value (see _one_step).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1412_4489_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NSTEPS = 20
+CHUNKS = 8
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1412_4489_amd import gks
+    gks.lib()
+    return gks
+
+
+def _rel_l1(a, b):
+    assert np.isfinite(a).all()
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _rel_l1_each(a, b):
+    """largest over the components of the relative L1 difference (axis -3 is
+    the component axis)"""
+    assert np.isfinite(a).all() and np.isfinite(b).all()
+    vax = b.ndim - 3
+    ax = tuple(k for k in range(b.ndim) if k != vax)
+    return float((np.abs(a - b).sum(axis=ax) / np.maximum(np.abs(b).sum(axis=ax), 1e-300)).max())
+
+
+def _one_step(form, nxt, ref, what):
+    """One step from the same state.  FP64: every cell average and point
+    value to 1e-11 / 1e-10 of its component's magnitude.  FP32-mixed: the
+    limiter's decisions (minmod signs, the smallest cross-derivative
+    candidate, the admissibility fallback) are taken in single precision, and
+    a decision within its rounding may go the other way than the oracle's
+    double-precision one, a legitimate alternative result; so the bound is
+    5e-6 relative L1 per component for the cell averages and 1e-5 for the
+    point values, and 1e-3 of the component's magnitude for any one value."""
+    if form == "fp64":
+        ec, ef, eg = _rel_max(nxt.cell, ref.cell), _rel_max(nxt.fx, ref.fx), _rel_max(nxt.fy, ref.fy)
+        assert ec < 1e-11 and ef < 1e-10 and eg < 1e-10, (what, ec, ef, eg)
+        return f"max {ec:.1e} cells, {max(ef, eg):.1e} point values"
+    lc = _rel_l1_each(nxt.cell, ref.cell)
+    lp = max(_rel_l1_each(nxt.fx, ref.fx), _rel_l1_each(nxt.fy, ref.fy))
+    mc = _rel_max(nxt.cell, ref.cell)
+    mp = max(_rel_max(nxt.fx, ref.fx), _rel_max(nxt.fy, ref.fy))
+    assert lc < 5e-6 and lp < 1e-5 and mc < 1e-3 and mp < 1e-3, (what, lc, lp, mc, mp)
+    scale = np.abs(ref.cell).max(axis=(1, 2), keepdims=True)
+    scale[1:3] = scale[1:3].max()
+    over = int((np.abs(nxt.cell - ref.cell) / scale > 5e-6).any(axis=0).sum())
+    return (f"L1 {lc:.1e} cells, {lp:.1e} point values; max {mc:.1e}, {mp:.1e}; "
+            f"{over} of {ref.cell[0].size} cells beyond 5e-6")
+
+
+def _rel_max(a, b):
+    """max |a - b| relative to each component's magnitude (the momenta share
+    the momentum vector's); a and b are cell[nv][ny][nx] or
+    faces[ng][nv][..][..]"""
+    assert np.isfinite(a).all() and np.isfinite(b).all()
+    vax = b.ndim - 3
+    scale = np.abs(b).max(axis=tuple(k for k in range(b.ndim) if k != vax), keepdims=True)
+    idx = [slice(None)] * b.ndim
+    idx[vax] = slice(1, 3)
+    scale[tuple(idx)] = scale[tuple(idx)].max()
+    return float((np.abs(a - b) / np.maximum(scale, 1e-300)).max())
+
+
+@pytest.fixture(scope="module")
+def batch_run(G, oracle):
+    """The 96-grid batch in one handle per form at 0.8 of each grid's initial
+    CFL step: the states after 1 and after NSTEPS steps; then one more step
+    of the Riemann grids from their NSTEPS-step states (a second handle
+    started at their time)."""
+    items = W.batch()
+    probs, states = [p for p, _ in items], [s for _, s in items]
+    dts = [0.8 * oracle.dt(p, s) for p, s in items]
+    riem = [k for k, p in enumerate(probs) if "riemann" in p.name]
+    out = {}
+    for form, prec in (("fp64", G.GKS_FP64), ("fp32_mixed", G.GKS_FP32_MIXED)):
+        with G.Solver(probs, states, prec) as S:
+            S.step(1, dt=dts)
+            one = [S.fetch(k)[0] for k in range(len(probs))]
+            S.step(NSTEPS - 1, dt=dts)
+            got = [S.fetch(k) for k in range(len(probs))]
+        assert all(n == NSTEPS for _, _, n in got)
+        with G.Solver([probs[k] for k in riem], [got[k][0] for k in riem], prec,
+                      t0=[got[k][1] for k in riem]) as S:
+            S.step(1, dt=[dts[k] for k in riem])
+            nxt = {k: S.fetch(m)[0] for m, k in enumerate(riem)}
+        out[form] = (one, [g for g, _, _ in got], nxt)
+    print(f"batch: {len(probs)} grids, {len(riem)} Riemann, {NSTEPS} steps in both forms", flush=True)
+    return items, dts, out
+
+
+@pytest.mark.parametrize("chunk", range(CHUNKS))
+def test_batch_grids_against_the_oracle_alone(batch_run, oracle, chunk):
+    items, dts, out = batch_run
+    for k in range(chunk, len(items), CHUNKS):
+        p, s = items[k]
+        if "vortex" in p.name:
+            ref = s.copy()
+            n, _ = oracle.run(p, ref, nsteps=NSTEPS, dt_fixed=dts[k])
+            assert n == NSTEPS
+            for form, tol in (("fp64", 1e-11), ("fp32_mixed", 1e-5)):
+                got = out[form][1][k]
+                e = max(_rel_l1(got.cell[v], ref.cell[v]) for v in (0, 3))
+                assert e < tol, (p.name, form, e)
+        else:
+            ref1 = s.copy()
+            oracle.step(p, ref1, dts[k], 0.0)
+            for form in ("fp64", "fp32_mixed"):
+                r1 = _one_step(form, out[form][0][k], ref1, (p.name, form, "step 1"))
+                ref = out[form][1][k].copy()
+                oracle.step(p, ref, dts[k], NSTEPS * dts[k])
+                r21 = _one_step(form, out[form][2][k], ref, (p.name, form, f"step {NSTEPS + 1}"))
+                print(f"{p.name} {form}: step 1 {r1}; step {NSTEPS + 1} {r21}", flush=True)
+            spread = _rel_l1(out["fp32_mixed"][1][k].cell[0], out["fp64"][1][k].cell[0])
+            assert spread < 1e-3, (p.name, spread)
+
+
+def test_cavity_512_against_the_oracle_200_steps(G):
+    """After 200 steps from rest the flow is confined to the lid's layer: the
+    momenta are a few 1e-4 of the lid momentum on average, so their
+    differences are measured on the lid-momentum scale (relative L1 of their
+    own fields is printed too, with where the v-momentum differs most)."""
+    path = os.path.join(GOLDEN, "cavity512_re1000_200steps.npz")
+    gold = np.load(path)
+    dt, steps = float(gold["dt"]), int(gold["steps"])
+    prob, st = W.cavity(512)
+    ref = st.cell + gold["dcell"]
+    ulid = prob.bc[3].wall[0]
+    for form, prec, tol in (("fp64", G.GKS_FP64, 1e-11), ("fp32_mixed", G.GKS_FP32_MIXED, 1e-5)):
+        with G.Solver(prob, st, prec) as S:
+            S.step(steps, dt=dt)
+            got, t, n = S.fetch()
+        assert n == steps
+        own = [_rel_l1(got.cell[v], ref[v]) for v in range(4)]
+        lid = [float(np.abs(got.cell[v] - ref[v]).mean() / ulid) for v in (1, 2)]
+        dv = np.abs(got.cell[2] - ref[2])
+        corners = (dv[-8:, :8].sum() + dv[-8:, -8:].sum()) / max(dv.sum(), 1e-300)
+        jm, im = np.unravel_index(np.argmax(dv), dv.shape)
+        print(f"cavity 512^2 {form}, {steps} steps: relative L1 of rho, rho u, rho v, E {own}; "
+              f"momenta on the lid scale {lid}; largest rho v difference at cell (j, i) = ({jm}, {im}), "
+              f"share of its L1 in the 8 x 8 cells at the lid's corners {corners:.2f}", flush=True)
+        if form == "fp64":
+            assert max(own) < tol, (form, own)
+        else:
+            assert max(own[0], own[3], *lid) < tol, (form, own, lid)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_mixed"])
+def test_double_mach_reflection_1920x480_late_steps(G, oracle, form):
+    prec = G.GKS_FP64 if form == "fp64" else G.GKS_FP32_MIXED
+    prob, st = W.dmr(1920, 480)
+    t_prev = 0.0
+    state = st
+    for t_stop in (0.05, 0.1, 0.2):
+        with G.Solver(prob, state, prec, t0=t_prev) as S:
+            S.step(100000, t_end=t_stop)
+            got, t, n = S.fetch()
+        assert t == pytest.approx(t_stop, rel=0, abs=1e-12)
+        dt = 0.8 * oracle.dt(prob, got)
+        ref = got.copy()
+        oracle.step(prob, ref, dt, t)
+        with G.Solver(prob, got, prec, t0=t) as S:
+            S.step(1, dt=dt)
+            nxt, _, _ = S.fetch()
+        r = _one_step(form, nxt, ref, (form, t_stop))
+        print(f"dmr 1920x480 {form} at t = {t_stop}: one step vs the oracle: {r}", flush=True)
+        state, t_prev = got, t
+
+
+@pytest.mark.skipif(os.environ.get("GKS_LONG") != "1", reason="about 5 minutes of GPU time: set GKS_LONG=1")
+def test_cavity_512_twenty_lid_transits_fp32_mixed_against_fp64(G):
+    """Sec. 4.8, Re 1000 on 512^2 to t = 20 L / U_lid (about 450 000 CFL
+    steps) in both forms; reports the largest differences of u along the
+    vertical centreline and of v along the horizontal one, relative to the
+    lid speed, and the minimum of u on the vertical centreline."""
+    prob, st = W.cavity(512)
+    n = prob.nx
+    ulid = prob.bc[3].wall[0]
+    prof = {}
+    for form, prec in (("fp64", G.GKS_FP64), ("fp32_mixed", G.GKS_FP32_MIXED)):
+        with G.Solver(prob, st, prec) as S:
+            t = 0.0
+            while t < prob.t_end * (1 - 1e-14):
+                S.step(50000, t_end=prob.t_end)
+                got, t, steps = S.fetch()
+                print(f"cavity 512^2 {form}: t = {t:.3f} of {prob.t_end:.3f} after {steps} steps", flush=True)
+        c = got.cell
+        u, v = c[1] / c[0], c[2] / c[0]
+        prof[form] = (0.5 * (u[:, n // 2 - 1] + u[:, n // 2]), 0.5 * (v[n // 2 - 1, :] + v[n // 2, :]))
+    du = np.abs(prof["fp32_mixed"][0] - prof["fp64"][0]).max() / ulid
+    dv = np.abs(prof["fp32_mixed"][1] - prof["fp64"][1]).max() / ulid
+    umin = prof["fp64"][0].min() / ulid
+    print(f"cavity 512^2 after 20 lid transits: centreline max |u32 - u64| / U = {du:.2e}, "
+          f"max |v32 - v64| / U = {dv:.2e}; min u / U on x = 1/2: {umin:.4f}", flush=True)
+    assert du < 1e-2 and dv < 1e-2
