@@ -1364,6 +1364,33 @@ static int solid(const orc_problem* P, int i, int j) {
   return P->obst_nj > 0 && i >= P->obst_i0 && j < P->obst_nj;
 }
 
+/* Reading (Sec. 4.6: reflective walls of the step): at an interface
+ * between a gas cell and a solid cell, the solid side is the mirror image
+ * of the gas side across that interface.  In the interface frame (component
+ * 1 the normal momentum, derivatives n along the normal) its interface
+ * values are the gas side's with the normal momentum negated and with every
+ * odd order in n negated, and its row of the equilibrium stencil is the
+ * image of the gas row.  The mirror makes the interface pass no mass.  The
+ * layers of solid images (fill_obstacle_2d) still serve the reconstruction
+ * of the gas cells; they cannot do this at the corner, where one solid cell
+ * would have to be the image across two faces: with the solid cells' own
+ * polynomials there, mass passes through the step's walls next to the
+ * corner and the cell above the corner empties (240 x 80 and 360 x 120 cells
+ * of the Mach 3 flow, before t = 2). */
+static void wall_mirror(orc_face_input* in, int s, int nv) {
+  int g = 1 - s;
+  for (int v = 0; v < nv; ++v) {
+    double sg = v == 1 ? -1.0 : 1.0;
+    in->W[s][v] = sg * in->W[g][v];
+    in->Wn[s][v] = -sg * in->Wn[g][v];
+    in->Ws[s][v] = sg * in->Ws[g][v];
+    in->Wnn[s][v] = sg * in->Wnn[g][v];
+    in->Wns[s][v] = -sg * in->Wns[g][v];
+    in->Wss[s][v] = sg * in->Wss[g][v];
+    for (int n = 0; n < 3; ++n) in->Ueq[s][n][v] = sg * in->Ueq[g][n][v];
+  }
+}
+
 /* negate the momentum along x (ax = 0) and/or y (ax = 1) */
 static void flip(const double* Ws, int fu, int fv, double* Wg) {
   for (int v = 0; v < 4; ++v) Wg[v] = Ws[v];
@@ -1373,8 +1400,10 @@ static void flip(const double* Ws, int fu, int fv, double* Wg) {
 
 /* Reading (the paper defers the corner to an external reference): the two
  * layers of solid cells along the step's faces are slip-wall images of the
- * gas: below the top face the image across it (v negated), and beside the
- * vertical face, below those two rows, the image across that face (u
+ * gas, for the reconstruction of the gas cells next to the step (the
+ * interfaces on the step's faces take the face-wise image of wall_mirror
+ * instead): below the top face the image across it (v negated), and beside
+ * the vertical face, below those two rows, the image across that face (u
  * negated).  The 2 x 2 block at the corner thus takes the image across the
  * top face.  (Its image through the corner point lets the expansion round
  * the corner empty the cells above the step: the Mach 3 flow of Sec. 4.6
@@ -1514,6 +1543,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 3; ++n)
           for (int v = 0; v < nv; ++v) in.Ueq[m][n][v] = GW(G, v, j - 1 + n, fi - 1 + m);
+      if (solid(P, fi - 1, j) != solid(P, fi, j)) wall_mirror(&in, solid(P, fi - 1, j) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
       for (int v = 0; v < nv; ++v) {
@@ -1545,6 +1575,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 3; ++n)
           for (int v = 0; v < nv; ++v) in.Ueq[m][n][sw[v]] = GW(G, v, fj - 1 + m, i - 1 + n);
+      if (solid(P, i, fj - 1) != solid(P, i, fj)) wall_mirror(&in, solid(P, i, fj - 1) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
       for (int v = 0; v < nv; ++v) {
