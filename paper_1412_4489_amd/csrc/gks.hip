@@ -874,6 +874,36 @@ __device__ __forceinline__ void load_face_cell(const Grid<TS, TP>& g, const Face
   }
 }
 
+// Reflective walls of the solid step (Sec. 4.6): on an interface between a
+// gas cell and a solid cell the solid side is the mirror image of the gas
+// side across that interface, so the wall passes no mass.  (The solid image
+// layers serve the gas cells' reconstruction; at the corner one solid cell
+// cannot be the image across both faces.)  wall_side: the solid side (0 or
+// 1) of interface F, -1 if it is no wall.
+template <class PR>
+__device__ __forceinline__ int wall_side(const PR& Q, const Face& F) {
+  if (Q.obst_nj <= 0) return -1;
+  const bool s0 = F.isx ? Q.solid(F.b - 1, F.a) : Q.solid(F.b, F.a - 1);
+  const bool s1 = Q.solid(F.b, F.a);
+  return s0 == s1 ? -1 : (s0 ? 0 : 1);
+}
+
+// the image of a side across the interface, in the interface frame: the
+// normal momentum (component 1) and the odd orders in the normal
+// coordinate (p_n, p_ns) negated
+__device__ __forceinline__ void mirror_side(double (&Wc)[4], double (&pc)[4][5]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double sg = v == 1 ? -1.0 : 1.0;
+    Wc[v] *= sg;
+    pc[v][0] *= -sg;
+    pc[v][1] *= sg;
+    pc[v][2] *= sg;
+    pc[v][3] *= sg;
+    pc[v][4] *= -sg;
+  }
+}
+
 // LDS bytes per thread of k_iface_2d: the frame record of g0 and the
 // accumulated flux and point values (interface frame)
 template <typename TC>
@@ -906,6 +936,7 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
   if (inside_step(Q, F)) return;
+  const int ws = wall_side(Q, F);
   const unsigned nb = blockDim.x, me = threadIdx.x;
   const Rec<TC> R{(double*)lds, (TC*)(lds + (size_t)ND_REC * 8 * nb), nb};
   double* acc = (double*)(lds + (size_t)(ND_REC * 8 + nt_rec<TC>() * sizeof(TC)) * nb);  // [12][nb]
@@ -932,6 +963,21 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
 #pragma unroll
           for (int v = 0; v < 4; ++v) Ueq[m][n][loc(false, v)] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
     }
+    // a wall of the step: the solid side and its stencil row are the gas
+    // side's image (constant indices only: the arrays stay in registers)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (ws == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Wc[s][v] = Wc[1 - s][v];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) pc[s][v][m] = pc[1 - s][v][m];
+#pragma unroll
+          for (int n = 0; n < 3; ++n) Ueq[s][n][v] = (v == 1 ? -1.0 : 1.0) * Ueq[1 - s][n][v];
+        }
+        mirror_side(Wc[s], pc[s]);
+      }
     if (!(dt > 0.0)) return;  // an empty step (end time reached, or after a nonphysical state)
     const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, me, flux, pv);
     if (!ok) {
@@ -970,7 +1016,8 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     section_boundary();
     const bool valid = R.D(D_RHO0, me) > 0.0;
     double Wc[4], pc[4][5];
-    load_face_cell(g, F, side, Wc, pc);
+    load_face_cell(g, F, side == ws ? 1 - side : side, Wc, pc);
+    if (side == ws) mirror_side(Wc, pc);
     double flux[4], pvm[4], pvp[4], E[4];
     iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, me, flux, pvm, pvp, E);
     if (valid) {

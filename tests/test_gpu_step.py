@@ -98,6 +98,11 @@ def test_step_faces_are_slip_walls_on_the_gpu(G, oracle, face):
     A = W.Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=nx * h, y0=0.0, y1=ny * h, gamma=1.4, tau_eps=0.05,
                   cfl=0.2, recon_vars=1, bc=list(out), obstacle=(i0, nj))
     sA = W.smooth_periodic_2d(nx=nx, ny=ny, seed=5 if face == "top" else 6, amp=0.1)[1]
+    # point values consistent with the wall (no normal momentum on it)
+    if face == "top":
+        sA.fy[:, 2, nj, i0:] = 0.0
+    else:
+        sA.fx[:, 1, :nj, i0] = 0.0
     if face == "top":
         B = replace(A, nx=nx - i0, ny=ny - nj, x0=i0 * h, y0=nj * h, obstacle=(0, 0),
                     bc=[W.BC("outflow"), W.BC("outflow"), W.BC("reflect"), W.BC("outflow")])
@@ -168,18 +173,14 @@ def test_step_in_a_mixed_handle(G, oracle):
             assert _rel(got.cell, r.cell, _masks(p)[0]) < tol, p.name
 
 
-@pytest.mark.parametrize("prec", ["fp64",
-                                  "fp32_mixed"])
-@pytest.mark.parametrize("shape", [(120, 40), (240, 80)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("shape", [(120, 40), (240, 80), (360, 120)])
 def test_forward_facing_step_at_the_paper_resolutions(G, oracle, shape, prec):
-    """Sec. 4.6 to t = 4.  (On the paper's finest 360 x 120 the expansion
-    round the corner empties the gas cell above it: a nonphysical state
-    there before t = 4.  The paper modifies the flow near the corner after an
-    external reference that the source does not give.  The FP32-mixed form
-    on 240 x 80 meets the same failure at the corner cell since its
-    cross-derivative ties are taken within single-precision rounding.)"""
-    if shape == (240, 80) and prec == "fp32_mixed":
-        pytest.xfail("FP32-mixed 240 x 80: nonphysical state at the step corner (no corner treatment)")
+    """Sec. 4.6 to t = 4 on the paper's three grids, both forms: every gas
+    cell physical, and one more step from the final state against the
+    oracle's.  (The step's faces take the face-wise mirror image of the gas
+    side; with the solid cells' own polynomials the corner passed mass and
+    the cell above it emptied on 240 x 80 and 360 x 120.)"""
     prob, st = W.forward_facing_step(*shape)
     nmax = int(3.0 * 4.0 / oracle.dt(prob, st)) + 50
     for prec in [prec]:
