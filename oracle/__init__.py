@@ -87,6 +87,8 @@ def lib():
         L.orc_last_fluxes.argtypes = [C.POINTER(orc_problem), _D, _D]
         L.orc_last_fallbacks.argtypes = []
         L.orc_last_fallbacks.restype = C.c_long
+        L.orc_take_capped.argtypes = []
+        L.orc_take_capped.restype = C.c_long
         _lib = L
     return _lib
 
@@ -277,6 +279,13 @@ def last_fallbacks():
     """Interior (gas) cells whose reconstruction fell back to the constant
     average in the last step (the admissibility reading)."""
     return int(lib().orc_last_fallbacks())
+
+
+def take_capped():
+    """Interface sides whose Chapman-Enskog correction was capped at cell
+    Knudsen number one (the Knudsen reading of eq. dis2) since the last
+    call; resets the count."""
+    return int(lib().orc_take_capped())
 
 
 def num_threads():

@@ -162,6 +162,9 @@ int orc_run(const orc_problem* P, double* cell, double* fx, double* fy, int nste
 /* Interior (gas) cells whose reconstruction fell back to the constant
  * average in the last orc_step */
 long orc_last_fallbacks(void);
+/* interface sides whose Chapman-Enskog correction was capped since the last
+ * call (and resets the count) */
+long orc_take_capped(void);
 
 /* Flux diagnostics of the last orc_step (x faces then y faces, [nvar][..]) */
 int orc_last_fluxes(const orc_problem* P, double* fxflux, double* fyflux);

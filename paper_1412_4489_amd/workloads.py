@@ -233,6 +233,21 @@ def sod_1d(n=100, t_end=0.2, recon_vars=1):
     return prob, State(cell.reshape(3, 1, n), fx.reshape(1, 3, 1, n + 1), np.zeros((2, 3, 2, n)))
 
 
+def viscous_shock_tube_1d(n=600, re=200.0, t_end=0.2, prandtl=0.73, recon_vars=1):
+    """The gas of the Sec. 4.7 viscous shock tube along the tube without its
+    walls: (rho, u, p) = (120, 0, 120/gamma) for x < 0.5 and (1.2, 0,
+    1.2/gamma) beyond on [0, 1], reflecting ends, gamma = 1.4, constant
+    mu = 1/Re, Pr 0.73.  On n cells the low-pressure side's cell Knudsen
+    number mu/p c / h is about n / (1.2 Re)."""
+    g = 1.4
+    prob = Problem(dim=1, nx=n, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=g, viscous=True,
+                   mu=1.0 / re, prandtl=prandtl, tau_eps=0.05, tau_c=1.0, cfl=0.2, t_end=t_end,
+                   recon_vars=recon_vars, bc=[BC("reflect"), BC("reflect"), BC(), BC()],
+                   admissibility=1, name=f"viscous_shock_tube_1d_{n}_re{int(re)}")
+    cell, fx = _piecewise_1d(n, 0.0, 1.0, [0.5], [(120.0, 0.0, 120.0 / g), (1.2, 0.0, 1.2 / g)], g)
+    return prob, State(cell.reshape(3, 1, n), fx.reshape(1, 3, 1, n + 1), np.zeros((2, 3, 2, n)))
+
+
 def blast_1d(n=400, t_end=3.8, recon_vars=1):
     """Sec. 4.2 Woodward-Colella blast wave on [0, 100], reflecting ends."""
     g = 1.4
