@@ -108,6 +108,21 @@ __device__ __forceinline__ void to_frame_1d(const double* b, double U, double* o
   o[2] = b[2] - U * o[1] - 0.5 * U * U * b[0];
 }
 
+// Knudsen reading of eq. dis2 (Navier-Stokes): the correction
+// -tau (a1 u + a2 v + A) g_k of a side's initial distribution is the
+// first-order Chapman-Enskog expansion, valid while the side's cell Knudsen
+// number tau s is below one, s the rate at which its equilibrium changes for
+// a particle at the sound speed c: the sum over the normal and tangential
+// derivatives of c |d rho| / rho + |d u| + |d v| + |d (rho e)| / (rho c).
+// Where tau s exceeds one the correction takes tau capped at 1 / s (the
+// relaxation keeps tau); in resolved flow it is the printed bracket.
+// rate_term: one direction's share from the frame derivatives f of
+// to_frame (f0 = d rho / rho, f1, f2 = d u, d v, f3 = d (rho e) / rho).
+__device__ __forceinline__ double rate_term(double c, double f0, double fu, double fv, double fe) {
+  return c * fabs(f0) + fabs(fu) + fabs(fv) + fabs(fe) / c;
+}
+__device__ __forceinline__ double bracket_tau(double tau, double s) { return tau * s > 1.0 ? 1.0 / s : tau; }
+
 // moment target of a derivative vector d (conservative variables) for the
 // Maxwellian of density rho = 1/ir moving with (U, V), in its frame
 template <typename T>
@@ -587,6 +602,19 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
 #pragma unroll
   for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
   const TC us = (TC)U, vs = (TC)V;
+  // the side's rate of change for the Knudsen reading (before pc is released)
+  double rate = 0.0;
+  if (P.viscous) {
+    const double ir = 1.0 / rho, xn = s == 0 ? 0.5 * hn : -0.5 * hn, cs = sqrt(P.gamma * S.pr * ir);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double d[4], fr[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) d[v] = (k == 0 ? pc[v][0] + pc[v][2] * xn : pc[v][1] + pc[v][4] * xn) * ir;
+      to_frame_2d(d, U, V, fr);
+      rate += rate_term(cs, fr[0], fr[1], fr[2], fr[3]);
+    }
+  }
   Coefs<TC> c;
   {
     TC b[5][4];
@@ -603,8 +631,9 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
     const double tau = R.D(D_TAU, f);
     TimeWeights tw;
     time_weights(tau, dt, tw);
+    const double tb = P.viscous ? bracket_tau(tau, rate) : tau;  // collision time of the Chapman-Enskog correction
     double kw[12];
-    kinetic_weights(tw, tau, P.viscous ? tau : 0.0, hs, kw);  // Euler: f_G = g_k
+    kinetic_weights(tw, tb, P.viscous ? tb : 0.0, hs, kw);  // Euler: f_G = g_k
 #pragma unroll
     for (int k = 0; k < 12; ++k) w[k] = (TC)kw[k];
   }
@@ -1094,6 +1123,15 @@ __device__ __forceinline__ bool iface_1d(const Phys& P, double dt, double h, con
     const double ir = 1.0 / rho[s];
     frame_rhs_1d(Dn[s], ir, U[s], bx);
     frame_rhs_1d(Dnn[s], ir, U[s], bxx);
+    double tb = tau;  // collision time of the Chapman-Enskog correction (Knudsen reading)
+    if (P.viscous) {
+      double d[3], fr[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) d[v] = Dn[s][v] * ir;
+      to_frame_1d(d, U[s], fr);
+      tb = bracket_tau(tau, rate_term(sqrt(P.gamma * pr[s] * ir), fr[0], fr[1], 0.0, fr[2]));
+    }
+    const double tvb = P.viscous ? tb : 0.0;
     TC ax[3], ay[3] = {0, 0, 0}, At[3] = {0, 0, 0}, dxx[3], dxy[3] = {0, 0, 0}, dyy[3] = {0, 0, 0},
                                  bxt[3] = {0, 0, 0}, byt[3] = {0, 0, 0}, Bt[3] = {0, 0, 0};
     const TC us = (TC)U[s];
@@ -1115,16 +1153,16 @@ __device__ __forceinline__ bool iface_1d(const Phys& P, double dt, double h, con
     };
     // C8 g a1 u  [and -tau C7 g a1 u]
     mom_half_conv_1d<TC>(th, kp, ht, us, TC(0), ax, ay, m0, m1);
-    acc(w.I[8] - tv * w.I[7], w.C[8] - tv * w.C[7]);
+    acc(w.I[8] - tvb * w.I[7], w.C[8] - tvb * w.C[7]);
     // 1/2 C7 t^2 g (a1^2 + d11) u^2  [and -tau C8 g (a1^2 + d11) u^2]
     mom_half_quad_1d<TC>(th, kp, ht, us, TC(0), ax, ay, dxx, dxy, dyy, m0, m1);
-    acc(0.5 * w.I[10] - tv * w.I[8], 0.5 * w.C[10] - tv * w.C[8]);
+    acc(0.5 * w.I[10] - tvb * w.I[8], 0.5 * w.C[10] - tvb * w.C[8]);
     if (P.viscous) {
       // -tau C7 g A, -tau C8 g (A a1 + b1) u
       mom_half_A_1d<TC>(th, kp, ht, us, TC(0), At, m0, m1);
-      acc(-tau * w.I[7], -tau * w.C[7]);
+      acc(-tb * w.I[7], -tb * w.C[7]);
       mom_half_tlin_1d<TC>(th, kp, ht, us, TC(0), ax, ay, At, bxt, byt, m0, m1);
-      acc(-tau * w.I[8], -tau * w.C[8]);
+      acc(-tb * w.I[8], -tb * w.C[8]);
     }
     add(AF, BF, V0, U[s], rho[s]);
   }
