@@ -271,7 +271,8 @@ enum RecD {  // double fields
   D_RHO0, D_U0, D_V0, D_LAM0,
   D_TAU,                    // collision time (the sections rebuild the time weights)
   D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
-  ND_REC = D_E3 + 1
+  D_RATE0, D_RATE1,        // each side's rate s (Knudsen reading; Navier-Stokes only; kinetic sections)
+  ND_REC = D_RATE1 + 1
 };
 enum RecT {  // compute-type fields
   T_CG = 0  // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar frame; in double
@@ -384,9 +385,6 @@ __device__ __forceinline__ bool side_state_2d(const Phys& P, int s, double hn, d
   return o.rho > 0.0 && o.pr > 0.0;
 }
 
-// targets of side s's coefficient systems (dU/dn, dU/ds, d2U/dn2, d2U/dnds,
-// d2U/ds2 of the cell polynomial at the interface, divided by rho, in the
-// frame of the side's Maxwellian)
 template <typename TC>
 __device__ __forceinline__ void side_targets_2d(int s, double hn, const Side& S, const double (&pc)[4][5],
                                                 TC (&b)[5][4]) {
@@ -602,23 +600,16 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
 #pragma unroll
   for (int e = 0; e < 4; ++e) kp[e] = (TC)P.kp[e];
   const TC us = (TC)U, vs = (TC)V;
-  // the side's rate of change for the Knudsen reading (before pc is released)
-  double rate = 0.0;
-  if (P.viscous) {
-    const double ir = 1.0 / rho, xn = s == 0 ? 0.5 * hn : -0.5 * hn, cs = sqrt(P.gamma * S.pr * ir);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      double d[4], fr[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) d[v] = (k == 0 ? pc[v][0] + pc[v][2] * xn : pc[v][1] + pc[v][4] * xn) * ir;
-      to_frame_2d(d, U, V, fr);
-      rate += rate_term(cs, fr[0], fr[1], fr[2], fr[3]);
-    }
-  }
   Coefs<TC> c;
   {
     TC b[5][4];
     side_targets_2d(s, hn, S, pc, b);
+    // the side's rate for the Knudsen reading from its first derivatives
+    if (P.viscous) {
+      const double cs = sqrt(P.gamma * S.pr / S.rho);
+      R.D(D_RATE0 + s, f) = rate_term(cs, b[0][0], b[0][1], b[0][2], b[0][3]) +
+                            rate_term(cs, b[1][0], b[1][1], b[1][2], b[1][3]);
+    }
     if (P.viscous)
       coef_side_ns_2d<TC>(th, kp, (TC)P.nth, us, vs, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy,
                           c.dyy, c.bxt, c.byt, c.Bt);
@@ -631,7 +622,8 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
     const double tau = R.D(D_TAU, f);
     TimeWeights tw;
     time_weights(tau, dt, tw);
-    const double tb = P.viscous ? bracket_tau(tau, rate) : tau;  // collision time of the Chapman-Enskog correction
+    // collision time of the Chapman-Enskog correction
+    const double tb = P.viscous ? bracket_tau(tau, R.D(D_RATE0 + s, f)) : tau;
     double kw[12];
     kinetic_weights(tw, tb, P.viscous ? tb : 0.0, hs, kw);  // Euler: f_G = g_k
 #pragma unroll

@@ -33,8 +33,9 @@ import re
 
 COPY_BYTES = 256 << 20  # the calibration copies of bench.py --pmc-probe
 IFACE = "k_iface_2d"
+IFACE_NAMES = ("k_iface_2d", "k_iface_2d_loop")  # one block per tile; persistent form
 CUS, CLOCK_MHZ = 256, 2400  # MI355X compute units and clock (VALUBusy below)
-BATCH_MIN_GRID = 400000  # interface launches of the 96-grid batch are larger than this
+PROBE_STEPS = 3  # the tuned-shape steps that end bench.py --pmc-probe
 BATCH_CELLS = 4130816
 BATCH_ALG_BYTES = BATCH_CELLS * 192  # state read once and written once per step, FP32-mixed
 KERNEL_SOURCES = ("gks.hip", "gks_device.h", "interface_gen.h")
@@ -86,7 +87,11 @@ def _counter_rows(path):
 
 
 def _batch_iface_rows(rows, ttype="float"):
-    return [r for r in rows if _short(r["Kernel_Name"]) == (IFACE, ttype) and int(r["Grid_Size"]) >= BATCH_MIN_GRID]
+    """counter rows of the interface launches of the probe's last steps (the
+    tuned launch shape; the tuner's trial launches come before them)"""
+    rows = [(n, r) for n, r in enumerate(rows) if _short(r["Kernel_Name"]) in [(k, ttype) for k in IFACE_NAMES]]
+    ids = sorted({int(r.get("Dispatch_Id", n)) for n, r in rows})[-PROBE_STEPS:]
+    return [r for n, r in rows if int(r.get("Dispatch_Id", n)) in ids]
 
 
 def traffic(fetch_csv, write_csv):
@@ -145,29 +150,39 @@ def _averages(agg):
     return {t: {k: sum(v) / len(v) for k, v in d.items()} for t, d in per.items()}
 
 
-def _step_line(d):
-    tot = d[IFACE] + d["k_recon_2d"] + d["k_update_2d"] + d["k_ghost_2d"]
-    return (f"interface {d[IFACE]:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
+def _step_line(d, iface):
+    tot = iface + d["k_recon_2d"] + d["k_update_2d"] + d["k_ghost_2d"]
+    return (f"interface {iface:.1f} us; reconstruction {d['k_recon_2d']:.1f}, update "
             f"{d['k_update_2d']:.1f}, boundary (+ time step) {d['k_ghost_2d']:.1f}; sum {tot:.1f} us")
 
 
+def headline_iface(agg, ttype="float"):
+    """(kernel, type, grid) and durations of the interface launches of the
+    tuned shape: the group with the most calls (the timed steps; the tuner's
+    trial shapes have a few each)"""
+    groups = [(key, v) for key, v in agg.items() if key[0] in IFACE_NAMES and key[1] == ttype]
+    return max(groups, key=lambda kv: len(kv[1])) if groups else (None, [])
+
+
 def batch_iface_duration(trace_csv, ttype="float"):
-    """average duration (us) of the interface kernel's batch launches"""
-    v = [x for (k, t, g), d in kernel_table(trace_csv).items() if k == IFACE and t == ttype and g >= BATCH_MIN_GRID
-         for x in d]
+    """average duration (us) of the interface kernel's launches in the tuned shape"""
+    _, v = headline_iface(kernel_table(trace_csv), ttype)
     return sum(v) / len(v) if v else None
 
 
 def write_kernel_summaries(trace_csv, out):
-    agg = {k: v for k, v in kernel_table(trace_csv).items() if k[0] != IFACE or k[2] >= BATCH_MIN_GRID}
-    avg = _averages(agg)
+    agg = kernel_table(trace_csv)
+    avg = _averages({k: v for k, v in agg.items() if k[0] not in IFACE_NAMES})
     md = kernel_markdown(agg, f"Kernel trace: 96-grid batch ({BATCH_CELLS} cells), GKS_FP32_MIXED and GKS_FP64",
                          TRACE_CMD)
     md += "\nPer step (averages over the launch sizes of a kernel; each launch covers all 96 grids):\n\n"
     for t, name in (("float", "FP32-mixed"), ("double", "FP64")):
-        if t in avg and IFACE in avg[t]:
-            md += f"* {name}: {_step_line(avg[t])}\n"
-    md += ("\nThe tuner's timing steps (64, 128, 256 threads per block) add launches of other sizes to the "
+        key, v = headline_iface(agg, t)
+        if t in avg and v:
+            md += (f"* {name} (interface launch {key[0]}, {key[2]} threads): "
+                   f"{_step_line(avg[t], sum(v) / len(v))}\n")
+    md += ("\nThe tuned shape of the interface launch is the row with the most calls; the tuner's timing steps "
+           "(64, 128, 256 threads per block, and the persistent form) add launches of other sizes, also to the "
            "smaller kernels' rows.\n")
     with open(os.path.join(out, "kernels_batch96.md"), "w") as fh:
         fh.write(md)
@@ -191,7 +206,7 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
     with open(os.path.join(out, "traffic_iface_batch96_fp32mixed.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
-    t = ["# Counters: interface kernel k_iface_2d, 96-grid batch, GKS_FP32_MIXED", "",
+    t = ["# Counters: interface kernel (tuned launch shape), 96-grid batch, GKS_FP32_MIXED", "",
          "Commands (on the machine with the GPU, from /tmp with TMPDIR=/tmp, repository root R, output directory O), "
          "one counter pass per run:", ""]
     t += [f"    timeout -s KILL 120 rocprofv3 --pmc {c} -d $O/{d} -o {o} --output-format csv "
