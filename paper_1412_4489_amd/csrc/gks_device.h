@@ -607,8 +607,8 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
     // the side's rate for the Knudsen reading from its first derivatives
     if (P.viscous) {
       const double cs = sqrt(P.gamma * S.pr / S.rho);
-      R.D(D_RATE0 + s, f) = rate_term(cs, b[0][0], b[0][1], b[0][2], b[0][3]) +
-                            rate_term(cs, b[1][0], b[1][1], b[1][2], b[1][3]);
+      R.D(D_RATE0 + s, f) = rate_term(cs, (double)b[0][0], (double)b[0][1], (double)b[0][2], (double)b[0][3]) +
+                            rate_term(cs, (double)b[1][0], (double)b[1][1], (double)b[1][2], (double)b[1][3]);
     }
     if (P.viscous)
       coef_side_ns_2d<TC>(th, kp, (TC)P.nth, us, vs, b[0], b[1], b[2], b[3], b[4], c.ax, c.ay, c.At, c.dxx, c.dxy,
