@@ -42,12 +42,14 @@ class orc_problem(C.Structure):
         ("exact_c", C.c_int), ("bc_kind", C.c_int * 4), ("bc_state", (C.c_double * 4) * 4),
         ("bc_alt", (C.c_double * 4) * 4), ("bc_wall", (C.c_double * 3) * 4),
         ("obst_i0", C.c_int), ("obst_nj", C.c_int), ("admissibility", C.c_int),
+        ("mesh", C.POINTER(C.c_double)), ("bc_omega", C.c_double * 4),
     ]
 
 
 class orc_face_input(C.Structure):
     _fields_ = [(n, (C.c_double * 4) * 2) for n in ("W", "Wn", "Ws", "Wnn", "Wns", "Wss")] + [
-        ("Ueq", ((C.c_double * 4) * 3) * 2), ("dn", C.c_double), ("ds", C.c_double)]
+        ("Ueq", ((C.c_double * 4) * 3) * 2), ("dn", C.c_double), ("ds", C.c_double),
+        ("curv", C.c_int), ("G", C.c_double * 3)]
 
 
 class orc_face_output(C.Structure):
@@ -119,8 +121,15 @@ def make_problem(prob, exact_c=False) -> orc_problem:
             P.bc_alt[s][i] = bc.alt[i]
         for i in range(3):
             P.bc_wall[s][i] = bc.wall[i]
+        P.bc_omega[s] = getattr(bc, "omega", 0.0)
     P.obst_i0, P.obst_nj = prob.obstacle
     P.admissibility = prob.admissibility
+    mesh = getattr(prob, "mesh", None)
+    if mesh is not None:
+        m = np.ascontiguousarray(mesh, dtype=np.float64)
+        assert m.shape == (prob.ny + 1, prob.nx + 1, 2), m.shape
+        P._mesh_keep = m  # the C side reads it during the call
+        P.mesh = _p(m)
     return P
 
 
@@ -179,6 +188,9 @@ def face(prob, inputs: dict, dt, exact_c=False):
         for n in range(3):
             fi.Ueq[m][n][:] = list(U[m, n])
     fi.dn, fi.ds = inputs["dn"], inputs.get("ds", 1.0)
+    if "G" in inputs:  # an interface of a curvilinear grid: metric (G_nn, G_ns, G_ss)
+        fi.curv = 1
+        fi.G[:] = list(inputs["G"])
     fo = orc_face_output()
     P = make_problem(prob, exact_c)
     rc = lib().orc_face(C.byref(P), C.byref(fi), dt, C.byref(fo))

@@ -684,7 +684,30 @@ int orc_face(const orc_problem* P, const orc_face_input* in, double dt, orc_face
   for (int i = 0; i < nv; ++i) out->W0[i] = hl.rho * ml[i] + hr.rho * mr[i];
 
   /* Sec. 3.3: equilibrium quadratic from the six cell averages and U0 */
-  orc_equilibrium_poly(dim, &in->Ueq[0][0][0], out->W0, in->dn, in->ds, &out->q[0][0]);
+  if (in->curv) {
+    /* logical coordinates (unit spacing), then the interface frame through
+     * the metric (curvilinear grids) */
+    double ql[5][4];
+    orc_equilibrium_poly(dim, &in->Ueq[0][0][0], out->W0, 1.0, 1.0, &ql[0][0]);
+    double G[2][2] = {{in->G[0], in->G[1]}, {0.0, in->G[2]}};
+    for (int v = 0; v < nv; ++v) {
+      double grad[2] = {ql[0][v], ql[1][v]}, hess[2][2] = {{ql[2][v], ql[4][v]}, {ql[4][v], ql[3][v]}};
+      double hf[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          hf[a][b] = 0.0;
+          for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 2; ++e) hf[a][b] += G[a][c] * hess[c][e] * G[b][e];
+        }
+      out->q[0][v] = G[0][0] * grad[0] + G[0][1] * grad[1];
+      out->q[1][v] = G[1][0] * grad[0] + G[1][1] * grad[1];
+      out->q[2][v] = hf[0][0];
+      out->q[3][v] = hf[1][1];
+      out->q[4][v] = hf[0][1];
+    }
+  } else {
+    orc_equilibrium_poly(dim, &in->Ueq[0][0][0], out->W0, in->dn, in->ds, &out->q[0][0]);
+  }
 
   /* Sec. 4: collision time (reading: p_l, p_r of the two interface values,
    * p of U0) */
@@ -1126,8 +1149,37 @@ static void prim_to_cons(int dim, double gamma, const double* q, double* W) {
   }
 }
 
-/* image of a mirrored state across a boundary whose normal is `axis` */
-static void mirror_state(const orc_problem* P, int side, int kind, const double* Ws, double* Wg) {
+/* point of boundary `side` of a curvilinear grid at logical coordinate s
+ * along it (s = i or j of the vertices; linear along the straight edges,
+ * extended linearly beyond the end vertices) */
+static void wall_point(const orc_problem* P, int side, double s, double* x, double* y) {
+  int along_j = side < 2, n = along_j ? P->ny : P->nx;
+  int e = (int)floor(s);
+  if (e < 0) e = 0;
+  if (e > n - 1) e = n - 1;
+  double f = s - e;
+  int fix = side == 0 ? 0 : side == 1 ? P->nx : side == 2 ? 0 : P->ny;
+  for (int c = 0; c < 2; ++c) {
+    double a, b;
+    if (along_j) {
+      a = P->mesh[((size_t)e * (P->nx + 1) + fix) * 2 + c];
+      b = P->mesh[((size_t)(e + 1) * (P->nx + 1) + fix) * 2 + c];
+    } else {
+      a = P->mesh[((size_t)fix * (P->nx + 1) + e) * 2 + c];
+      b = P->mesh[((size_t)fix * (P->nx + 1) + e + 1) * 2 + c];
+    }
+    double v = a + f * (b - a);
+    if (c == 0)
+      *x = v;
+    else
+      *y = v;
+  }
+}
+
+/* image of a mirrored state across a boundary whose normal is `axis`; s:
+ * logical position along the boundary (curvilinear grids with a turning
+ * wall: the wall velocity there) */
+static void mirror_state(const orc_problem* P, int side, int kind, const double* Ws, double* Wg, double s) {
   int dim = P->dim, nv = dim + 2, axis = side / 2;
   double gamma = P->gamma;
   for (int i = 0; i < nv; ++i) Wg[i] = Ws[i];
@@ -1140,6 +1192,12 @@ static void mirror_state(const orc_problem* P, int side, int kind, const double*
     double rho = Ws[0], u = Ws[1] / rho, v = dim == 2 ? Ws[2] / rho : 0.0;
     double p = pressure(dim, gamma, Ws), T = p / rho;
     double uw = P->bc_wall[side][0], vw = P->bc_wall[side][1], Tw = P->bc_wall[side][2];
+    if (P->mesh && P->bc_omega[side] != 0.0) {
+      double xw, yw;
+      wall_point(P, side, s, &xw, &yw);
+      uw -= P->bc_omega[side] * yw;
+      vw += P->bc_omega[side] * xw;
+    }
     double Tg = kind == ORC_BC_NOSLIP_ISO ? 2.0 * Tw - T : T;
     double q[4] = {rho, 2.0 * uw - u, 2.0 * vw - v, rho * Tg};
     prim_to_cons(dim, gamma, q, Wg);
@@ -1210,7 +1268,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, j + 0.5);
         }
         set_cell(G, j, ig, Wg);
       }
@@ -1224,7 +1282,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, j + 0.5 + (g == 0 ? -dl : dl));
         }
         for (int v = 0; v < nv; ++v) GFX(G, g, v, j, fg) = Wg[v];
       }
@@ -1241,7 +1299,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, (double)fj);
         }
         for (int v = 0; v < nv; ++v) GFY(G, g, v, fj, ig) = Wg[v];
       }
@@ -1260,7 +1318,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, i + 0.5);
         }
         set_cell(G, jg, i, Wg);
       }
@@ -1276,7 +1334,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, i + 0.5 + (g == 0 ? -dl : dl));
         }
         for (int v = 0; v < nv; ++v) GFY(G, g, v, fg, i) = Wg[v];
       }
@@ -1292,7 +1350,7 @@ static void fill_ghosts_2d(const orc_problem* P, grid2* G, double t) {
           if (kind == ORC_BC_PERIODIC)
             memcpy(Wg, Ws, sizeof(Ws));
           else
-            mirror_state(P, side, kind, Ws, Wg);
+            mirror_state(P, side, kind, Ws, Wg, (double)fi);
         }
         for (int v = 0; v < nv; ++v) GFX(G, g, v, jg, fi) = Wg[v];
       }
@@ -1328,7 +1386,7 @@ static void range_add(int dim, double gamma, const double* W, double* lo, double
 
 /* reconstruction of cell (i, j), all components, with the admissibility
  * reading above; returns 1 when the cell fell back to its average */
-static int recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k) {
+static int recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h, double k, double Cw) {
   double S[13][4], pc[4][5];
   for (int v = 0; v < G->nv; ++v) {
     S[0][v] = GW(G, v, j, i);
@@ -1347,7 +1405,7 @@ static int recon_cell_2d(const orc_problem* P, grid2* G, int j, int i, double h,
   }
   /* a nonphysical average (characteristic variables) leaves p = 0; the
    * interfaces of the cell report it */
-  (void)orc_recon2d_cell(P->recon_vars, P->gamma, &S[0][0], h, k, P->weno_eps, P->weno_c, &pc[0][0]);
+  (void)orc_recon2d_cell(P->recon_vars, P->gamma, &S[0][0], h, k, P->weno_eps, Cw, &pc[0][0]);
   /* range of the averages of the cell and its four face neighbours */
   double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
   const int nb[5][2] = {{0, 0}, {0, 1}, {0, -1}, {1, 0}, {-1, 0}};
@@ -1471,14 +1529,14 @@ static void fill_obstacle_2d(const orc_problem* P, grid2* G) {
     for (int m = 0; m < 2; ++m) {
       get_cell(G, m, i0 - 1 - dx, Ws);
       flip(Ws, 1, 0, Wm);
-      mirror_state(P, 2, P->bc_kind[2], Wm, Wg);
+      mirror_state(P, 2, P->bc_kind[2], Wm, Wg, 0.0);
       set_cell(G, -1 - m, i0 + dx, Wg);
     }
   for (int m = 0; m < 2; ++m)
     for (int dy = 0; dy < 2; ++dy) {
       get_cell(G, nj + dy, nx - 1 - m, Ws);
       flip(Ws, 0, 1, Wm);
-      mirror_state(P, 1, P->bc_kind[1], Wm, Wg);
+      mirror_state(P, 1, P->bc_kind[1], Wm, Wg, 0.0);
       set_cell(G, nj - 1 - dy, nx + m, Wg);
     }
   /* x interfaces: fi = i0+1..nx in the two rows below the top face, fi =
@@ -1512,7 +1570,318 @@ static void fill_obstacle_2d(const orc_problem* P, grid2* G) {
 }
 
 /* interior cells whose reconstruction fell back to the average in the last step */
+/* ---- 2D curvilinear grids ----------------------------------------------
+ * Reading (the remark closing Sec. 3.3 calls the compact reconstruction easy
+ * to extend to other meshes and gives no formulas; Sec. 4.8 runs a polar
+ * cavity).  Cells are the straight-edged quadrilaterals of the vertex grid.
+ *   - Reconstruction: Sec. 3.2 verbatim in the logical coordinates (xi, eta)
+ *     of the grid (unit spacing), from the cell averages and the interface
+ *     Gauss-point values; the weight constant I(U1) = C |K| takes the cell's
+ *     area, so that both indicators keep their physical scale.
+ *   - Interface: straight edge of length L, unit tangent t along the edge
+ *     (towards increasing eta on xi-interfaces, increasing xi on
+ *     eta-interfaces), unit normal n from side 0 to side 1; Gauss points at
+ *     the centre +- (sqrt(3)/6) L t.  Logical derivatives become interface
+ *     derivatives through the metric at the interface centre: the logical
+ *     normal step is the vector e between the two cell centres (the mean of
+ *     each cell's corners; across a wall, the mirror image of the inside
+ *     centre; across a periodic seam, the partner translated by the period),
+ *     the logical tangential step is the edge L t, so
+ *       d/dxi = (e.n) d/dn + (e.t) d/dt,  d/deta = L d/dt,
+ *     whose inverse G gives first and (second-order terms of the map
+ *     dropped) second derivatives.  Momentum is rotated to (n, t).
+ *   - Flux and point values: Sec. 2.2 in that frame with the interface
+ *     extent L; update eq. finite with the cell areas.
+ *   - Time step: Sec. 4's CFL condition with the widths |K| / (mean length
+ *     of the two opposite edges) across each logical direction and the
+ *     speed |u|.
+ * The map's own curvature is not carried into the second derivatives, so
+ * the scheme is third order on affine grids (constant metric) and of lower
+ * order where the grid curves. */
+typedef struct {
+  double *cx, *cy, *area, *h1, *h2; /* [ny][nx] */
+  double *fx, *fy;                  /* x faces [ny][nx+1][7], y faces [ny+1][nx][7]: n, t, L, G_nn, G_ns */
+} cgeom;
+
+#define MV(P, j, i, c) (P)->mesh[((size_t)(j) * ((P)->nx + 1) + (size_t)(i)) * 2 + (c)]
+
+static void cgeom_free(cgeom* g) {
+  free(g->cx);
+  free(g->cy);
+  free(g->area);
+  free(g->h1);
+  free(g->h2);
+  free(g->fx);
+  free(g->fy);
+}
+
+/* centre of the cell on side `side` of a boundary face beyond the grid:
+ * the periodic partner translated by the period, or the mirror image of the
+ * inside centre (ix, iy) across the face line through (px, py) with normal n */
+static void ghost_centre(const orc_problem* P, const cgeom* g, int axis, int high, int part_i, int part_j, double ix,
+                         double iy, double px, double py, const double* n, double* ox, double* oy) {
+  int nx = P->nx, ny = P->ny;
+  if (P->bc_kind[axis * 2 + high] == ORC_BC_PERIODIC) {
+    double sx = axis == 0 ? MV(P, 0, nx, 0) - MV(P, 0, 0, 0) : MV(P, ny, 0, 0) - MV(P, 0, 0, 0);
+    double sy = axis == 0 ? MV(P, 0, nx, 1) - MV(P, 0, 0, 1) : MV(P, ny, 0, 1) - MV(P, 0, 0, 1);
+    double sg = high ? 1.0 : -1.0;
+    *ox = g->cx[(size_t)part_j * nx + part_i] + sg * sx;
+    *oy = g->cy[(size_t)part_j * nx + part_i] + sg * sy;
+  } else {
+    double d = (ix - px) * n[0] + (iy - py) * n[1];
+    *ox = ix - 2.0 * d * n[0];
+    *oy = iy - 2.0 * d * n[1];
+  }
+}
+
+/* frame and metric of one face from its edge (a -> b) and the centres of
+ * its side cells (c0 -> c1); xface: n is t turned clockwise, else
+ * anticlockwise */
+static void face_frame(double ax, double ay, double bx, double by, int xface, double* fr) {
+  double ex = bx - ax, ey = by - ay, L = sqrt(ex * ex + ey * ey);
+  double tx = ex / L, ty = ey / L;
+  fr[0] = xface ? ty : -ty;
+  fr[1] = xface ? -tx : tx;
+  fr[2] = tx;
+  fr[3] = ty;
+  fr[4] = L;
+}
+
+static void face_metric(double* fr, double c0x, double c0y, double c1x, double c1y) {
+  /* Jacobian of (xi, eta) -> (n, t) coordinates: rows d/dxi, d/deta */
+  double ex = c1x - c0x, ey = c1y - c0y, L = fr[4];
+  double J[2][2] = {{ex * fr[0] + ey * fr[1], ex * fr[2] + ey * fr[3]}, {0.0, L}};
+  double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  /* (d/dn, d/dt) = J^-1 (d/dxi, d/deta) */
+  fr[5] = J[1][1] / det;
+  fr[6] = -J[0][1] / det;
+}
+
+static void cgeom_build(const orc_problem* P, cgeom* g) {
+  int nx = P->nx, ny = P->ny;
+  size_t nc = (size_t)nx * ny;
+  g->cx = malloc(nc * sizeof(double));
+  g->cy = malloc(nc * sizeof(double));
+  g->area = malloc(nc * sizeof(double));
+  g->h1 = malloc(nc * sizeof(double));
+  g->h2 = malloc(nc * sizeof(double));
+  g->fx = malloc((size_t)ny * (nx + 1) * 7 * sizeof(double));
+  g->fy = malloc((size_t)(ny + 1) * nx * 7 * sizeof(double));
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double x[4] = {MV(P, j, i, 0), MV(P, j, i + 1, 0), MV(P, j + 1, i + 1, 0), MV(P, j + 1, i, 0)};
+      double y[4] = {MV(P, j, i, 1), MV(P, j, i + 1, 1), MV(P, j + 1, i + 1, 1), MV(P, j + 1, i, 1)};
+      size_t c = (size_t)j * nx + i;
+      g->cx[c] = 0.25 * (x[0] + x[1] + x[2] + x[3]);
+      g->cy[c] = 0.25 * (y[0] + y[1] + y[2] + y[3]);
+      /* half the cross product of the diagonals */
+      g->area[c] = 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (y[2] - y[0]) * (x[3] - x[1]));
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int fi = 0; fi <= nx; ++fi) {
+      double* fr = g->fx + ((size_t)j * (nx + 1) + fi) * 7;
+      face_frame(MV(P, j, fi, 0), MV(P, j, fi, 1), MV(P, j + 1, fi, 0), MV(P, j + 1, fi, 1), 1, fr);
+      double px = 0.5 * (MV(P, j, fi, 0) + MV(P, j + 1, fi, 0)), py = 0.5 * (MV(P, j, fi, 1) + MV(P, j + 1, fi, 1));
+      double c0x, c0y, c1x, c1y;
+      if (fi > 0) {
+        c0x = g->cx[(size_t)j * nx + fi - 1];
+        c0y = g->cy[(size_t)j * nx + fi - 1];
+      } else {
+        ghost_centre(P, g, 0, 0, nx - 1, j, g->cx[(size_t)j * nx], g->cy[(size_t)j * nx], px, py, fr, &c0x, &c0y);
+      }
+      if (fi < nx) {
+        c1x = g->cx[(size_t)j * nx + fi];
+        c1y = g->cy[(size_t)j * nx + fi];
+      } else {
+        ghost_centre(P, g, 0, 1, 0, j, g->cx[(size_t)j * nx + nx - 1], g->cy[(size_t)j * nx + nx - 1], px, py, fr,
+                     &c1x, &c1y);
+      }
+      face_metric(fr, c0x, c0y, c1x, c1y);
+    }
+  for (int fj = 0; fj <= ny; ++fj)
+    for (int i = 0; i < nx; ++i) {
+      double* fr = g->fy + ((size_t)fj * nx + i) * 7;
+      face_frame(MV(P, fj, i, 0), MV(P, fj, i, 1), MV(P, fj, i + 1, 0), MV(P, fj, i + 1, 1), 0, fr);
+      double px = 0.5 * (MV(P, fj, i, 0) + MV(P, fj, i + 1, 0)), py = 0.5 * (MV(P, fj, i, 1) + MV(P, fj, i + 1, 1));
+      double c0x, c0y, c1x, c1y;
+      if (fj > 0) {
+        c0x = g->cx[(size_t)(fj - 1) * nx + i];
+        c0y = g->cy[(size_t)(fj - 1) * nx + i];
+      } else {
+        ghost_centre(P, g, 1, 0, i, ny - 1, g->cx[i], g->cy[i], px, py, fr, &c0x, &c0y);
+      }
+      if (fj < ny) {
+        c1x = g->cx[(size_t)fj * nx + i];
+        c1y = g->cy[(size_t)fj * nx + i];
+      } else {
+        ghost_centre(P, g, 1, 1, i, 0, g->cx[(size_t)(ny - 1) * nx + i], g->cy[(size_t)(ny - 1) * nx + i], px, py, fr,
+                     &c1x, &c1y);
+      }
+      face_metric(fr, c0x, c0y, c1x, c1y);
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t c = (size_t)j * nx + i;
+      double lw = g->fx[((size_t)j * (nx + 1) + i) * 7 + 4], le = g->fx[((size_t)j * (nx + 1) + i + 1) * 7 + 4];
+      double ls = g->fy[((size_t)j * nx + i) * 7 + 4], ln = g->fy[((size_t)(j + 1) * nx + i) * 7 + 4];
+      g->h1[c] = g->area[c] / (0.5 * (lw + le));
+      g->h2[c] = g->area[c] / (0.5 * (ls + ln));
+    }
+}
+
+/* area of the cell (i, j) of the reconstruction range (-1..nx, -1..ny, no
+ * corners): a ghost cell takes its image's (periodic partner or mirrored
+ * inside cell) */
+static double cell_area(const orc_problem* P, const cgeom* g, int i, int j) {
+  int nx = P->nx, ny = P->ny;
+  if (i < 0) i = P->bc_kind[0] == ORC_BC_PERIODIC ? i + nx : -1 - i;
+  if (i >= nx) i = P->bc_kind[1] == ORC_BC_PERIODIC ? i - nx : 2 * nx - 1 - i;
+  if (j < 0) j = P->bc_kind[2] == ORC_BC_PERIODIC ? j + ny : -1 - j;
+  if (j >= ny) j = P->bc_kind[3] == ORC_BC_PERIODIC ? j - ny : 2 * ny - 1 - j;
+  return g->area[(size_t)j * nx + i];
+}
+
+/* interface-frame data of side s of a face with frame fr: the side cell's
+ * average Ub and logical polynomial p (p2..p6 of the cell), normal logical
+ * axis ax (0: xi, 1: eta), at the logical normal offset xn (+1/2 for side
+ * 0, -1/2 for side 1) */
+static void curv_side(orc_face_input* in, int s, const double* fr, int ax, double xn, const double* Ub,
+                      const double (*p)[5]) {
+  double val[4], d[5][4];
+  for (int v = 0; v < 4; ++v) {
+    double pn = ax == 0 ? p[v][0] : p[v][1], ps = ax == 0 ? p[v][1] : p[v][0];
+    double pnn = ax == 0 ? p[v][2] : p[v][3], pss = ax == 0 ? p[v][3] : p[v][2], pns = p[v][4];
+    /* the polynomial Ubar + pn x + ps y + pnn (x^2 - 1/12)/2 + pss (y^2 - 1/12)/2 + pns x y at (xn, 0) */
+    val[v] = Ub[v] + pn * xn + 0.5 * pnn * (xn * xn - 1.0 / 12.0) - pss / 24.0;
+    double grad[2] = {pn + pnn * xn, ps + pns * xn};
+    double hess[2][2] = {{pnn, pns}, {pns, pss}};
+    double G[2][2] = {{fr[5], fr[6]}, {0.0, 1.0 / fr[4]}};
+    double gf[2], hf[2][2];
+    for (int a = 0; a < 2; ++a) {
+      gf[a] = G[a][0] * grad[0] + G[a][1] * grad[1];
+      for (int b = 0; b < 2; ++b) {
+        hf[a][b] = 0.0;
+        for (int c = 0; c < 2; ++c)
+          for (int e = 0; e < 2; ++e) hf[a][b] += G[a][c] * hess[c][e] * G[b][e];
+      }
+    }
+    d[0][v] = gf[0];
+    d[1][v] = gf[1];
+    d[2][v] = hf[0][0];
+    d[3][v] = hf[0][1];
+    d[4][v] = hf[1][1];
+  }
+  /* momentum to (n, t) */
+  double* outs[6] = {in->W[s], in->Wn[s], in->Ws[s], in->Wnn[s], in->Wns[s], in->Wss[s]};
+  const double* srcs[6] = {val, d[0], d[1], d[2], d[3], d[4]};
+  for (int q = 0; q < 6; ++q) {
+    const double* a = srcs[q];
+    outs[q][0] = a[0];
+    outs[q][1] = fr[0] * a[1] + fr[1] * a[2];
+    outs[q][2] = fr[2] * a[1] + fr[3] * a[2];
+    outs[q][3] = a[3];
+  }
+}
+
+static void to_face_frame(const double* fr, const double* W, double* o) {
+  o[0] = W[0];
+  o[1] = fr[0] * W[1] + fr[1] * W[2];
+  o[2] = fr[2] * W[1] + fr[3] * W[2];
+  o[3] = W[3];
+}
+
+static void from_face_frame(const double* fr, const double* F, double* o) {
+  o[0] = F[0];
+  o[1] = fr[0] * F[1] + fr[2] * F[2];
+  o[2] = fr[1] * F[1] + fr[3] * F[2];
+  o[3] = F[3];
+}
+
 static long g_last_fallbacks = 0;
+/* every interface of a curvilinear grid (fluxes FLX / FLY and the new
+ * Gauss-point values in the grid's (x, y) components) */
+static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt, double* fx, double* fy, double* FLX,
+                      double* FLY) {
+  int nx = P->nx, ny = P->ny, nv = 4, status = 0;
+#pragma omp parallel for schedule(static) reduction(| : status)
+  for (int j = 0; j < ny; ++j)
+    for (int fi = 0; fi <= nx; ++fi) {
+      const double* fr = cg->fx + ((size_t)j * (nx + 1) + fi) * 7;
+      orc_face_input in;
+      memset(&in, 0, sizeof(in));
+      in.dn = 1.0;
+      in.ds = fr[4];
+      in.curv = 1;
+      in.G[0] = fr[5];
+      in.G[1] = fr[6];
+      in.G[2] = 1.0 / fr[4];
+      for (int s = 0; s < 2; ++s) {
+        int ic = fi - 1 + s;
+        double Ub[4], p[4][5];
+        for (int v = 0; v < nv; ++v) {
+          Ub[v] = GW(G, v, j, ic);
+          for (int m = 0; m < 5; ++m) p[v][m] = GPC(G, v, m, j, ic);
+        }
+        curv_side(&in, s, fr, 0, s == 0 ? 0.5 : -0.5, Ub, p);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int n = 0; n < 3; ++n) {
+          double W[4];
+          get_cell(G, j - 1 + n, fi - 1 + m, W);
+          to_face_frame(fr, W, in.Ueq[m][n]);
+        }
+      orc_face_output o;
+      if (orc_face(P, &in, dt, &o)) status |= 1;
+      double F[4], pg[2][4];
+      from_face_frame(fr, o.flux, F);
+      from_face_frame(fr, o.pv[0], pg[0]);
+      from_face_frame(fr, o.pv[1], pg[1]);
+      for (int v = 0; v < nv; ++v) {
+        FLX[((size_t)v * ny + j) * (nx + 1) + fi] = F[v];
+        for (int g = 0; g < 2; ++g) fx[(((size_t)g * nv + v) * ny + j) * (nx + 1) + fi] = pg[g][v];
+      }
+    }
+#pragma omp parallel for schedule(static) reduction(| : status)
+  for (int fj = 0; fj <= ny; ++fj)
+    for (int i = 0; i < nx; ++i) {
+      const double* fr = cg->fy + ((size_t)fj * nx + i) * 7;
+      orc_face_input in;
+      memset(&in, 0, sizeof(in));
+      in.dn = 1.0;
+      in.ds = fr[4];
+      in.curv = 1;
+      in.G[0] = fr[5];
+      in.G[1] = fr[6];
+      in.G[2] = 1.0 / fr[4];
+      for (int s = 0; s < 2; ++s) {
+        int jc = fj - 1 + s;
+        double Ub[4], p[4][5];
+        for (int v = 0; v < nv; ++v) {
+          Ub[v] = GW(G, v, jc, i);
+          for (int m = 0; m < 5; ++m) p[v][m] = GPC(G, v, m, jc, i);
+        }
+        curv_side(&in, s, fr, 1, s == 0 ? 0.5 : -0.5, Ub, p);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int n = 0; n < 3; ++n) {
+          double W[4];
+          get_cell(G, fj - 1 + m, i - 1 + n, W);
+          to_face_frame(fr, W, in.Ueq[m][n]);
+        }
+      orc_face_output o;
+      if (orc_face(P, &in, dt, &o)) status |= 1;
+      double F[4], pg[2][4];
+      from_face_frame(fr, o.flux, F);
+      from_face_frame(fr, o.pv[0], pg[0]);
+      from_face_frame(fr, o.pv[1], pg[1]);
+      for (int v = 0; v < nv; ++v) {
+        FLY[((size_t)v * (ny + 1) + fj) * nx + i] = F[v];
+        for (int g = 0; g < 2; ++g) fy[(((size_t)g * nv + v) * (ny + 1) + fj) * nx + i] = pg[g][v];
+      }
+    }
+  return status;
+}
+
 
 static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, double dt, double t, double* fluxx,
                   double* fluxy) {
@@ -1541,6 +1910,14 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
     }
   fill_ghosts_2d(P, G, t);
   fill_obstacle_2d(P, G);
+  cgeom cg;
+  memset(&cg, 0, sizeof(cg));
+  if (P->mesh) {
+    /* curvilinear grid: logical coordinates with unit spacing */
+    cgeom_build(P, &cg);
+    h = 1.0;
+    k = 1.0;
+  }
 
   /* reconstruction: interior cells and the edge ghost cells; the count of
    * interior gas cells that fell back to their average */
@@ -1550,10 +1927,16 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
     for (int i = -1; i <= nx; ++i) {
       int gx = (i < 0 || i >= nx), gy = (j < 0 || j >= ny);
       if (gx && gy) continue;
-      int fb = recon_cell_2d(P, G, j, i, h, k);
+      double Cw = P->mesh ? P->weno_c * cell_area(P, &cg, i, j) : P->weno_c;
+      int fb = recon_cell_2d(P, G, j, i, h, k, Cw);
       if (fb && !gx && !gy && !solid(P, i, j)) fallbacks += 1;
     }
   g_last_fallbacks = fallbacks;
+
+  if (P->mesh) {
+    status |= curv_faces(P, G, &cg, dt, fx, fy, FLX, FLY);
+    goto update;
+  }
 
   /* x interfaces */
 #pragma omp parallel for schedule(static) reduction(| : status)
@@ -1617,6 +2000,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       }
     }
 
+update:
   /* eq. finite: conservative update */
   for (int v = 0; v < nv; ++v)
     for (int j = 0; j < ny; ++j)
@@ -1624,8 +2008,9 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
         if (solid(P, i, j)) continue;
         double d = FLX[((size_t)v * ny + j) * (nx + 1) + i] - FLX[((size_t)v * ny + j) * (nx + 1) + i + 1] +
                    FLY[((size_t)v * (ny + 1) + j) * nx + i] - FLY[((size_t)v * (ny + 1) + j + 1) * nx + i];
-        cell[((size_t)v * ny + j) * nx + i] += d / (h * k);
+        cell[((size_t)v * ny + j) * nx + i] += d / (P->mesh ? cg.area[(size_t)j * nx + i] : h * k);
       }
+  cgeom_free(&cg);
   if (fluxx) memcpy(fluxx, FLX, sizeof(double) * nv * ny * (nx + 1));
   if (fluxy) memcpy(fluxy, FLY, sizeof(double) * nv * (ny + 1) * nx);
   free(G->W);
@@ -1691,7 +2076,7 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
         if (kind == ORC_BC_PERIODIC)
           memcpy(Wg, Ws, sizeof(Ws));
         else
-          mirror_state(P, side, kind, Ws, Wg);
+          mirror_state(P, side, kind, Ws, Wg, 0.0);
       }
       for (int v = 0; v < nv; ++v) W1(v, ig) = Wg[v];
     }
@@ -1702,7 +2087,7 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
       if (kind == ORC_BC_PERIODIC)
         memcpy(Wg, Ws, sizeof(Ws));
       else
-        mirror_state(P, side, kind, Ws, Wg);
+        mirror_state(P, side, kind, Ws, Wg, 0.0);
     }
     for (int v = 0; v < nv; ++v) F1(v, fg) = Wg[v];
   }
@@ -1826,6 +2211,29 @@ double orc_dt(const orc_problem* P, const double* cell) {
   double h = (P->x1 - P->x0) / nx, k = dim == 2 ? (P->y1 - P->y0) / ny : 1.0;
   double best = INFINITY;
   size_t n = (size_t)nx * ny;
+  if (dim == 2 && P->mesh) {
+    /* curvilinear grid: the widths across the two logical directions and
+     * the speed */
+    cgeom cg;
+    cgeom_build(P, &cg);
+    for (size_t c = 0; c < n; ++c) {
+      double W[4];
+      for (int v = 0; v < 4; ++v) W[v] = cell[(size_t)v * n + c];
+      double rho = W[0], u = W[1] / rho, vv = W[2] / rho, p = pressure(2, P->gamma, W);
+      if (!(rho > 0.0) || !(p > 0.0)) {
+        cgeom_free(&cg);
+        return -1.0;
+      }
+      double cs = sqrt(P->gamma * p / rho), nu = P->viscous ? P->mu / rho : 0.0, sp = sqrt(u * u + vv * vv);
+      double w[2] = {cg.h1[c], cg.h2[c]};
+      for (int d = 0; d < 2; ++d) {
+        double b = w[d] / (sp + cs + 2.0 * nu / w[d]);
+        if (b < best) best = b;
+      }
+    }
+    cgeom_free(&cg);
+    return P->cfl * best;
+  }
   for (size_t c = 0; c < n; ++c) {
     if (dim == 2 && solid(P, (int)(c % nx), (int)(c / nx))) continue;
     double W[4];

@@ -57,6 +57,14 @@ typedef struct {
   int admissibility;       /* a reconstructed cell polynomial is kept if, at its interface centres,
                               0: rho > 0 and p > 0; 1: also within a factor two of the range of
                               the neighbouring averages (else the constant average is used) */
+  /* 2D curvilinear grid (the extension the remark closing Sec. 3.3 points
+   * to; the polar cavity of Sec. 4.8): vertex coordinates [ny+1][nx+1][2] of
+   * straight-edged quadrilateral cells, cell (i, j) having the corners
+   * (i, j), (i+1, j), (i+1, j+1), (i, j+1) counter-clockwise.  NULL: the
+   * uniform grid of [x0, x1] x [y0, y1]. */
+  const double* mesh;
+  double bc_omega[4];      /* curvilinear grids: the no-slip wall also turns about the origin at this
+                              angular velocity (wall velocity (u_w - omega y, v_w + omega x)) */
 } orc_problem;
 
 /* --- kinetic building blocks ------------------------------------------- */
@@ -94,6 +102,12 @@ typedef struct {
   double W[2][4], Wn[2][4], Ws[2][4], Wnn[2][4], Wns[2][4], Wss[2][4];
   double Ueq[2][3][4]; /* cell averages of the equilibrium stencil [normal m][tangential n] */
   double dn, ds;       /* cell size normal / tangential to the interface */
+  /* curv = 1 (an interface of a curvilinear grid): the equilibrium quadratic
+   * of Sec. 3.3 is formed from Ueq with unit spacing (logical coordinates)
+   * and mapped to the interface frame with G = (G_nn, G_ns, G_ss): d/dn =
+   * G_nn d/dxi + G_ns d/deta, d/ds = G_ss d/deta (dn is then unused) */
+  int curv;
+  double G[3];
 } orc_face_input;
 
 typedef struct {

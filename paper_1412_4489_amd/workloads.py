@@ -42,6 +42,9 @@ class BC:
     state: tuple = (0.0, 0.0, 0.0, 0.0)   # primitive (rho, u, v, p)
     alt: tuple = (0.0, 0.0, 0.0, 0.0)     # second primitive state (DMR pre-shock)
     wall: tuple = (0.0, 0.0, 0.0)         # wall (u, v, T)
+    # curvilinear grids: a no-slip wall also turns about the origin at this
+    # angular velocity (wall velocity (u - omega y, v + omega x))
+    omega: float = 0.0
 
 
 @dataclass
@@ -81,6 +84,10 @@ class Problem:
     admissibility: int = 0
     t_end: float = 0.0
     name: str = ""
+    # 2D curvilinear grid: vertex coordinates [ny+1][nx+1][2] of straight-edged
+    # quadrilateral cells (cell (i, j): corners (i, j), (i+1, j), (i+1, j+1),
+    # (i, j+1), counter-clockwise); None: the uniform grid of the domain
+    mesh: object = None
 
     @property
     def nvar(self) -> int:
@@ -141,6 +148,62 @@ def _cell_average_2d(fun, prob: Problem, nq=4):
             X, Y = np.broadcast_arrays(X, Y)
             acc += wq[a] * wq[b] * fun(X, Y)
     return acc
+
+
+def _quad_average(fun, mesh, nq=4):
+    """Average of fun(x, y) -> (nvar, ...) over each straight-edged
+    quadrilateral of a vertex grid mesh[ny+1][nx+1][2]: tensor Gauss-Legendre
+    on the bilinear map of the corners (exact parametrisation of the cell),
+    weighted by its Jacobian."""
+    xq, wq = _gl(nq)
+    P00, P10 = mesh[:-1, :-1], mesh[:-1, 1:]
+    P11, P01 = mesh[1:, 1:], mesh[1:, :-1]
+    num, den = 0.0, 0.0
+    for a in range(nq):
+        for b in range(nq):
+            s, t = 0.5 + 0.5 * xq[a], 0.5 + 0.5 * xq[b]
+            X = (1 - s) * (1 - t) * P00 + s * (1 - t) * P10 + s * t * P11 + (1 - s) * t * P01
+            Xs = (1 - t) * (P10 - P00) + t * (P11 - P01)
+            Xt = (1 - s) * (P01 - P00) + s * (P11 - P10)
+            J = Xs[..., 0] * Xt[..., 1] - Xs[..., 1] * Xt[..., 0]
+            w = wq[a] * wq[b] * J
+            num = num + w * fun(X[..., 0], X[..., 1])
+            den = den + w
+    return num / den
+
+
+def _quad_face_values(fun, mesh):
+    """Values of fun at the two Gauss points of every edge of a vertex grid:
+    xi-interfaces (edges along eta) and eta-interfaces (edges along xi), the
+    point at -sqrt(3)/6 of the edge first (towards the lower index)."""
+    a, b = mesh[:-1, :], mesh[1:, :]      # xi-interfaces [ny][nx+1]
+    c, d = mesh[:, :-1], mesh[:, 1:]      # eta-interfaces [ny+1][nx]
+    fx = np.stack([fun(*np.moveaxis(0.5 * (a + b) + s * (b - a), -1, 0)) for s in (-GAUSS_OFFSET, GAUSS_OFFSET)])
+    fy = np.stack([fun(*np.moveaxis(0.5 * (c + d) + s * (d - c), -1, 0)) for s in (-GAUSS_OFFSET, GAUSS_OFFSET)])
+    return np.ascontiguousarray(fx), np.ascontiguousarray(fy)
+
+
+def polar_mesh(nr, nth, r0=1.0, r1=2.0, th0=-0.5, th1=0.5):
+    """Vertices of the grid uniform in (r, theta): xi along r, eta along theta."""
+    r = r0 + (r1 - r0) * np.arange(nr + 1) / nr
+    th = th0 + (th1 - th0) * np.arange(nth + 1) / nth
+    R, TH = np.meshgrid(r, th)
+    return np.ascontiguousarray(np.stack([R * np.cos(TH), R * np.sin(TH)], axis=-1))
+
+
+def mapped_mesh(nx, ny, lx=10.0, ly=10.0, amp=0.0, angle=0.0, shear=0.0):
+    """Vertices of [0, lx] x [0, ly] moved by a periodic wave of amplitude amp
+    (x += amp lx sin(2 pi x/lx) sin(2 pi y/ly), y likewise), then sheared
+    (x += shear y) and turned by angle about the origin.  With amp = 0 the
+    cells are parallelograms; the grid stays periodic by translation."""
+    x = lx * np.arange(nx + 1) / nx
+    y = ly * np.arange(ny + 1) / ny
+    X, Y = np.meshgrid(x, y)
+    wave = np.sin(2 * math.pi * X / lx) * np.sin(2 * math.pi * Y / ly)
+    X, Y = X + amp * lx * wave, Y + amp * ly * wave
+    X = X + shear * Y
+    c, s = math.cos(angle), math.sin(angle)
+    return np.ascontiguousarray(np.stack([c * X - s * Y, s * X + c * Y], axis=-1))
 
 
 def _face_values_2d(fun, prob: Problem):
@@ -650,6 +713,148 @@ def random_perturbed_2d(nx=24, ny=20, seed=0, amp=0.2, gamma=1.4, bc="periodic",
         fx[..., nx] = fx[..., 0]
         fy[..., ny, :] = fy[..., 0, :]
     return prob, State(np.ascontiguousarray(cell), np.ascontiguousarray(fx), np.ascontiguousarray(fy))
+
+
+# --------------------------------------------------------------------------
+# curvilinear grids (the extension the remark closing Sec. 3.3 points to;
+# the polar cavity of Sec. 4.8)
+# --------------------------------------------------------------------------
+
+def _mesh_problem(mesh, **kw):
+    ny, nx = mesh.shape[0] - 1, mesh.shape[1] - 1
+    lo, hi = mesh.reshape(-1, 2).min(axis=0), mesh.reshape(-1, 2).max(axis=0)
+    return Problem(dim=2, nx=nx, ny=ny, x0=float(lo[0]), x1=float(hi[0]), y0=float(lo[1]), y1=float(hi[1]),
+                   mesh=mesh, **kw)
+
+
+def _mesh_state(prob, fun, nq=4):
+    cell = np.ascontiguousarray(_quad_average(fun, prob.mesh, nq=nq))
+    fx, fy = _quad_face_values(fun, prob.mesh)
+    if prob.bc[0].kind == "periodic":
+        fx[..., prob.nx] = fx[..., 0]
+    if prob.bc[2].kind == "periodic":
+        fy[..., prob.ny, :] = fy[..., 0, :]
+    return State(cell, np.ascontiguousarray(fx), np.ascontiguousarray(fy))
+
+
+def _lattice_vortex(X, Y, g, eps, centre, A, B, mean):
+    """the isentropic vortex of Sec. 4.1 (strength eps, unit core) centred at
+    the periodic image of `centre` nearest to (X, Y) on the lattice spanned
+    by A and B, carried by the mean flow `mean` (rho = p = 1 at infinity)"""
+    M = np.array([[A[0], B[0]], [A[1], B[1]]])
+    Mi = np.linalg.inv(M)
+    dX, dY = X - centre[0], Y - centre[1]
+    a = Mi[0, 0] * dX + Mi[0, 1] * dY
+    b = Mi[1, 0] * dX + Mi[1, 1] * dY
+    a -= np.floor(a + 0.5)
+    b -= np.floor(b + 0.5)
+    dxp = M[0, 0] * a + M[0, 1] * b
+    dyp = M[1, 0] * a + M[1, 1] * b
+    r2 = dxp * dxp + dyp * dyp
+    du = eps / (2 * math.pi) * np.exp(0.5 * (1.0 - r2)) * (-dyp)
+    dv = eps / (2 * math.pi) * np.exp(0.5 * (1.0 - r2)) * dxp
+    T = 1.0 - (g - 1.0) * eps * eps / (8.0 * g * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (g - 1.0))
+    return rho, mean[0] + du, mean[1] + dv, rho * T
+
+
+def vortex_mapped(n=64, amp=0.0, angle=0.0, shear=0.0, t_end=10.0, eps=5.0, cfl=0.2, nq=4):
+    """The isentropic vortex of Sec. 4.1 on a curvilinear periodic grid:
+    [0, 10]^2 with n x n cells, waved (amp), sheared and turned by `angle`
+    (mapped_mesh); the mean flow (1, 1) and the vortex centre (5, 5) are
+    carried by the same shear and turn, so with amp = shear = 0 the problem is
+    the Cartesian vortex turned as a whole."""
+    g = 1.4
+    mesh = mapped_mesh(n, n, 10.0, 10.0, amp=amp, angle=angle, shear=shear)
+    c, s_ = math.cos(angle), math.sin(angle)
+
+    def turn(x, y):
+        x = x + shear * y
+        return (c * x - s_ * y, s_ * x + c * y)
+
+    A, B, centre = turn(10.0, 0.0), turn(0.0, 10.0), turn(5.0, 5.0)
+    mean = (c - s_, s_ + c) if shear == 0.0 else turn(1.0, 1.0)
+    prob = _mesh_problem(mesh, gamma=g, tau_eps=0.0, tau_c=1.0, cfl=cfl, t_end=t_end,
+                         name=f"vortex_mapped_{n}")
+    prob.vortex = dict(eps=eps, centre=centre, A=A, B=B, mean=mean)
+
+    def fun(X, Y):
+        return cons(g, *_lattice_vortex(X, Y, g, eps, centre, A, B, mean))
+
+    return prob, _mesh_state(prob, fun, nq=nq)
+
+
+def vortex_mapped_exact_density(prob, t, nq=6):
+    """exact cell-average density of vortex_mapped at time t"""
+    v = prob.vortex
+    centre = (v["centre"][0] + v["mean"][0] * t, v["centre"][1] + v["mean"][1] * t)
+
+    def fun(X, Y):
+        return _lattice_vortex(X, Y, prob.gamma, v["eps"], centre, v["A"], v["B"], v["mean"])[0][None]
+
+    return _quad_average(fun, prob.mesh, nq=nq)[0]
+
+
+def uniform_mesh(mesh, state=(1.3, 0.4, -0.7, 2.1), gamma=1.4, bc="periodic", **kw):
+    """Free stream on a curvilinear grid (periodic, or the state flowing in on
+    every side)."""
+    prob = _mesh_problem(mesh, gamma=gamma, name="uniform_mesh", **kw)
+    prob.bc = [BC(bc, state=state) for _ in range(4)]
+    q = cons(gamma, *state)
+    return prob, _mesh_state(prob, lambda X, Y: np.broadcast_to(q.reshape(4, *([1] * X.ndim)), (4,) + X.shape).copy())
+
+
+def solid_rotation(n=32, omega=0.5, viscous=False, mu=1e-3, prandtl=0.72, gamma=5.0 / 3.0, t_end=1.0,
+                   cfl=0.2):
+    """Gas turning as a solid body, u = omega (-y, x), at the uniform
+    temperature 1, in the annulus 1 < r < 2 (the radii of the polar cavity of
+    Sec. 4.8) with n cells across and 4n around (periodic in theta): density
+    rho = exp(omega^2 (r^2 - 1)/2) holds the radial pressure gradient.  Both
+    walls are isothermal (T = 1) and turn with the gas, so this state is
+    steady for the Euler and the Navier-Stokes equations (no strain, no heat
+    flux)."""
+    mesh = polar_mesh(n, 4 * n, th0=-math.pi, th1=math.pi)
+    mesh[-1] = mesh[0]  # the seam: the same vertices
+    bc = [BC("noslip_iso", wall=(0.0, 0.0, 1.0), omega=omega) for _ in range(2)] + [BC("periodic"), BC("periodic")]
+    prob = _mesh_problem(mesh, gamma=gamma, viscous=viscous, mu=mu if viscous else 0.0,
+                         prandtl=prandtl if viscous else 1.0, tau_eps=0.05, tau_c=1.0, cfl=cfl, t_end=t_end,
+                         bc=bc, name=f"solid_rotation_{n}")
+    prob.rotation = omega
+
+    def fun(X, Y):
+        rho = np.exp(0.5 * omega * omega * (X * X + Y * Y - 1.0))
+        return cons(gamma, rho, -omega * Y, omega * X, rho)
+
+    return prob, _mesh_state(prob, fun, nq=6)
+
+
+def solid_rotation_exact(prob, nq=6):
+    """exact cell averages of solid_rotation (steady)"""
+    w, g = prob.rotation, prob.gamma
+
+    def fun(X, Y):
+        rho = np.exp(0.5 * w * w * (X * X + Y * Y - 1.0))
+        return cons(g, rho, -w * Y, w * X, rho)
+
+    return _quad_average(fun, prob.mesh, nq=nq)
+
+
+def polar_cavity(n=65, re=350.0, mach=0.15, prandtl=0.72, gamma=5.0 / 3.0, turns=20.0):
+    """Sec. 4.8 polar cavity: (r, theta) in [1, 2] x [-0.5, 0.5], uniform in r
+    and theta ("65 x 65 mesh points" read as cells, like the square cavity),
+    gas at rest (rho = 1, T = 1), isothermal no-slip walls at T = 1; the inner
+    wall r = 1 turns anticlockwise at the speed U_i = Ma sqrt(gamma) (angular
+    velocity U_i / R_i, R_i = 1); constant mu = U_i R_i / Re.  The end time
+    is `turns` passages of the inner wall's speed across the unit gap."""
+    ui = mach * math.sqrt(gamma)
+    mesh = polar_mesh(n, n)
+    wall = (0.0, 0.0, 1.0)
+    bc = [BC("noslip_iso", wall=wall, omega=ui), BC("noslip_iso", wall=wall),
+          BC("noslip_iso", wall=wall), BC("noslip_iso", wall=wall)]
+    prob = _mesh_problem(mesh, gamma=gamma, viscous=True, mu=ui / re, prandtl=prandtl, tau_eps=0.0, tau_c=1.0,
+                         cfl=0.2, t_end=turns / ui, bc=bc, name=f"polar_cavity_{n}_re{int(re)}")
+    q = cons(gamma, 1.0, 0.0, 0.0, 1.0)
+    return prob, _mesh_state(prob, lambda X, Y: np.broadcast_to(q.reshape(4, *([1] * X.ndim)), (4,) + X.shape).copy())
 
 
 def mirror_extension(prob, st, axis):
