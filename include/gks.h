@@ -83,6 +83,11 @@ typedef struct {
   double state[4]; /* primitive (rho, u, v, p) */
   double alt[4];   /* second primitive state (DMR pre-shock) */
   double wall_u, wall_v, wall_T;
+  /* no-slip walls of a curvilinear grid (gks_problem.mesh) only: the wall
+   * also turns about the origin at this angular velocity, its velocity at
+   * the wall point (x, y) being (wall_u - wall_omega y, wall_v + wall_omega x)
+   * (the turning inner wall of the polar cavity, Sec. 4.8); 0 elsewhere */
+  double wall_omega;
 } gks_bc;
 
 /* The problem, as the paper states it: Euler or Navier-Stokes for
@@ -121,6 +126,28 @@ typedef struct {
    * (needed by the Mach-10 double Mach reflection of Sec. 4.5).  Otherwise
    * the cell takes its constant average for the step. */
   int32_t admissibility;
+  /* 2D curvilinear grid (the extension that the remark closing Sec. 3.3
+   * points to; the polar cavity of Sec. 4.8), or NULL for the uniform grid
+   * of [x0, x1] x [y0, y1].  Host memory, read during gks_init /
+   * gks_init_device only: vertex coordinates [ny+1][nx+1][2] (x, y), cell
+   * (i, j) being the straight-edged quadrilateral with corners (i, j),
+   * (i+1, j), (i+1, j+1), (i, j+1) in counter-clockwise order (positive
+   * area).  The scheme then runs in the grid's logical coordinates: the
+   * compact reconstruction of Sec. 3.2 with unit spacing and I(U1) = C |K|
+   * (|K| the cell's area); each interface is evaluated in the frame of its
+   * edge (unit normal from the lower to the higher logical index, unit
+   * tangent along the edge towards the higher index, its length as the
+   * interface extent), the logical derivatives turned into frame derivatives
+   * by the metric at the interface centre (the vector between the two cell
+   * centres, the mean of each cell's corners, and the edge); the update
+   * divides by the cell areas; the CFL condition takes the widths |K| / (mean
+   * length of the two opposite edges) and the speed.  Allowed with: dim 2,
+   * conservative variables (recon_vars 0), no solid step, boundaries
+   * periodic (the opposite edges one translation apart), outflow, no-slip
+   * (with wall_omega) or inflow.  x0..y1 are not used.  The "x" ("y")
+   * interfaces and the point value layouts refer to the logical directions
+   * i (j); momentum components and point values stay in (x, y). */
+  const double* mesh;
 } gks_problem;
 
 typedef struct gks_handle gks_handle; /* opaque, owned by the library */

@@ -36,6 +36,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -104,16 +106,36 @@ struct BCDev {
   double state[4];  // conservative
   double alt[4];    // conservative
   double wu, wv, wT;
+  double wo;        // curvilinear grids: angular velocity of a turning no-slip wall
 };
 
 struct Geo {
-  double x0, y0, h, k;
+  double x0, y0, h, k;  // curvilinear grids: h = k = 1 (logical coordinates)
 };
+
+// Geometry of a curvilinear grid (all null for the uniform grid):
+//   fx   x interfaces (logical direction i), 7 planes of [ny][nx+1]: unit
+//        normal (2), unit tangent (2), length L, metric G_nn, G_ns
+//        (d/dn = G_nn d/dxi + G_ns d/deta, d/dt = d/deta / L)
+//   fy   y interfaces, 7 planes of [ny+1][nx], the same with xi <-> eta
+//   area cell areas [ny+2][nx+2] over cells -1..nx x -1..ny (an edge ghost
+//        cell has its image's)
+//   wid  2 planes of [ny][nx]: widths across the i and the j direction
+//   bnd  boundary vertices (x, y): west [ny+1], east [ny+1], south [nx+1], north [nx+1]
+struct CurvDev {
+  const double* fx;
+  const double* fy;
+  const double* area;
+  const double* wid;
+  const double* bnd;
+};
+constexpr int kFaceGeo = 7;
 
 template <typename TS, typename TP>
 struct Grid {
   Idx ix;
   Geo geo;
+  CurvDev cv;
   double* W;
   TS* FX;
   TS* FY;
@@ -229,8 +251,28 @@ __device__ bool bc_fixed(const BCDev& b, int nv, double x, double y, double t, d
   return false;
 }
 
-// mirror image of a 2D state across a boundary with normal `axis`
-__device__ void bc_mirror(const BCDev& b, int axis, double gamma, const double* s, double* o) {
+// wall velocity of boundary `side` at logical position sp along it: a
+// turning wall of a curvilinear grid moves at its wall point (linear along
+// the boundary's edges, continued linearly past its ends)
+template <typename TS, typename TP>
+__device__ void wall_velocity(const Grid<TS, TP>& g, const BCDev& b, int side, double sp, double& wu, double& wv) {
+  wu = b.wu;
+  wv = b.wv;
+  if (b.wo == 0.0) return;
+  const int nx = g.ix.nx, ny = g.ix.ny, n = side < 2 ? ny : nx;
+  const double* v = g.cv.bnd + (side == 0 ? 0 : side == 1 ? 2 * (ny + 1) : side == 2 ? 4 * (ny + 1) : 4 * (ny + 1) + 2 * (nx + 1));
+  int e = (int)floor(sp);
+  e = e < 0 ? 0 : (e > n - 1 ? n - 1 : e);
+  const double f = sp - e;
+  const double x = v[2 * e] + f * (v[2 * e + 2] - v[2 * e]), y = v[2 * e + 1] + f * (v[2 * e + 3] - v[2 * e + 1]);
+  wu -= b.wo * y;
+  wv += b.wo * x;
+}
+
+// mirror image of a 2D state across a boundary with normal `axis` (wu, wv:
+// the wall velocity of a no-slip wall)
+__device__ void bc_mirror(const BCDev& b, int axis, double gamma, const double* s, double* o, double wu,
+                          double wv) {
   for (int v = 0; v < 4; ++v) o[v] = s[v];
   const int kind = b.kind;
   if (kind == GKS_BC_REFLECT || kind == GKS_BC_DMR_BOTTOM) {
@@ -240,7 +282,7 @@ __device__ void bc_mirror(const BCDev& b, int axis, double gamma, const double* 
     const double p = (gamma - 1.0) * (s[3] - 0.5 * rho * (u * u + v * v));
     const double T = p / rho;
     const double Tg = kind == GKS_BC_NOSLIP_ISOTHERMAL ? 2.0 * b.wT - T : T;
-    const double ug = 2.0 * b.wu - u, vg = 2.0 * b.wv - v;
+    const double ug = 2.0 * wu - u, vg = 2.0 * wv - v;
     o[0] = rho;
     o[1] = rho * ug;
     o[2] = rho * vg;
@@ -276,10 +318,13 @@ __device__ void ghost_x_cell(const Prob<TS, TP, TC>& Q, const Grid<TS, TP>& g, d
   double src[4];
   const int is = b.kind == GKS_BC_PERIODIC ? (side == 0 ? ig + nx : ig - nx) : (side == 0 ? -1 - ig : 2 * nx - 1 - ig);
   for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, j, is)];
-  if (b.kind == GKS_BC_PERIODIC)
+  if (b.kind == GKS_BC_PERIODIC) {
     for (int v = 0; v < 4; ++v) out[v] = src[v];
-  else
-    bc_mirror(b, 0, Q.P.gamma, src, out);
+  } else {
+    double wu, wv;
+    wall_velocity(g, b, side, j + 0.5, wu, wv);
+    bc_mirror(b, 0, Q.P.gamma, src, out, wu, wv);
+  }
 }
 
 // West (side 0) / east (side 1): ghost cells of rows 0..ny-1, ghost x
@@ -309,10 +354,13 @@ __device__ void ghost_we_item(const Prob<TS, TP, TC>& Q, int id) {
     if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const int fs = b.kind == GKS_BC_PERIODIC ? (side == 0 ? nx - 1 : 1) : (side == 0 ? 1 : nx - 1);
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FX[g.ix.fx(gp, v, j, fs)];
-      if (b.kind == GKS_BC_PERIODIC)
+      if (b.kind == GKS_BC_PERIODIC) {
         for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 0, gamma, src, out);
+      } else {
+        double wu, wv;
+        wall_velocity(g, b, side, j + 0.5 + (gp ? kGaussOffset : -kGaussOffset), wu, wv);
+        bc_mirror(b, 0, gamma, src, out, wu, wv);
+      }
     }
     for (int v = 0; v < 4; ++v) g.FX[g.ix.fx(gp, v, j, fg)] = (TS)out[v];
     return;
@@ -328,10 +376,13 @@ __device__ void ghost_we_item(const Prob<TS, TP, TC>& Q, int id) {
       const int is = per ? (side == 0 ? nx - 1 : 0) : (side == 0 ? 0 : nx - 1);
       const int gs = per ? gp : 1 - gp;  // a mirror swaps the tangential Gauss points
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FY[g.ix.fy(gs, v, fj, is)];
-      if (per)
+      if (per) {
         for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 0, gamma, src, out);
+      } else {
+        double wu, wv;
+        wall_velocity(g, b, side, (double)fj, wu, wv);
+        bc_mirror(b, 0, gamma, src, out, wu, wv);
+      }
     }
     for (int v = 0; v < 4; ++v) g.FY[g.ix.fy(gp, v, fj, ig)] = (TS)out[v];
   }
@@ -365,10 +416,13 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
         ghost_x_cell(Q, g, t, js, i, src);
       else
         for (int v = 0; v < 4; ++v) src[v] = g.W[g.ix.w(v, js, i)];
-      if (b.kind == GKS_BC_PERIODIC)
+      if (b.kind == GKS_BC_PERIODIC) {
         for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 1, gamma, src, out);
+      } else {
+        double wu, wv;
+        wall_velocity(g, b, 2 + side, i + 0.5, wu, wv);
+        bc_mirror(b, 1, gamma, src, out, wu, wv);
+      }
     }
     for (int v = 0; v < 4; ++v) g.W[g.ix.w(v, jg, i)] = out[v];
     return;
@@ -382,10 +436,13 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
     if (!bc_fixed(b, 4, xg, yg, t, out)) {
       const int fs = b.kind == GKS_BC_PERIODIC ? (side == 0 ? ny - 1 : 1) : (side == 0 ? 1 : ny - 1);
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FY[g.ix.fy(gp, v, fs, i)];
-      if (b.kind == GKS_BC_PERIODIC)
+      if (b.kind == GKS_BC_PERIODIC) {
         for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 1, gamma, src, out);
+      } else {
+        double wu, wv;
+        wall_velocity(g, b, 2 + side, i + 0.5 + (gp ? kGaussOffset : -kGaussOffset), wu, wv);
+        bc_mirror(b, 1, gamma, src, out, wu, wv);
+      }
     }
     for (int v = 0; v < 4; ++v) g.FY[g.ix.fy(gp, v, fg, i)] = (TS)out[v];
     return;
@@ -401,10 +458,13 @@ __device__ void ghost_sn_item(const Prob<TS, TP, TC>& Q, int id) {
       const int js = per ? (side == 0 ? ny - 1 : 0) : (side == 0 ? 0 : ny - 1);
       const int gs = per ? gp : 1 - gp;
       for (int v = 0; v < 4; ++v) src[v] = (double)g.FX[g.ix.fx(gs, v, js, fi)];
-      if (per)
+      if (per) {
         for (int v = 0; v < 4; ++v) out[v] = src[v];
-      else
-        bc_mirror(b, 1, gamma, src, out);
+      } else {
+        double wu, wv;
+        wall_velocity(g, b, 2 + side, (double)fi, wu, wv);
+        bc_mirror(b, 1, gamma, src, out, wu, wv);
+      }
     }
     for (int v = 0; v < 4; ++v) g.FX[g.ix.fx(gp, v, jg, fi)] = (TS)out[v];
   }
@@ -521,7 +581,7 @@ __global__ void __launch_bounds__(256) k_step_images_2d(KA<Prob<TS, TP, TC>> a) 
     const int dx = id / 2, m = id % 2;
     for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, m, i0 - 1 - dx)];
     flip_uv(src, true, false, mid);
-    bc_mirror(Q.bc[2], 1, gamma, mid, out);
+    bc_mirror(Q.bc[2], 1, gamma, mid, out, Q.bc[2].wu, Q.bc[2].wv);
     for (int v = 0; v < 4; ++v) g.W[x.w(v, -1 - m, i0 + dx)] = out[v];
     return;
   }
@@ -531,7 +591,7 @@ __global__ void __launch_bounds__(256) k_step_images_2d(KA<Prob<TS, TP, TC>> a) 
     const int m = id / 2, dy = id % 2;
     for (int v = 0; v < 4; ++v) src[v] = g.W[x.w(v, nj + dy, nx - 1 - m)];
     flip_uv(src, false, true, mid);
-    bc_mirror(Q.bc[1], 0, gamma, mid, out);
+    bc_mirror(Q.bc[1], 0, gamma, mid, out, Q.bc[1].wu, Q.bc[1].wv);
     for (int v = 0; v < 4; ++v) g.W[x.w(v, nj - 1 - dy, nx + m)] = out[v];
     return;
   }
@@ -627,6 +687,16 @@ __device__ __forceinline__ double cell_dt_bound(const double* W, const Phys& P, 
   return fmin(h / (fabs(u) + cs + 2.0 * nu / h), k / (fabs(v) + cs + 2.0 * nu / k));
 }
 
+// curvilinear grids: the widths w1, w2 across the two logical directions and
+// the speed
+__device__ __forceinline__ double cell_dt_bound_curv(const double* W, const Phys& P, double w1, double w2) {
+  const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
+  const double p = (P.gamma - 1.0) * (W[3] - 0.5 * rho * (u * u + v * v));
+  const double cs = sqrt(P.gamma * p / rho), sp = sqrt(u * u + v * v);
+  const double nu = P.viscous ? P.mu / rho : 0.0;
+  return fmin(w1 / (sp + cs + 2.0 * nu / w1), w2 / (sp + cs + 2.0 * nu / w2));
+}
+
 __device__ __forceinline__ double cell_dt_bound_1d(const double* W, const Phys& P, double h) {
   const double rho = W[0], u = W[1] / rho;
   const double p = (P.gamma - 1.0) * (W[2] - 0.5 * rho * u * u);
@@ -659,7 +729,10 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   if (id >= (nx + 2) * (ny + 2)) return;
   const int j = id / (nx + 2) - 1, i = id % (nx + 2) - 1;
   if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
-  const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, Cw = Q.P.weno_c, gamma = Q.P.gamma;
+  // a curvilinear grid reconstructs in logical coordinates (h = k = 1) with
+  // I(U1) = C |K|, the cell's area
+  const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, gamma = Q.P.gamma;
+  const double Cw = Q.P.weno_c * (g.cv.area ? g.cv.area[(size_t)(j + 1) * (nx + 2) + (i + 1)] : 1.0);
   const Idx& x = g.ix;
   // ties of the cross-derivative candidates: the rounding noise of the stored
   // point values -- in double the accumulated rounding of the arithmetic that
@@ -904,6 +977,81 @@ __device__ __forceinline__ void mirror_side(double (&Wc)[4], double (&pc)[4][5])
   }
 }
 
+// Curvilinear grids: the frame of interface F, fr = (unit normal, unit
+// tangent, length L, metric G_nn, G_ns)
+template <typename TS, typename TP>
+__device__ __forceinline__ void face_geo(const Grid<TS, TP>& g, const Face& F, double (&fr)[kFaceGeo]) {
+  const Idx& x = g.ix;
+  const double* base = F.isx ? g.cv.fx : g.cv.fy;
+  const size_t plane = F.isx ? (size_t)x.ny * (x.nx + 1) : (size_t)(x.ny + 1) * x.nx;
+  const size_t o = F.isx ? (size_t)F.a * (x.nx + 1) + F.b : (size_t)F.a * x.nx + F.b;
+#pragma unroll
+  for (int q = 0; q < kFaceGeo; ++q) fr[q] = base[q * plane + o];
+}
+
+// momentum components (x, y) -> (normal, tangential) of frame fr
+__device__ __forceinline__ void to_face(const double (&fr)[kFaceGeo], double& m1, double& m2) {
+  const double a = fr[0] * m1 + fr[1] * m2, b = fr[2] * m1 + fr[3] * m2;
+  m1 = a;
+  m2 = b;
+}
+
+// Side s of interface F of a curvilinear grid in the interface frame: the
+// value and logical derivatives of the side cell's polynomial (logical
+// coordinates, unit spacing) at the interface centre, turned into frame
+// derivatives by the metric (d/dn = G_nn d/dxi + G_ns d/deta, d/dt =
+// d/deta / L; second derivatives likewise) and frame momentum, then written
+// as the average and coefficients that side_state_2d and side_targets_2d
+// read with hn = 1 and hs = L.
+template <typename TS, typename TP>
+__device__ __forceinline__ void load_face_cell_curv(const Grid<TS, TP>& g, const Face& F, int s,
+                                                    const double (&fr)[kFaceGeo], double (&Wc)[4],
+                                                    double (&pc)[4][5]) {
+  const Idx& x = g.ix;
+  const double xn = s == 0 ? 0.5 : -0.5, L = fr[4], g00 = fr[5], g01 = fr[6], g11 = 1.0 / L;
+  double U[4], D[5][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double w, pn, ps, pnn, pss, pns;
+    if (F.isx) {
+      const int j = F.a, ic = F.b - 1 + s;
+      w = g.W[x.w(v, j, ic)];
+      pn = (double)g.PC[x.pc(v, 0, j, ic)];
+      ps = (double)g.PC[x.pc(v, 1, j, ic)];
+      pnn = (double)g.PC[x.pc(v, 2, j, ic)];
+      pss = (double)g.PC[x.pc(v, 3, j, ic)];
+      pns = (double)g.PC[x.pc(v, 4, j, ic)];
+    } else {
+      const int jc = F.a - 1 + s, i = F.b;
+      w = g.W[x.w(v, jc, i)];
+      pn = (double)g.PC[x.pc(v, 1, jc, i)];
+      ps = (double)g.PC[x.pc(v, 0, jc, i)];
+      pnn = (double)g.PC[x.pc(v, 3, jc, i)];
+      pss = (double)g.PC[x.pc(v, 2, jc, i)];
+      pns = (double)g.PC[x.pc(v, 4, jc, i)];
+    }
+    U[v] = w + pn * xn + pnn * (1.0 / 12.0) - pss * (1.0 / 24.0);
+    const double ln = pn + pnn * xn, ls = ps + pns * xn;
+    D[0][v] = g00 * ln + g01 * ls;
+    D[1][v] = g11 * ls;
+    D[2][v] = g00 * g00 * pnn + 2.0 * g00 * g01 * pns + g01 * g01 * pss;
+    D[3][v] = g11 * g11 * pss;
+    D[4][v] = g11 * (g00 * pns + g01 * pss);
+  }
+  to_face(fr, U[1], U[2]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) to_face(fr, D[k][1], D[k][2]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    pc[v][2] = D[2][v];
+    pc[v][3] = D[3][v];
+    pc[v][4] = D[4][v];
+    pc[v][0] = D[0][v] - D[2][v] * xn;
+    pc[v][1] = D[1][v] - D[4][v] * xn;
+    Wc[v] = U[v] - pc[v][0] * xn - D[2][v] * (1.0 / 12.0) + D[3][v] * (L * L * (1.0 / 24.0));
+  }
+}
+
 // LDS bytes per thread of k_iface_2d: the frame record of g0 and the
 // accumulated flux and point values (interface frame)
 template <typename TC>
@@ -925,7 +1073,9 @@ __device__ __forceinline__ void section_boundary() {
 // LDS, the flux and the point values stored once at the end.  No thread
 // reads another's slots (no barrier), so a block may take several logical
 // blocks in turn.
-template <typename TS, typename TP, typename TC>
+// kCurv: the problems of the launch are curvilinear grids (each interface
+// in the frame of its edge; no solid step)
+template <typename TS, typename TP, typename TC, bool kCurv>
 __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, unsigned L, unsigned char* lds) {
   int id;
   const Prob<TS, TP, TC>& Q = locate_at(a, L, KK_FACE, id);
@@ -935,18 +1085,40 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
   const Phys P = Q.P;
   const Idx& x = g.ix;
   const Face F = face_of(x, id);
-  if (inside_step(Q, F)) return;
-  const int ws = wall_side(Q, F);
+  if (!kCurv && inside_step(Q, F)) return;
+  const int ws = kCurv ? -1 : wall_side(Q, F);
   const unsigned nb = blockDim.x, me = threadIdx.x;
   const Rec<TC> R{(double*)lds, (TC*)(lds + (size_t)ND_REC * 8 * nb), nb};
   double* acc = (double*)(lds + (size_t)(ND_REC * 8 + nt_rec<TC>() * sizeof(TC)) * nb);  // [12][nb]
-  const double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
+  double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
+  if constexpr (kCurv) {
+    double fr[kFaceGeo];
+    face_geo(g, F, fr);
+    hn = 1.0;
+    hs = fr[4];
+  }
   // prologue
   {
     double Wc[2][4], pc[2][4][5], Ueq[2][3][4], flux[4], pv[4];
-    load_face_cell(g, F, 0, Wc[0], pc[0]);
-    load_face_cell(g, F, 1, Wc[1], pc[1]);
-    if (F.isx) {
+    double fr[kFaceGeo];
+    if constexpr (kCurv) {
+      face_geo(g, F, fr);
+      load_face_cell_curv(g, F, 0, fr, Wc[0], pc[0]);
+      load_face_cell_curv(g, F, 1, fr, Wc[1], pc[1]);
+    } else {
+      load_face_cell(g, F, 0, Wc[0], pc[0]);
+      load_face_cell(g, F, 1, Wc[1], pc[1]);
+    }
+    if (kCurv && !F.isx) {
+      // logical orientation, frame momentum below
+      const int fj = F.a, i = F.b;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Ueq[m][n][v] = g.W[x.w(v, fj - 1 + m, i - 1 + n)];
+    } else if (F.isx) {
       const int j = F.a, fi = F.b;
 #pragma unroll
       for (int m = 0; m < 2; ++m)
@@ -978,8 +1150,18 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
         }
         mirror_side(Wc[s], pc[s]);
       }
+    double Gm[3] = {0.0, 0.0, 0.0};
+    if constexpr (kCurv) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 3; ++n) to_face(fr, Ueq[m][n][1], Ueq[m][n][2]);
+      Gm[0] = fr[5];
+      Gm[1] = fr[6];
+      Gm[2] = 1.0 / fr[4];
+    }
     if (!(dt > 0.0)) return;  // an empty step (end time reached, or after a nonphysical state)
-    const bool ok = iface_prologue_2d<TC>(P, dt, hn, hs, Wc, pc, Ueq, R, me, flux, pv);
+    const bool ok = iface_prologue_2d<TC, kCurv>(P, dt, hn, hs, Wc, pc, Ueq, R, me, flux, pv, Gm);
     if (!ok) {
       R.D(D_RHO0, me) = 0.0;  // the later sections add nothing
       atomicCAS(g.err, 0ull,
@@ -1016,8 +1198,14 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     section_boundary();
     const bool valid = R.D(D_RHO0, me) > 0.0;
     double Wc[4], pc[4][5];
-    load_face_cell(g, F, side == ws ? 1 - side : side, Wc, pc);
-    if (side == ws) mirror_side(Wc, pc);
+    if constexpr (kCurv) {
+      double fr[kFaceGeo];
+      face_geo(g, F, fr);
+      load_face_cell_curv(g, F, side, fr, Wc, pc);
+    } else {
+      load_face_cell(g, F, side == ws ? 1 - side : side, Wc, pc);
+      if (side == ws) mirror_side(Wc, pc);
+    }
     double flux[4], pvm[4], pvp[4], E[4];
     iface_kinetic_2d<TC>(P, dt, hn, hs, side, Wc, pc, R, me, flux, pvm, pvp, E);
     if (valid) {
@@ -1049,6 +1237,31 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
     Fl[3] += P.prfix * qh;
   }
+  if constexpr (kCurv) {
+    // frame momentum back to (x, y); the grid's own interface layouts
+    double fr[kFaceGeo];
+    face_geo(g, F, fr);
+    const double f1 = Fl[1], f2 = Fl[2], m1 = Pm[1], m2 = Pm[2], q1 = Pp[1], q2 = Pp[2];
+    Fl[1] = fr[0] * f1 + fr[2] * f2;
+    Fl[2] = fr[1] * f1 + fr[3] * f2;
+    Pm[1] = fr[0] * m1 + fr[2] * m2;
+    Pm[2] = fr[1] * m1 + fr[3] * m2;
+    Pp[1] = fr[0] * q1 + fr[2] * q2;
+    Pp[2] = fr[1] * q1 + fr[3] * q2;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (F.isx) {
+        g.FLX[x.flx(v, F.a, F.b)] = Fl[v];
+        g.FX[x.fx(0, v, F.a, F.b)] = (TS)Pm[v];
+        g.FX[x.fx(1, v, F.a, F.b)] = (TS)Pp[v];
+      } else {
+        g.FLY[x.fly(v, F.a, F.b)] = Fl[v];
+        g.FY[x.fy(0, v, F.a, F.b)] = (TS)Pm[v];
+        g.FY[x.fy(1, v, F.a, F.b)] = (TS)Pp[v];
+      }
+    }
+    return;
+  }
   if (F.isx) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1069,18 +1282,19 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
 }
 
 // one logical block per block
-template <typename TS, typename TP, typename TC>
+template <typename TS, typename TP, typename TC, bool kCurv = false>
 __global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  iface_2d_block(a, logical_block(a.nblk), lds);
+  iface_2d_block<TS, TP, TC, kCurv>(a, logical_block(a.nblk), lds);
 }
 
 // persistent form: gridDim.x (a multiple of 8) blocks take the logical
 // blocks in turn
-template <typename TS, typename TP, typename TC>
+template <typename TS, typename TP, typename TC, bool kCurv = false>
 __global__ void __launch_bounds__(256) k_iface_2d_loop(KA<Prob<TS, TP, TC>> a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  for (unsigned b = blockIdx.x; b < a.nblk; b += gridDim.x) iface_2d_block(a, logical_of(b, a.nblk), lds);
+  for (unsigned b = blockIdx.x; b < a.nblk; b += gridDim.x)
+    iface_2d_block<TS, TP, TC, kCurv>(a, logical_of(b, a.nblk), lds);
 }
 
 // 1D interfaces 0..nx, fused
@@ -1155,7 +1369,7 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
       const double t0 = id == 0 ? *g.t : 0.0;
       const long long n0 = id == 0 ? *g.steps : 0;
       if (dt > 0.0) {
-        const double ia = 1.0 / (g.geo.h * g.geo.k);
+        const double ia = 1.0 / (g.cv.area ? g.cv.area[(size_t)(j + 1) * (nx + 2) + (i + 1)] : g.geo.h * g.geo.k);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           W[v] += d[v] * ia;
@@ -1180,7 +1394,8 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
         atomicCAS(g.err, 0ull,
                   1ull + ((unsigned long long)(j + 1) << 32) + (unsigned long long)(i + 1) + (1ull << 63));
     }
-    bound = cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
+    bound = g.cv.wid ? cell_dt_bound_curv(W, Q.P, g.cv.wid[id], g.cv.wid[(size_t)nx * ny + id])
+                     : cell_dt_bound(W, Q.P, g.geo.h, g.geo.k);
   }
   reduce_dt_bound(bound, g.dtmin, (unsigned)id >> 6, g.dtmask);
 }
@@ -1245,13 +1460,15 @@ struct Problem {
   void* recd = nullptr;  // (unused: the interface kernel keeps its frame record in LDS)
   void* rect = nullptr;
   bool borrowed = false;  // W, FX, FY belong to the caller (gks_init_device)
+  void* geom = nullptr;   // curvilinear grids: CurvDev arrays (one allocation)
 };
 
 // problems of one dimension and precision, advanced by one launch sequence
 struct Group {
   int dim = 2;
   bool mixed = false;
-  bool chr = false;  // 2D reconstruction in characteristic variables
+  bool chr = false;   // 2D reconstruction in characteristic variables
+  bool curv = false;  // curvilinear grids
   std::vector<int> members;
   void* dprobs = nullptr;                  // device Prob<...>[members]
   uint32_t* owner[KK_COUNT] = {};          // device block-owner tables
@@ -1344,6 +1561,23 @@ std::string validate(const gks_problem& p) {
       return "step: the east and south boundaries must be mirror kinds (outflow, reflect, no-slip)";
   }
   if (p.precision != GKS_FP64 && p.precision != GKS_FP32_MIXED) return "unknown precision";
+  if (p.mesh) {
+    if (p.dim != 2) return "a curvilinear grid needs dim 2";
+    if (p.obstacle_nj != 0) return "a curvilinear grid takes no solid step";
+    if (p.recon_vars != 0) return "a curvilinear grid reconstructs in conservative variables (recon_vars 0)";
+    for (int s = 0; s < 4; ++s) {
+      const int k = p.bc[s].kind;
+      if (k != GKS_BC_PERIODIC && k != GKS_BC_OUTFLOW && k != GKS_BC_NOSLIP_ISOTHERMAL && k != GKS_BC_NOSLIP_ADIABATIC &&
+          k != GKS_BC_INFLOW)
+        return "curvilinear grid: boundaries must be periodic, outflow, no-slip or inflow";
+    }
+  }
+  for (int s = 0; s < (p.dim == 2 ? 4 : 2); ++s) {
+    const double w = p.bc[s].wall_omega;
+    if (!std::isfinite(w)) return "wall_omega must be finite";
+    if (w != 0.0 && (!p.mesh || (p.bc[s].kind != GKS_BC_NOSLIP_ISOTHERMAL && p.bc[s].kind != GKS_BC_NOSLIP_ADIABATIC)))
+      return "wall_omega is for the no-slip walls of a curvilinear grid";
+  }
   const int nsides = p.dim == 2 ? 4 : 2;
   for (int s = 0; s < nsides; ++s) {
     const int k = p.bc[s].kind;
@@ -1366,6 +1600,7 @@ void setup_problem(const gks_problem& s, Problem& p) {
     p.ix = Idx{s.nx, ny, px ? s.nx : s.nx + 1, py ? ny : ny + 1};
   }
   p.geo = Geo{s.x0, s.y0, (s.x1 - s.x0) / s.nx, s.dim == 2 ? (s.y1 - s.y0) / s.ny : 1.0};
+  if (s.mesh) p.geo = Geo{0.0, 0.0, 1.0, 1.0};  // logical coordinates
   Phys& P = p.phys;
   memset(&P, 0, sizeof(P));
   P.gamma = s.gamma;
@@ -1390,7 +1625,168 @@ void setup_problem(const gks_problem& s, Problem& p) {
     b.wu = s.bc[side].wall_u;
     b.wv = s.bc[side].wall_v;
     b.wT = s.bc[side].wall_T;
+    b.wo = s.bc[side].wall_omega;
   }
+}
+
+// Geometry of a curvilinear grid (the CurvDev arrays, concatenated): every
+// interface's frame and metric, the cell areas (edge ghosts: their image's),
+// the widths of the CFL condition and the boundary vertices.  "" or the
+// reason the grid is refused (a cell of nonpositive area, a centre on the
+// wrong side of an interface, periodic edges that are not one translation
+// apart, a non-finite coordinate).
+std::string curvilinear_geometry(const gks_problem& s, std::vector<double>& out) {
+  const int nx = s.nx, ny = s.ny;
+  auto V = [&](int j, int i, int c) { return s.mesh[((size_t)j * (nx + 1) + i) * 2 + c]; };
+  for (size_t q = 0; q < (size_t)(nx + 1) * (ny + 1) * 2; ++q)
+    if (!std::isfinite(s.mesh[q])) return "mesh: non-finite coordinate";
+  const size_t nfx = (size_t)ny * (nx + 1), nfy = (size_t)(ny + 1) * nx, nc = (size_t)nx * ny;
+  const size_t o_fy = kFaceGeo * nfx, o_area = o_fy + kFaceGeo * nfy, o_wid = o_area + (size_t)(nx + 2) * (ny + 2),
+               o_bnd = o_wid + 2 * nc;
+  out.assign(o_bnd + 4 * (size_t)(ny + 1) + 4 * (size_t)(nx + 1), 0.0);
+  std::vector<double> cx(nc), cy(nc), ar(nc);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)j * nx + i;
+      const double x0 = V(j, i, 0), y0 = V(j, i, 1), x1 = V(j, i + 1, 0), y1 = V(j, i + 1, 1);
+      const double x2 = V(j + 1, i + 1, 0), y2 = V(j + 1, i + 1, 1), x3 = V(j + 1, i, 0), y3 = V(j + 1, i, 1);
+      cx[c] = 0.25 * (x0 + x1 + x2 + x3);
+      cy[c] = 0.25 * (y0 + y1 + y2 + y3);
+      ar[c] = 0.5 * ((x2 - x0) * (y3 - y1) - (y2 - y0) * (x3 - x1));
+      if (!(ar[c] > 0.0)) return "mesh: cell (" + std::to_string(i) + ", " + std::to_string(j) + ") has no positive area";
+    }
+  // periodic edges: one translation apart
+  double per[2][2] = {{V(0, nx, 0) - V(0, 0, 0), V(0, nx, 1) - V(0, 0, 1)},
+                      {V(ny, 0, 0) - V(0, 0, 0), V(ny, 0, 1) - V(0, 0, 1)}};
+  double ext = 0.0;
+  for (size_t q = 0; q < (size_t)(nx + 1) * (ny + 1) * 2; ++q) ext = std::max(ext, std::fabs(s.mesh[q]));
+  if (s.bc[0].kind == GKS_BC_PERIODIC)
+    for (int j = 0; j <= ny; ++j)
+      if (std::fabs(V(j, nx, 0) - V(j, 0, 0) - per[0][0]) > 1e-12 * ext ||
+          std::fabs(V(j, nx, 1) - V(j, 0, 1) - per[0][1]) > 1e-12 * ext)
+        return "mesh: the periodic west and east edges are not one translation apart";
+  if (s.bc[2].kind == GKS_BC_PERIODIC)
+    for (int i = 0; i <= nx; ++i)
+      if (std::fabs(V(ny, i, 0) - V(0, i, 0) - per[1][0]) > 1e-12 * ext ||
+          std::fabs(V(ny, i, 1) - V(0, i, 1) - per[1][1]) > 1e-12 * ext)
+        return "mesh: the periodic south and north edges are not one translation apart";
+  // one interface: edge a -> b, cell centres c0 (lower index) and c1; the
+  // normal is the tangent turned clockwise (x interfaces) or anticlockwise
+  auto frame = [&](double* dst, size_t plane, size_t o, double ax, double ay, double bx, double by, bool xface,
+                   double c0x, double c0y, double c1x, double c1y) -> bool {
+    const double ex = bx - ax, ey = by - ay, L = std::sqrt(ex * ex + ey * ey);
+    const double tx = ex / L, ty = ey / L, nxv = xface ? ty : -ty, nyv = xface ? -tx : tx;
+    const double dx = c1x - c0x, dy = c1y - c0y, an = dx * nxv + dy * nyv, at = dx * tx + dy * ty;
+    if (!(L > 0.0) || !(an > 0.0)) return false;
+    const double f[kFaceGeo] = {nxv, nyv, tx, ty, L, 1.0 / an, -at / (an * L)};
+    for (int q = 0; q < kFaceGeo; ++q) dst[q * plane + o] = f[q];
+    return true;
+  };
+  // centre of the cell across a boundary interface: the periodic partner
+  // translated, else the mirror image of the inside centre (ix, iy) across
+  // the edge (a -> b)
+  auto across = [&](bool periodic, int pc, double sx, double sy, double ix, double iy, double ax, double ay, double bx,
+                    double by, double& ox, double& oy) {
+    if (periodic) {
+      ox = cx[pc] + sx;
+      oy = cy[pc] + sy;
+      return;
+    }
+    const double ex = bx - ax, ey = by - ay, L = std::sqrt(ex * ex + ey * ey), nxv = -ey / L, nyv = ex / L;
+    const double d = (ix - ax) * nxv + (iy - ay) * nyv;
+    ox = ix - 2.0 * d * nxv;
+    oy = iy - 2.0 * d * nyv;
+  };
+  for (int j = 0; j < ny; ++j)
+    for (int fi = 0; fi <= nx; ++fi) {
+      const double ax = V(j, fi, 0), ay = V(j, fi, 1), bx = V(j + 1, fi, 0), by = V(j + 1, fi, 1);
+      double c0x, c0y, c1x, c1y;
+      const bool pw = s.bc[0].kind == GKS_BC_PERIODIC, pe = s.bc[1].kind == GKS_BC_PERIODIC;
+      if (fi > 0) {
+        c0x = cx[(size_t)j * nx + fi - 1];
+        c0y = cy[(size_t)j * nx + fi - 1];
+      } else {
+        across(pw, j * nx + nx - 1, -per[0][0], -per[0][1], cx[(size_t)j * nx], cy[(size_t)j * nx], ax, ay, bx, by, c0x,
+               c0y);
+      }
+      if (fi < nx) {
+        c1x = cx[(size_t)j * nx + fi];
+        c1y = cy[(size_t)j * nx + fi];
+      } else {
+        across(pe, j * nx, per[0][0], per[0][1], cx[(size_t)j * nx + nx - 1], cy[(size_t)j * nx + nx - 1], ax, ay, bx,
+               by, c1x, c1y);
+      }
+      if (!frame(out.data(), nfx, (size_t)j * (nx + 1) + fi, ax, ay, bx, by, true, c0x, c0y, c1x, c1y))
+        return "mesh: x interface (" + std::to_string(fi) + ", " + std::to_string(j) + ") has its cells on one side";
+    }
+  for (int fj = 0; fj <= ny; ++fj)
+    for (int i = 0; i < nx; ++i) {
+      const double ax = V(fj, i, 0), ay = V(fj, i, 1), bx = V(fj, i + 1, 0), by = V(fj, i + 1, 1);
+      double c0x, c0y, c1x, c1y;
+      const bool ps = s.bc[2].kind == GKS_BC_PERIODIC, pn = s.bc[3].kind == GKS_BC_PERIODIC;
+      if (fj > 0) {
+        c0x = cx[(size_t)(fj - 1) * nx + i];
+        c0y = cy[(size_t)(fj - 1) * nx + i];
+      } else {
+        across(ps, (ny - 1) * nx + i, -per[1][0], -per[1][1], cx[i], cy[i], ax, ay, bx, by, c0x, c0y);
+      }
+      if (fj < ny) {
+        c1x = cx[(size_t)fj * nx + i];
+        c1y = cy[(size_t)fj * nx + i];
+      } else {
+        across(pn, i, per[1][0], per[1][1], cx[(size_t)(ny - 1) * nx + i], cy[(size_t)(ny - 1) * nx + i], ax, ay, bx,
+               by, c1x, c1y);
+      }
+      if (!frame(out.data() + o_fy, nfy, (size_t)fj * nx + i, ax, ay, bx, by, false, c0x, c0y, c1x, c1y))
+        return "mesh: y interface (" + std::to_string(i) + ", " + std::to_string(fj) + ") has its cells on one side";
+    }
+  // areas over cells -1..nx x -1..ny: an edge ghost takes its image's
+  auto image = [](int q, int n, bool plo, bool phi) {
+    if (q < 0) return plo ? q + n : -1 - q;
+    if (q >= n) return phi ? q - n : 2 * n - 1 - q;
+    return q;
+  };
+  for (int j = -1; j <= ny; ++j)
+    for (int i = -1; i <= nx; ++i) {
+      if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) continue;
+      const int ii = image(i, nx, s.bc[0].kind == GKS_BC_PERIODIC, s.bc[1].kind == GKS_BC_PERIODIC);
+      const int jj = image(j, ny, s.bc[2].kind == GKS_BC_PERIODIC, s.bc[3].kind == GKS_BC_PERIODIC);
+      out[o_area + (size_t)(j + 1) * (nx + 2) + (i + 1)] = ar[(size_t)jj * nx + ii];
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)j * nx + i;
+      const double lw = out[4 * nfx + (size_t)j * (nx + 1) + i], le = out[4 * nfx + (size_t)j * (nx + 1) + i + 1];
+      const double ls = out[o_fy + 4 * nfy + (size_t)j * nx + i], ln = out[o_fy + 4 * nfy + (size_t)(j + 1) * nx + i];
+      out[o_wid + c] = ar[c] / (0.5 * (lw + le));
+      out[o_wid + nc + c] = ar[c] / (0.5 * (ls + ln));
+    }
+  double* b = out.data() + o_bnd;
+  for (int j = 0; j <= ny; ++j)
+    for (int c = 0; c < 2; ++c) {
+      b[2 * j + c] = V(j, 0, c);
+      b[2 * (ny + 1) + 2 * j + c] = V(j, nx, c);
+    }
+  for (int i = 0; i <= nx; ++i)
+    for (int c = 0; c < 2; ++c) {
+      b[4 * (ny + 1) + 2 * i + c] = V(0, i, c);
+      b[4 * (ny + 1) + 2 * (nx + 1) + 2 * i + c] = V(ny, i, c);
+    }
+  return "";
+}
+
+// device CurvDev pointers into the geometry allocation of problem p
+CurvDev curv_pointers(const Problem& p) {
+  CurvDev c{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!p.geom) return c;
+  const size_t nx = p.ix.nx, ny = p.ix.ny;
+  const double* g = (const double*)p.geom;
+  c.fx = g;
+  c.fy = c.fx + kFaceGeo * ny * (nx + 1);
+  c.area = c.fy + kFaceGeo * (ny + 1) * nx;
+  c.wid = c.area + (nx + 2) * (ny + 2);
+  c.bnd = c.wid + 2 * nx * ny;
+  return c;
 }
 
 size_t cells_of(const Problem& p) { return p.spec.dim == 2 ? (size_t)p.ix.nx * p.ix.ny : (size_t)p.ix.nx; }
@@ -1482,6 +1878,7 @@ Grid<TS, TP> grid_of(Problem& p) {
   Grid<TS, TP> g;
   g.ix = p.ix;
   g.geo = p.geo;
+  g.cv = curv_pointers(p);
   g.W = (double*)p.W;
   g.FX = (TS*)p.FX;
   g.FY = (TS*)p.FY;
@@ -1589,7 +1986,7 @@ void collect(gks_handle* h) {
 // fixed step / end time array ctl.  h (may be null) records kernel timing.
 template <typename TS, typename TP, typename TC>
 void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const int (&bs)[KK_COUNT], int dim,
-                 bool chr, unsigned face_grid, const double* ctl, hipStream_t st) {
+                 bool chr, unsigned face_grid, const double* ctl, hipStream_t st, bool curv = false) {
   using PR = Prob<TS, TP, TC>;
   record_begin(h, st);
   if (dim == 2) {
@@ -1610,7 +2007,11 @@ void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const
   record_begin(h, st);
   if (dim == 2) {
     const size_t lds = bs[KK_FACE] * iface_lds_per_thread<TC>();
-    if (face_grid)
+    if (curv && face_grid)
+      k_iface_2d_loop<TS, TP, TC, true><<<face_grid, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
+    else if (curv)
+      k_iface_2d<TS, TP, TC, true><<<A[KK_FACE].nblk, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
+    else if (face_grid)
       k_iface_2d_loop<TS, TP, TC><<<face_grid, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
     else
       k_iface_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
@@ -1633,7 +2034,7 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   KA<PR> A[KK_COUNT];
   const int single = G.members.size() == 1;
   for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k], single};
-  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.dim == 2 ? G.face_grid : 0u, G.ctl, st);
+  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.dim == 2 ? G.face_grid : 0u, G.ctl, st, G.curv);
 }
 
 void enqueue_step(gks_handle* h, hipStream_t st) {
@@ -1722,9 +2123,11 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     return code;
   };
   h->probs.resize(n_problems);
+  std::vector<std::vector<double>> geoms(n_problems);
   for (int n = 0; n < n_problems; ++n) {
     const gks_problem& s = probs[n];
     std::string why = validate(s);
+    if (why.empty() && s.mesh) why = curvilinear_geometry(s, geoms[n]);
     const bool given = dev ? dcell[n] && dfx[n] && (s.dim == 1 || (dfy && dfy[n]))
                            : cell[n] && face_x[n] && (s.dim == 1 || (face_y && face_y[n]));
     if (why.empty() && !given) why = "null array";
@@ -1785,6 +2188,14 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
       }
       if (hipMemsetAsync(*bufs[b], 0, sizes[b], h->stream) != hipSuccess)
         return init_fail(GKS_EDEVICE, "hipMemsetAsync failed");
+    }
+    if (!geoms[n].empty()) {
+      if (hipMalloc(&p.geom, geoms[n].size() * 8) != hipSuccess) {
+        p.geom = nullptr;
+        return init_fail(GKS_ENOMEM, "device allocation failed");
+      }
+      if (hipMemcpy(p.geom, geoms[n].data(), geoms[n].size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return init_fail(GKS_EDEVICE, "upload failed");
     }
     // a periodic seam is one interface: its values are those of the first
     if (dev && s.dim == 2) {
@@ -1854,14 +2265,16 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     const Problem& p = h->probs[n];
     Group* G = nullptr;
     const bool chr = p.spec.dim == 2 && p.spec.recon_vars == 1;
+    const bool curv = p.geom != nullptr;
     for (Group& g : h->groups)
-      if (g.dim == p.spec.dim && g.mixed == p.mixed && g.chr == chr) G = &g;
+      if (g.dim == p.spec.dim && g.mixed == p.mixed && g.chr == chr && g.curv == curv) G = &g;
     if (!G) {
       h->groups.emplace_back();
       G = &h->groups.back();
       G->dim = p.spec.dim;
       G->mixed = p.mixed;
       G->chr = chr;
+      G->curv = curv;
     }
     G->members.push_back(n);
   }
@@ -2053,6 +2466,7 @@ int gks_step_noalloc(const gks_problem* prob, void* d_cell, void* d_face_x, void
     return GKS_EINVAL;
   }
   std::string why = validate(*prob);
+  if (why.empty() && prob->mesh) why = "curvilinear grids are stepped through a handle (gks_init, gks_init_device)";
   if (why.empty() && nsteps < 0) why = "nsteps < 0";
   if (why.empty() && !(dt_fixed >= 0.0 && std::isfinite(dt_fixed))) why = "dt_fixed must be >= 0 and finite";
   if (why.empty() && !(t_end >= 0.0 && std::isfinite(t_end))) why = "t_end must be >= 0 and finite";
@@ -2396,6 +2810,7 @@ int gks_destroy(gks_handle* h) {
       if (G.owner[k]) (void)hipFree(G.owner[k]);
   }
   for (Problem& p : h->probs) {
+    if (p.geom) (void)hipFree(p.geom);
     void* bufs[9] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal, p.recd, p.rect};
     for (int b = p.borrowed ? 3 : 0; b < 9; ++b)
       if (bufs[b]) (void)hipFree(bufs[b]);

@@ -409,11 +409,17 @@ __device__ __forceinline__ void side_targets_2d(int s, double hn, const Side& S,
 // around the interface.  Writes the record of g0 (state, tau, expansion
 // coefficients) and returns the leading flux (C1 g0 and C7 g_k terms) and the
 // leading point value U0.
-template <typename TC>
+// kCurv (an interface of a curvilinear grid): Ueq are the six averages in
+// the grid's logical orientation with frame momentum components; the
+// equilibrium quadratic is formed with unit spacing and turned into frame
+// derivatives with the metric Gm = (G_nn, G_ns, G_tt) (d/dn = G_nn d/dxi +
+// G_ns d/deta, d/dt = G_tt d/deta).
+template <typename TC, bool kCurv = false>
 __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, double hn, double hs,
                                                   const double (&Wc)[2][4], const double (&pc)[2][4][5],
                                                   const double (&Ueq)[2][3][4], const Rec<TC>& R, unsigned f,
-                                                  double (&flux)[4], double (&pv)[4]) {
+                                                  double (&flux)[4], double (&pv)[4],
+                                                  const double* Gm = nullptr) {
   const double g1 = P.gamma - 1.0;
   Side S[2];
   const bool okl = side_state_2d(P, 0, hn, hs, Wc[0], pc[0], S[0]);
@@ -446,12 +452,39 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   // equilibrium quadratic (Sec. 3.3) -> targets and coefficients of g0
   {
     const double ir = 1.0 / rho0;
+    TC b[5][4];
+    if constexpr (kCurv) {
+      double q[5][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double L0 = Ueq[0][0][v], L1 = Ueq[0][1][v], L2 = Ueq[0][2][v];
+        const double R0 = Ueq[1][0][v], R1 = Ueq[1][1][v], R2 = Ueq[1][2][v];
+        // logical derivatives (unit spacing)
+        const double lx = 0.25 * ((R2 - L2) + 2.0 * (R1 - L1) + (R0 - L0));
+        const double ly = 0.25 * (R2 - R0 + L2 - L0);
+        const double lxx = 0.125 * (26.0 * (R1 + L1) - (R2 + L2 + R0 + L0) - 48.0 * W0[v]);
+        const double lxy = 0.5 * (R2 - L2 - R0 + L0);
+        const double lyy = 0.5 * (R2 - 2.0 * R1 + R0 + L2 - 2.0 * L1 + L0);
+        const double g00 = Gm[0], g01 = Gm[1], g11 = Gm[2];
+        q[0][v] = (g00 * lx + g01 * ly) * ir;
+        q[1][v] = g11 * ly * ir;
+        q[2][v] = (g00 * g00 * lxx + 2.0 * g00 * g01 * lxy + g01 * g01 * lyy) * ir;
+        q[3][v] = g11 * (g00 * lxy + g01 * lyy) * ir;
+        q[4][v] = g11 * g11 * lyy * ir;
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        double bf[4];
+        to_frame_2d(q[k], U0, V0, bf);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b[k][v] = (TC)bf[v];
+      }
+    }
     // the divisors of the five derivatives (uniform over a launch)
     const Divisor qdiv[5] = {divisor(4.0 * hn), divisor(4.0 * hs), divisor(8.0 * hn * hn), divisor(2.0 * hn * hs),
                              divisor(2.0 * hs * hs)};
-    TC b[5][4];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < (kCurv ? 0 : 5); ++k) {
       double qd[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {

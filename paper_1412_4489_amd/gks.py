@@ -29,9 +29,13 @@ STATUS = {0: "GKS_OK", -1: "GKS_EINVAL", -2: "GKS_ENOMEM", -3: "GKS_EDEVICE", -4
           -5: "GKS_ESTATE"}
 
 
+_D = C.POINTER(C.c_double)
+
+
 class gks_bc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("state", C.c_double * 4), ("alt", C.c_double * 4),
-                ("wall_u", C.c_double), ("wall_v", C.c_double), ("wall_T", C.c_double)]
+                ("wall_u", C.c_double), ("wall_v", C.c_double), ("wall_T", C.c_double),
+                ("wall_omega", C.c_double)]
 
 
 class gks_problem(C.Structure):
@@ -42,7 +46,7 @@ class gks_problem(C.Structure):
                 ("cfl", C.c_double), ("weno_eps", C.c_double), ("weno_c", C.c_double),
                 ("recon_vars", C.c_int32), ("precision", C.c_int32), ("bc", gks_bc * 4),
                 ("t0", C.c_double), ("obstacle_i0", C.c_int32), ("obstacle_nj", C.c_int32),
-                ("admissibility", C.c_int32)]
+                ("admissibility", C.c_int32), ("mesh", _D)]
 
 
 class gks_noalloc_status(C.Structure):
@@ -57,7 +61,6 @@ class GKSError(RuntimeError):
 
 _lib = None
 _P = C.c_void_p
-_D = C.POINTER(C.c_double)
 
 
 def lib():
@@ -113,6 +116,14 @@ def to_c_problem(prob, precision=GKS_FP64, t0=0.0) -> gks_problem:
             P.bc[s].state[i] = bc.state[i]
             P.bc[s].alt[i] = bc.alt[i]
         P.bc[s].wall_u, P.bc[s].wall_v, P.bc[s].wall_T = bc.wall
+        P.bc[s].wall_omega = getattr(bc, "omega", 0.0)
+    mesh = getattr(prob, "mesh", None)
+    if mesh is not None:
+        m = np.ascontiguousarray(mesh, dtype=np.float64)
+        if m.shape != (prob.ny + 1, prob.nx + 1, 2):
+            raise ValueError(f"mesh must have shape {(prob.ny + 1, prob.nx + 1, 2)}, not {m.shape}")
+        P._mesh_keep = m  # read by the library during the call
+        P.mesh = m.ctypes.data_as(_D)
     return P
 
 
@@ -127,7 +138,8 @@ def gks_init(probs, states, precision=GKS_FP64, stream=None, t0=None):
     n = len(probs)
     t0 = [0.0] * n if t0 is None else list(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
     prec = [int(x) for x in np.broadcast_to(np.asarray(precision, dtype=np.int64), (n,))]
-    cp = (gks_problem * n)(*[to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)])
+    ps = [to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)]  # (their meshes stay alive for the call)
+    cp = (gks_problem * n)(*ps)
     keep = []
     cells, fxs, fys = (_D * n)(), (_D * n)(), (_D * n)()
     for k, (p, st) in enumerate(zip(probs, states)):
@@ -206,7 +218,8 @@ def gks_init_device(probs, d_cell, d_face_x, d_face_y, precision=GKS_FP64, strea
     n = len(probs)
     t0 = [0.0] * n if t0 is None else list(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
     prec = [int(x) for x in np.broadcast_to(np.asarray(precision, dtype=np.int64), (n,))]
-    cp = (gks_problem * n)(*[to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)])
+    ps = [to_c_problem(p, q, t) for p, q, t in zip(probs, prec, t0)]  # (their meshes stay alive for the call)
+    cp = (gks_problem * n)(*ps)
     for k, (p, q) in enumerate(zip(probs, prec)):
         ext = gks_state_extent(p, q)
         for x, elems, item, what in ((d_cell[k], ext[0], 8, "d_cell"), (d_face_x[k], ext[1], ext[3], "d_face_x"),

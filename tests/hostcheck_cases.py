@@ -52,6 +52,11 @@ CASES = {
     "sod_1d_char": lambda: W.sod_1d(24),
     "sod_1d_cons": lambda: W.sod_1d(24, recon_vars=0),
     "blast_1d": lambda: W.blast_1d(30),
+    # curvilinear grids
+    "curv_vortex_wavy": lambda: W.vortex_mapped(14, amp=0.04),
+    "curv_vortex_sheared": lambda: W.vortex_mapped(12, shear=0.3, angle=0.5),
+    "curv_polar_cavity": lambda: W.polar_cavity(12, re=50.0),
+    "curv_solid_rotation_ns": lambda: W.solid_rotation(6, viscous=True, mu=0.01),
 }
 
 
@@ -137,6 +142,24 @@ with gks.Solver(probs, states, precision=precs[:len(probs)]) as S:
             bad += not err < tol
             print(f"batch step {nstep} {k} {probs[k].name} rel_diff {err:.2e} {'ok' if err < tol else 'FAIL'}",
                   flush=True)
+# a curvilinear grid beside uniform ones in one handle (its own launches)
+mixed = [W.vortex_mapped(10, amp=0.05), W.smooth_periodic_2d(nx=9, ny=7, seed=4), W.polar_cavity(8, re=50.0)]
+probs, states = [m[0] for m in mixed], [m[1] for m in mixed]
+dts = [0.7 * O.dt(p, s) for p, s in mixed]
+refs = []
+for p, s, dt in zip(probs, states, dts):
+    r = s.copy()
+    O.step(p, r, dt, 0.0)
+    O.step(p, r, dt, dt)
+    refs.append(r)
+with gks.Solver(probs, states, precision=[gks.GKS_FP64, gks.GKS_FP32_MIXED, gks.GKS_FP64]) as S:
+    S.step(2, dt=dts)
+    for k in range(3):
+        got, t, n = S.fetch(k)
+        err = np.abs(got.cell - refs[k].cell).max() / np.abs(refs[k].cell).max()
+        tol = 1e-12 if k != 1 else 1e-6
+        bad += not err < tol
+        print(f"curvilinear batch {k} {probs[k].name} rel_diff {err:.2e} {'ok' if err < tol else 'FAIL'}", flush=True)
 print("batch ok", flush=True)
 # autotuned launch shapes: bitwise the same results, the state not advanced
 # (with a solid step: its image launch takes the boundary kernel's size)
