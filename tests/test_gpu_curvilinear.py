@@ -129,7 +129,6 @@ def test_polar_cavity_at_the_paper_resolution(G, oracle):
     prof = {}
     for form in ("fp64", "fp32_mixed"):
         with G.Solver(prob, st0, _prec(G, form)) as S:
-            t, before = 0.0, None
             t_last = prob.t_end - 1.0 / ui
             S.step(200000, t_end=t_last)
             mid, t, n1 = S.fetch()
@@ -149,8 +148,10 @@ def test_polar_cavity_at_the_paper_resolution(G, oracle):
               f"passage {change:.2e} U_i; mass drift {drift:.2e}", flush=True)
         print(f"  along theta = 0, r = {np.round(r[j0][::8], 3)}:\n  u_theta / U_i = {np.round(prof[form][0][::8], 4)}"
               f"\n  u_r / U_i = {np.round(prof[form][1][::8], 4)}", flush=True)
-        # the inner wall drags the gas round; the flow has settled
-        assert ut[j0][0] > 0.5 and change < 2e-2
+        # the inner wall drags the gas round; the flow has settled (the
+        # isothermal mirror-image walls are not mass-tight: the drift is
+        # reported)
+        assert ut[j0][0] / ui > 0.5 and change < 2e-2
     d = max(np.abs(prof["fp64"][0] - prof["fp32_mixed"][0]).max(), np.abs(prof["fp64"][1] - prof["fp32_mixed"][1]).max())
     print(f"polar cavity: FP32-mixed vs FP64 profiles along theta = 0 differ by {d:.2e} U_i", flush=True)
     assert d < 1e-3
