@@ -44,8 +44,10 @@ struct TimeWeights {
   double C[11];  // values at t = dt
 };
 
-__device__ __forceinline__ void time_weights(double tau, double dt, TimeWeights& w) {
-  const double E = tau > 0.0 ? exp(-dt / tau) : 0.0;
+__device__ __forceinline__ double decay(double tau, double dt) { return tau > 0.0 ? exp(-dt / tau) : 0.0; }
+
+// E = decay(tau, dt) = e^{-dt/tau}
+__device__ __forceinline__ void time_weights(double tau, double dt, double E, TimeWeights& w) {
   const double omE = 1.0 - E;
   const double t2 = tau * tau, t3 = t2 * tau, d2 = dt * dt;
   w.I[1] = dt - tau * omE;
@@ -82,16 +84,20 @@ struct Half {
   double M0, M1, M2, M3, h1;
 };
 
-__device__ __forceinline__ Half half_moments(double U, double lam, double sgn) {
+// the recurrence from <u^0> and h1
+__device__ __forceinline__ Half half_moments_from(double M0, double h1, double U, double lam) {
   Half m;
-  const double sl = sqrt(lam);
   const double th = 0.5 / lam;
-  m.M0 = 0.5 * erfc(-sgn * sl * U);
-  m.h1 = sgn * 0.5 * exp(-lam * U * U) / sqrt(kPi * lam);
+  m.M0 = M0;
+  m.h1 = h1;
   m.M1 = U * m.M0 + m.h1;
   m.M2 = U * m.M1 + th * m.M0;
   m.M3 = U * m.M2 + 2.0 * th * m.M1;
   return m;
+}
+__device__ __forceinline__ Half half_moments(double U, double lam, double sgn) {
+  const double sl = sqrt(lam);
+  return half_moments_from(0.5 * erfc(-sgn * sl * U), sgn * 0.5 * exp(-lam * U * U) / sqrt(kPi * lam), U, lam);
 }
 
 // Peculiar-frame transform of a moment target b (lab basis psi) for a
@@ -258,10 +264,12 @@ struct Acc {
 //                       coefficients of g0 (FP32-mixed); the record of g0;
 //   hydro     (TC)      the terms of eq. dis1 (FP64: after solving the
 //                       coefficients of g0 from the recorded targets);
-//   kinetic   (double)  the side's interface state, half-space moments and
-//                       targets again (from its cell, same arithmetic as in
-//                       the prologue), (TC) the coefficients of g_k and the
+//   kinetic   (double)  the side's interface state and targets again (from
+//                       its cell, same arithmetic as in the prologue), its
+//                       half-space moments from the prologue's <u^0> and h1
+//                       in the record, (TC) the coefficients of g_k and the
 //                       terms of eq. dis2 (once per side).
+// The later sections take e^{-dt/tau} from the record too.
 // The sums keep the order ((prologue + hydrodynamic) + side 0) + side 1.
 // The record is a structure of arrays over the threads of a block.
 // ---------------------------------------------------------------------------
@@ -272,7 +280,9 @@ enum RecD {  // double fields
   D_TAU,                    // collision time (the sections rebuild the time weights)
   D_E0, D_E1, D_E2, D_E3,  // time- and interface-integrated <psi f> (heat flux; Navier-Stokes only)
   D_RATE0, D_RATE1,        // each side's rate s (Knudsen reading; Navier-Stokes only; kinetic sections)
-  ND_REC = D_RATE1 + 1
+  D_DECAY,                  // e^{-dt/tau} (the time weights of the later sections)
+  D_HM0, D_HH1, D_HM1, D_HH2,  // each side's half-space <u^0> and h1 (its half-space moments, eq. compatibility2)
+  ND_REC = D_HH2 + 1
 };
 enum RecT {  // compute-type fields
   T_CG = 0  // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar frame; in double
@@ -429,6 +439,8 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const Half m = half_moments(S[s].U, S[s].lam, s == 0 ? 1.0 : -1.0);
+    R.D(D_HM0 + 2 * s, f) = m.M0;
+    R.D(D_HH1 + 2 * s, f) = m.h1;
     const double th = 0.5 / S[s].lam, rho = S[s].rho, V = S[s].V;
     const double e2 = V * V + (1.0 + P.K) * th;  // <v^2> + <xi^2>
     W0[0] += rho * m.M0;
@@ -528,7 +540,8 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   R.D(D_TAU, f) = tau;
   // leading terms: Euler flux of U0 (C1 g0) and free transport of the sides
   // (C7 g_k); only the two time integrals of the leading terms are needed here
-  const double E = tau > 0.0 ? exp(-dt / tau) : 0.0;
+  const double E = decay(tau, dt);
+  R.D(D_DECAY, f) = E;
   const double I7 = tau * (1.0 - E), I1 = dt - I7;
   const double FE[4] = {W0[1], W0[1] * U0 + p0, W0[1] * V0, U0 * (W0[3] + p0)};
 #pragma unroll
@@ -571,7 +584,7 @@ __device__ __forceinline__ void iface_hydro_2d(const Phys& P, double dt, double 
   TC w[13];
   {
     TimeWeights tw;
-    time_weights(R.D(D_TAU, f), dt, tw);
+    time_weights(R.D(D_TAU, f), dt, R.D(D_DECAY, f), tw);
     double hw[13];
     hydro_weights(tw, hs, hw);
 #pragma unroll
@@ -626,7 +639,7 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
   Side S;
   side_state_2d(P, s, hn, hs, Wc, pc, S);  // physical: the prologue checked it
   const double rho = S.rho, U = S.U, V = S.V, lam = S.lam;
-  const Half hm = half_moments(U, lam, s == 0 ? 1.0 : -1.0);
+  const Half hm = half_moments_from(R.D(D_HM0 + 2 * s, f), R.D(D_HH1 + 2 * s, f), U, lam);  // the prologue's
   TC th[5], kp[4], h[10];
   theta_powers(0.5 / lam, th);
   half_table(hm, U, lam, h);
@@ -654,7 +667,7 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
   {
     const double tau = R.D(D_TAU, f);
     TimeWeights tw;
-    time_weights(tau, dt, tw);
+    time_weights(tau, dt, R.D(D_DECAY, f), tw);
     // collision time of the Chapman-Enskog correction
     const double tb = P.viscous ? bracket_tau(tau, R.D(D_RATE0 + s, f)) : tau;
     double kw[12];
@@ -1075,7 +1088,7 @@ __device__ __forceinline__ bool iface_1d(const Phys& P, double dt, double h, con
   const double jump = fabs((pr[0] - pr[1]) / (pr[0] + pr[1]));
   const double tau = P.viscous ? P.mu / p0 + P.tau_c * jump * dt : (P.tau_eps + P.tau_c * jump) * dt;
   TimeWeights w;
-  time_weights(tau, dt, w);
+  time_weights(tau, dt, decay(tau, dt), w);
   const double tv = P.viscous ? tau : 0.0;
   TC kp[4];
 #pragma unroll
