@@ -20,7 +20,8 @@ steps bracketed by device synchronisation; value = cell-updates / second.
 
 Beside it: the same batch in the FP64 form and over a 200-step window; the
 256^2 vortex (Table 2) in both forms; the other full-size workloads of the
-paper (`configs`).
+paper (`configs`), among them curvilinear grids (the vortex on a waved
+512^2 grid, the polar cavity of Sec. 4.8).
 
 `roofline`: the dominant kernel is the interface kernel k_iface_2d; its
 algorithmic floating-point operations per launch (the operation count of
@@ -188,7 +189,9 @@ def config_rates(steps=20, warmup=3):
                      ("shock_vortex_801x401_characteristic", lambda: W.shock_vortex(801, 401)),
                      ("riemann2_400x400_characteristic", lambda: W.riemann_2d(2, n=400, recon_vars=1)),
                      ("forward_facing_step_240x80_characteristic", lambda: W.forward_facing_step(240, 80)),
-                     ("viscous_shock_tube_600x300_re1000", lambda: W.viscous_shock_tube(600, 300, re=1000.0))):
+                     ("viscous_shock_tube_600x300_re1000", lambda: W.viscous_shock_tube(600, 300, re=1000.0)),
+                     ("curvilinear_waved_vortex_512x512", lambda: W.vortex_mapped(512, amp=0.05)),
+                     ("curvilinear_polar_cavity_65x65_re350", lambda: W.polar_cavity(65, re=350.0))):
         prob, st = mk()
         out[name] = {}
         for fname, prec in (("fp32_mixed", gks.GKS_FP32_MIXED), ("fp64", gks.GKS_FP64)):

@@ -76,11 +76,36 @@ def test_transpose_symmetry(oracle):
     np.testing.assert_allclose(stt.fx[:, sw].transpose(0, 1, 3, 2), st.fy, rtol=1e-12, atol=1e-12)
 
 
+def table1_symbol_l1(n, alpha_l, t=2.0, amp=0.2):
+    """L1 error at time t of the density wave of Sec. 4.1 under the
+    semi-discrete scheme whose interface flux is alpha_l U^l + (1 - alpha_l)
+    U^r, U^l and U^r the interface values of the 3-cell parabolas of the two
+    neighbouring cells (the central polynomial U2 of Sec. 3.1): the Fourier
+    symbol of the finite-volume difference of those fluxes against the exact
+    translation.  alpha_l: the weight of the left state in the mass flux
+    (the half-space split of eq. compatibility2 linearised at rho = u = p = 1)."""
+    h = 2.0 / n
+    th = np.pi * h
+    z = np.exp(1j * th)
+    ul = (-1.0 / z + 5.0 + 2.0 * z) / 6.0
+    ur = (2.0 + 5.0 * z - z * z) / 6.0
+    lam = -(1.0 - 1.0 / z) * (alpha_l * ul + (1.0 - alpha_l) * ur) / h
+    avg = amp * np.sin(th / 2) / (th / 2)
+    return 2.0 / np.pi * avg * abs(np.exp((lam + 1j * np.pi) * t) - 1.0)
+
+
 def test_table1_advection_order(oracle):
-    """Sec. 4.1, Table 1: third order at CFL 0.2.  The printed L1 magnitudes
-    are about 14x below this reading's (the central polynomial dominates the
-    weights of Sec. 3.1 in smooth flow and its interface value error sets the
-    constant); the pin is the order and the decade-and-a-bit of the magnitude."""
+    """Sec. 4.1, Table 1: third order at CFL 0.2.  The magnitude is that of
+    the dissipation of the central polynomial's interface values (the weights
+    of Sec. 3.1 let U2 carry smooth flow): it lies between the semi-discrete
+    predictions with the density's half-space weight (alpha_l = 0.841) and
+    with the mass flux's linearised weight (0.962).  The printed magnitudes
+    are about 14x smaller and are not reproduced by any reading of the
+    weights (design notes, Sec. 2)."""
+    from math import erfc, exp, pi, sqrt
+    a_rho = 0.5 * erfc(-sqrt(0.5))                      # <1>_{u>0} at lambda = 1/2, U = 1
+    m = lambda r: r * (0.5 * erfc(-sqrt(r / 2)) + exp(-r / 2) / (2 * sqrt(pi * r / 2)))  # rho <u>_{u>0}
+    a_mass = (m(1 + 1e-6) - m(1 - 1e-6)) / 2e-6
     rows = {int(r[0]): float(r[1]) for r in _golden("table1_advection.txt")}
     errs = {}
     for n in (50, 100, 200):
@@ -93,7 +118,9 @@ def test_table1_advection_order(oracle):
     o2 = np.log2(errs[100][0] / errs[200][0])
     assert 2.7 < o1 < 3.3 and 2.7 < o2 < 3.3
     for n in (50, 100, 200):
-        assert rows[n] / 2 < errs[n][0] < rows[n] * 20
+        lo, hi = table1_symbol_l1(n, a_rho), table1_symbol_l1(n, a_mass)
+        print(n, errs[n][0], (lo, hi), "printed", rows[n])
+        assert lo < errs[n][0] < hi, (n, errs[n][0], lo, hi)
         # L2/L1 of a sine-shaped error is pi/(2 sqrt 2) (the printed table gives 1.11)
         assert 1.05 < errs[n][1] / errs[n][0] < 1.15
 
