@@ -112,7 +112,8 @@ def pmc_probe():
 def launch_forms(S, steps):
     """Interface kernel time per launch (HIP events) at the tuned block size
     in the one-block-per-tile form and in the persistent form (the tuner's
-    grid, else four waves per compute unit); the tuned shape is restored."""
+    grid, else four waves per compute unit), and the reconstruction's time in
+    row order and in LDS tiles; the tuned shapes are restored."""
     import torch
     from paper_1412_4489_amd import gks
     bs, grid = S.launch_shape("interface")
@@ -131,6 +132,22 @@ def launch_forms(S, steps):
         out[name] = {"threads": bs, "grid": g, "interface_ms": round(ms / max(n, 1), 5)}
     S.set_launch("interface", bs, grid)
     out["tuned"] = "persistent" if grid else "per_tile"
+    # the reconstruction in row order and in LDS tiles of 1, 2 and 4 rows
+    rbs, rrows = S.launch_shape("recon")
+    rec = {}
+    for rows in (0, 1, 2, 4):
+        S.set_launch("recon", rbs, rows)
+        S.step(2)
+        torch.cuda.synchronize()
+        gks.gks_profile(S.h, 1)
+        gks.gks_profile(S.h, 2)
+        S.step(steps)
+        torch.cuda.synchronize()
+        gks.gks_profile(S.h, 0)
+        ms, n = gks.gks_kernel_time(S.h, "recon")
+        rec[f"rows_{rows}" if rows else "row_order"] = round(ms / max(n, 1), 5)
+    S.set_launch("recon", rbs, rrows)
+    out["recon_ms"] = {"threads": rbs, **rec, "tuned": f"rows_{rrows}" if rrows else "row_order"}
     return out
 
 

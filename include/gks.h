@@ -303,14 +303,18 @@ int gks_block_size(gks_handle* h, int32_t kernel, int32_t* threads);
 
 /* Launch shape of kernel class `kernel` (GKS_K_GHOST, GKS_K_RECON,
  * GKS_K_INTERFACE or GKS_K_UPDATE; not part of the method): `threads` per
- * block (64, 128 or 256) and, for the 2D interface kernel only, the
- * persistent form: `grid` blocks (a multiple of 8 in [8, 65536]; the eight
+ * block (64, 128 or 256) and `grid`: for the 2D interface kernel, the
+ * persistent form, `grid` blocks (a multiple of 8 in [8, 65536]; the eight
  * XCDs get equal shares) that take the interface tiles in turn, each block
- * staying on its XCD's range of tiles; grid = 0 launches one block per tile
- * (the only value for the other classes).  gks_tune chooses the block sizes
- * as above and then keeps the persistent form, with as many blocks as fit on
- * the device at once, where it times faster.  Every shape gives bitwise the
- * same results.  gks_set_launch waits for the enqueued work and applies to
+ * staying on its XCD's range of tiles (0: one block per tile); for the 2D
+ * reconstruction, the rows of its LDS tiles (1, 2 or 4: a block takes
+ * threads / rows x rows cells and stages their averages and the one-cell
+ * ring around them in LDS first; 0: one thread per cell in row order
+ * reading the averages directly); 0 for the other classes.  gks_tune
+ * chooses the block sizes as above, then keeps the persistent interface form,
+ * with as many blocks as fit on the device at once, and the reconstruction
+ * tile rows where they time faster.  Every shape gives bitwise the same
+ * results.  gks_set_launch waits for the enqueued work and applies to
  * every problem of the handle; GKS_EINVAL for a bad value, GKS_ESTATE on a
  * handle in its error state.  gks_launch_shape reports the present shape of
  * a class (grid 0 where it is not persistent). */

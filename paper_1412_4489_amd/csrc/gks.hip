@@ -719,16 +719,12 @@ __device__ __forceinline__ void reduce_dt_bound(double b, unsigned long long* sl
 // ---------------------------------------------------------------------------
 
 // 2D: cells -1..nx x -1..ny except the four corners; kChar: the limiter of
-// each direction in that direction's characteristic variables
+// each direction in that direction's characteristic variables.  Wn: the
+// averages of the cell and its east, west, north, south neighbours.
 template <typename TS, typename TP, typename TC, bool kChar>
-__global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
-  int id;
-  const Prob<TS, TP, TC>& Q = locate(a, KK_RECON, id);
-  const Grid<TS, TP> g = Q.g;
+__device__ __forceinline__ void recon_cell_2d(const Prob<TS, TP, TC>& Q, const Grid<TS, TP>& g, int i, int j,
+                                              const double (&Wn)[5][4]) {
   const int nx = g.ix.nx, ny = g.ix.ny;
-  if (id >= (nx + 2) * (ny + 2)) return;
-  const int j = id / (nx + 2) - 1, i = id % (nx + 2) - 1;
-  if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
   // a curvilinear grid reconstructs in logical coordinates (h = k = 1) with
   // I(U1) = C |K|, the cell's area
   const double h = g.geo.h, k = g.geo.k, eps = Q.P.weno_eps, gamma = Q.P.gamma;
@@ -739,16 +735,6 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
   // made them (128 units, 2^-46); in single precision their storage rounding
   // (one unit, 2^-24), which exceeds that arithmetic noise
   constexpr double kTieRel = sizeof(TS) == 4 ? 5.9604644775390625e-08 : 1.4210854715202004e-14;
-  // the cell and its east, west, north, south neighbours
-  double Wn[5][4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    Wn[0][v] = g.W[x.w(v, j, i)];
-    Wn[1][v] = g.W[x.w(v, j, i + 1)];
-    Wn[2][v] = g.W[x.w(v, j, i - 1)];
-    Wn[3][v] = g.W[x.w(v, j + 1, i)];
-    Wn[4][v] = g.W[x.w(v, j - 1, i)];
-  }
   double p[4][5], Wc[4];
   const ReconDiv D(h, k);
   if constexpr (!kChar) {
@@ -805,6 +791,72 @@ __global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
     for (int m = 0; m < 5; ++m) g.PC[x.pc(v, m, j, i)] = ok ? (TP)p[v][m] : TP(0);
   // count of interior gas cells that fell back (rare: one atomic per such cell)
   if (!ok && i >= 0 && i < nx && j >= 0 && j < ny && !Q.solid(i, j) && *g.dt > 0.0) atomicAdd(g.nfall, 1ull);
+}
+
+// one thread per cell of the range, in row order
+template <typename TS, typename TP, typename TC, bool kChar>
+__global__ void __launch_bounds__(256) k_recon_2d(KA<Prob<TS, TP, TC>> a) {
+  int id;
+  const Prob<TS, TP, TC>& Q = locate(a, KK_RECON, id);
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx, ny = g.ix.ny;
+  if (id >= (nx + 2) * (ny + 2)) return;
+  const int j = id / (nx + 2) - 1, i = id % (nx + 2) - 1;
+  if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
+  const Idx& x = g.ix;
+  double Wn[5][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Wn[0][v] = g.W[x.w(v, j, i)];
+    Wn[1][v] = g.W[x.w(v, j, i + 1)];
+    Wn[2][v] = g.W[x.w(v, j, i - 1)];
+    Wn[3][v] = g.W[x.w(v, j + 1, i)];
+    Wn[4][v] = g.W[x.w(v, j - 1, i)];
+  }
+  recon_cell_2d<TS, TP, TC, kChar>(Q, g, i, j, Wn);
+}
+
+// Tiled form: a block takes a tile of tx x rows cells of the range (rows =
+// blockDim.x / tx) and first stages the averages of the tile and its
+// one-cell ring in LDS (the compact stencil's five averages per cell then
+// come from LDS; each average is read from memory once per tile); the
+// arithmetic is the row-order form's.  Every thread of the block takes part
+// in the staging and the barrier before it leaves.
+template <typename TS, typename TP, typename TC, bool kChar>
+__global__ void __launch_bounds__(256) k_recon_2d_tile(KA<Prob<TS, TP, TC>> a, int rows) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* sw = (double*)lds_raw;  // [4][rows + 2][tx + 2]
+  const unsigned L = logical_block(a.nblk);
+  const int p = a.single ? 0 : (int)a.owner[L];
+  const Prob<TS, TP, TC>& Q = a.probs[p];
+  const Grid<TS, TP> g = Q.g;
+  const int nx = g.ix.nx, ny = g.ix.ny;
+  const int tx = (int)blockDim.x / rows, ntx = (nx + 2 + tx - 1) / tx;
+  const int lb = (int)(L - Q.first[KK_RECON]);
+  const int i0 = (lb % ntx) * tx - 1, j0 = (lb / ntx) * rows - 1;  // first cell of the tile
+  const int sx = tx + 2, sy = rows + 2;
+  const Idx& x = g.ix;
+  // stage cells i0-1..i0+tx, j0-1..j0+rows (inside the ghosted array)
+  for (int q = threadIdx.x; q < 4 * sx * sy; q += blockDim.x) {
+    const int v = q / (sx * sy), r = q % (sx * sy), ci = i0 - 1 + r % sx, cj = j0 - 1 + r / sx;
+    if (ci >= -2 && ci <= nx + 1 && cj >= -2 && cj <= ny + 1) sw[q] = g.W[x.w(v, cj, ci)];
+  }
+  __syncthreads();
+  const int ti = (int)threadIdx.x % tx, tj = (int)threadIdx.x / tx, i = i0 + ti, j = j0 + tj;
+  if (i > nx || j > ny) return;
+  if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) return;
+  double Wn[5][4];
+  const int c = (tj + 1) * sx + (ti + 1);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* s = sw + v * sx * sy;
+    Wn[0][v] = s[c];
+    Wn[1][v] = s[c + 1];
+    Wn[2][v] = s[c - 1];
+    Wn[3][v] = s[c + sx];
+    Wn[4][v] = s[c - sx];
+  }
+  recon_cell_2d<TS, TP, TC, kChar>(Q, g, i, j, Wn);
 }
 
 // 1D: cells -1..nx, in conservative or characteristic variables (Sec. 4:
@@ -1476,6 +1528,7 @@ struct Group {
   unsigned cap[KK_COUNT] = {};             // allocated owner entries
   int bs[KK_COUNT] = {256, 256, 256, 256, 64};  // block size of each kind
   unsigned face_grid = 0;  // 2D interfaces: 0 one block per logical block, else a persistent grid of this many
+  int recon_rows = 0;      // 2D reconstruction: 0 row order, else LDS tiles of (block / rows) x rows cells
   double* ctl = nullptr;                   // device [members][2]: fixed step, end time
   std::vector<double> ctl_host;            // values last uploaded
 };
@@ -1852,13 +1905,19 @@ void state_elems(const gks_problem& s, size_t e[3]) {
 
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-// threads of one problem in a launch of kind k
-size_t work_items(const Problem& p, int dim, int k) {
+// threads of one problem in a launch of kind k (recon_rows > 0: the tiled
+// reconstruction with blocks of bs threads, whole tiles)
+size_t work_items(const Problem& p, int dim, int k, int recon_rows = 0, int bs = 256) {
   const size_t nx = p.ix.nx, ny = p.ix.ny;
   if (dim == 2) {
     switch (k) {
       case KK_GA: return 4 * ny + 4 * ny + 4 * (ny + 1) + 4 * (nx + 4) + 4 * nx + 4 * (nx + 1);
-      case KK_RECON: return (nx + 2) * (ny + 2);
+      case KK_RECON:
+        if (recon_rows > 0) {
+          const size_t tx = (size_t)bs / recon_rows;
+          return ((nx + 2 + tx - 1) / tx) * ((ny + 2 + recon_rows - 1) / recon_rows) * (size_t)bs;
+        }
+        return (nx + 2) * (ny + 2);
       case KK_FACE: return n_interfaces(p.ix);
       case KK_OBST: return p.spec.obstacle_nj > 0 ? step_items((int)nx, p.spec.obstacle_i0, p.spec.obstacle_nj) : 0;
       default: return nx * ny;
@@ -1920,7 +1979,7 @@ int build_tables(gks_handle* h, Group& G) {
   for (int k = 0; k < KK_COUNT; ++k) {
     for (size_t m = 0; m < n; ++m) {
       host[m].first[k] = (unsigned)own[k].size();
-      const unsigned nb = cdiv(work_items(h->probs[G.members[m]], G.dim, k), (size_t)G.bs[k]);
+      const unsigned nb = cdiv(work_items(h->probs[G.members[m]], G.dim, k, G.recon_rows, G.bs[k]), (size_t)G.bs[k]);
       own[k].insert(own[k].end(), nb, (uint32_t)m);
     }
     G.nblk[k] = (unsigned)own[k].size();
@@ -1986,7 +2045,8 @@ void collect(gks_handle* h) {
 // fixed step / end time array ctl.  h (may be null) records kernel timing.
 template <typename TS, typename TP, typename TC>
 void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const int (&bs)[KK_COUNT], int dim,
-                 bool chr, unsigned face_grid, const double* ctl, hipStream_t st, bool curv = false) {
+                 bool chr, unsigned face_grid, const double* ctl, hipStream_t st, bool curv = false,
+                 int recon_rows = 0) {
   using PR = Prob<TS, TP, TC>;
   record_begin(h, st);
   if (dim == 2) {
@@ -1997,7 +2057,12 @@ void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const
   }
   record_end(h, st, GKS_K_GHOST);  // includes the time step
   record_begin(h, st);
-  if (dim == 2 && chr)
+  const size_t rlds = recon_rows > 0 ? 4 * (size_t)(bs[KK_RECON] / recon_rows + 2) * (recon_rows + 2) * 8 : 0;
+  if (dim == 2 && recon_rows > 0 && chr)
+    k_recon_2d_tile<TS, TP, TC, true><<<A[KK_RECON].nblk, bs[KK_RECON], rlds, st>>>(A[KK_RECON], recon_rows);
+  else if (dim == 2 && recon_rows > 0)
+    k_recon_2d_tile<TS, TP, TC, false><<<A[KK_RECON].nblk, bs[KK_RECON], rlds, st>>>(A[KK_RECON], recon_rows);
+  else if (dim == 2 && chr)
     k_recon_2d<TS, TP, TC, true><<<A[KK_RECON].nblk, bs[KK_RECON], 0, st>>>(A[KK_RECON]);
   else if (dim == 2)
     k_recon_2d<TS, TP, TC, false><<<A[KK_RECON].nblk, bs[KK_RECON], 0, st>>>(A[KK_RECON]);
@@ -2034,7 +2099,8 @@ void enqueue_group(gks_handle* h, Group& G, hipStream_t st) {
   KA<PR> A[KK_COUNT];
   const int single = G.members.size() == 1;
   for (int k = 0; k < KK_COUNT; ++k) A[k] = KA<PR>{probs, G.owner[k], G.nblk[k], single};
-  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.dim == 2 ? G.face_grid : 0u, G.ctl, st, G.curv);
+  launch_step<TS, TP, TC>(h, A, G.bs, G.dim, G.chr, G.dim == 2 ? G.face_grid : 0u, G.ctl, st, G.curv,
+                          G.dim == 2 ? G.recon_rows : 0);
 }
 
 void enqueue_step(gks_handle* h, hipStream_t st) {
@@ -2720,7 +2786,10 @@ int gks_tune(gks_handle* h, int32_t steps) {
     collect(h);
     return restore();
   };
-  for (Group& G : h->groups) G.face_grid = 0;
+  for (Group& G : h->groups) {
+    G.face_grid = 0;
+    G.recon_rows = 0;
+  }
   for (int c = 0; c < 3 && rc == GKS_OK; ++c) {
     for (Group& G : h->groups) {
       for (int k = 0; k < KK_COUNT; ++k) G.bs[k] = cand[c];
@@ -2749,6 +2818,24 @@ int gks_tune(gks_handle* h, int32_t steps) {
     if (rc == GKS_OK) rc = time_steps();
     if (rc == GKS_OK && !(h->ktime[GKS_K_INTERFACE] < best_t[GKS_K_INTERFACE]))
       for (Group& G : h->groups) G.face_grid = 0;
+    // and the tiled reconstruction (averages staged in LDS) with 1, 2 or 4
+    // rows per tile at that block size
+    int best_rows = 0;
+    for (int rows = 1; rows <= 4 && rc == GKS_OK; rows *= 2) {
+      for (Group& G : h->groups) {
+        G.recon_rows = G.dim == 2 ? rows : 0;
+        if ((rc = build_tables(h, G)) != GKS_OK) break;
+      }
+      if (rc == GKS_OK && (rc = time_steps()) == GKS_OK && h->ktime[GKS_K_RECON] < best_t[GKS_K_RECON]) {
+        best_t[GKS_K_RECON] = h->ktime[GKS_K_RECON];
+        best_rows = rows;
+      }
+    }
+    for (Group& G : h->groups) {
+      if (rc != GKS_OK) break;
+      G.recon_rows = G.dim == 2 ? best_rows : 0;
+      rc = build_tables(h, G);
+    }
   }
   h->profiling = saved_prof;
   memcpy(h->ktime, saved_time, sizeof(saved_time));
@@ -2770,9 +2857,8 @@ int gks_launch_shape(gks_handle* h, int32_t kernel, int32_t* threads, int32_t* g
   if (!h || !threads || !grid || kernel < 0 || kernel >= GKS_K_COUNT) return GKS_EINVAL;
   int rc = gks_block_size(h, kernel, threads);
   *grid = 0;
-  if (kernel == GKS_K_INTERFACE)
-    for (const Group& G : h->groups)
-      if (G.dim == 2) *grid = (int32_t)G.face_grid;
+  for (const Group& G : h->groups)
+    if (G.dim == 2) *grid = kernel == GKS_K_INTERFACE ? (int32_t)G.face_grid : kernel == GKS_K_RECON ? G.recon_rows : 0;
   return rc;
 }
 
@@ -2782,7 +2868,9 @@ int gks_set_launch(gks_handle* h, int32_t kernel, int32_t threads, int32_t grid)
   if (kernel < 0 || kernel >= GKS_K_COUNT || kernel == GKS_K_DT)
     return fail(h, GKS_EINVAL, "no such kernel class");
   if (threads != 64 && threads != 128 && threads != 256) return fail(h, GKS_EINVAL, "threads must be 64, 128 or 256");
-  if (grid != 0 && (kernel != GKS_K_INTERFACE || grid < 8 || grid > 65536 || grid % 8))
+  if (kernel == GKS_K_RECON && grid != 0 && grid != 1 && grid != 2 && grid != 4)
+    return fail(h, GKS_EINVAL, "reconstruction tiles have 1, 2 or 4 rows (0: row order)");
+  if (kernel != GKS_K_RECON && grid != 0 && (kernel != GKS_K_INTERFACE || grid < 8 || grid > 65536 || grid % 8))
     return fail(h, GKS_EINVAL, "a persistent grid (a multiple of 8 in [8, 65536]) exists for the interface kernel only");
   HIP_OR(h, hipStreamSynchronize(h->stream));
   for (Group& G : h->groups) {
@@ -2791,6 +2879,7 @@ int gks_set_launch(gks_handle* h, int32_t kernel, int32_t threads, int32_t grid)
       if (cls[k] == kernel) G.bs[k] = threads;
     }
     if (kernel == GKS_K_INTERFACE) G.face_grid = G.dim == 2 ? (unsigned)grid : 0u;
+    if (kernel == GKS_K_RECON) G.recon_rows = G.dim == 2 ? grid : 0;
     int rc = build_tables(h, G);
     if (rc != GKS_OK) return rc;
   }

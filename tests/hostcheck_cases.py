@@ -186,6 +186,26 @@ with gks.Solver([q[0] for q in pair], [q[1] for q in pair],
 same = shape == (64, 8) and all(np.array_equal(a, b) for a, b in zip(outs[0], pers))
 bad += not same
 print(f"persistent interface launch {shape}: results {'identical' if same else 'DIFFER'}", flush=True)
+# the tiled reconstruction (averages staged in LDS): bitwise the row-order
+# form's results for 1, 2 and 4 rows at 64 and 256 threads, on uniform,
+# characteristic-variable, stepped and curvilinear grids of uneven sizes
+quad = [W.smooth_periodic_2d(nx=13, ny=11, seed=5), W.riemann_2d(2, n=9, recon_vars=1), W.forward_facing_step(30, 20),
+        W.polar_cavity(11, re=50.0)]
+precs4 = [gks.GKS_FP64, gks.GKS_FP32_MIXED, gks.GKS_FP64, gks.GKS_FP32_MIXED]
+base = None
+for bs, rows in ((64, 0), (64, 1), (64, 2), (64, 4), (256, 1), (256, 4)):
+    with gks.Solver([q[0] for q in quad], [q[1] for q in quad], precision=precs4) as S:
+        S.set_launch("recon", bs, rows)
+        shape = S.launch_shape("recon")
+        S.step(2, dt=[1e-3, 1e-4, 1e-3, 1e-3])
+        got = [S.fetch(k)[0] for k in range(4)]
+    if base is None:
+        base = got
+        continue
+    same = shape == (bs, rows) and all(np.array_equal(a.cell, b.cell) and np.array_equal(a.fx, b.fx)
+                                       and np.array_equal(a.fy, b.fy) for a, b in zip(got, base))
+    bad += not same
+    print(f"tiled reconstruction {shape}: results {'identical' if same else 'DIFFER'}", flush=True)
 # device-borrow form: the caller's buffers (emulated device memory) with NaN in
 # every ghost entry, stepped in place; bitwise the host-copy form's results
 import ctypes as C  # noqa: E402

@@ -33,3 +33,4 @@ def test_kernels_in_bounds_under_asan(tmp_path):
     assert "batch ok" in r.stdout
     assert "division ok" in r.stdout
     assert "persistent interface launch (64, 8): results identical" in r.stdout
+    assert r.stdout.count("tiled reconstruction") == 5 and "DIFFER" not in r.stdout
