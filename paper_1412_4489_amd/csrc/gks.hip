@@ -1250,7 +1250,9 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     section_boundary();
     const bool valid = R.D(D_RHO0, me) > 0.0;
     double Wc[4], pc[4][5];
-    if constexpr (kCurv) {
+    if constexpr (sides_in_record<TC>()) {
+      // the side's state and targets come from the record
+    } else if constexpr (kCurv) {
       double fr[kFaceGeo];
       face_geo(g, F, fr);
       load_face_cell_curv(g, F, side, fr, Wc, pc);

@@ -264,11 +264,13 @@ struct Acc {
 //                       coefficients of g0 (FP32-mixed); the record of g0;
 //   hydro     (TC)      the terms of eq. dis1 (FP64: after solving the
 //                       coefficients of g0 from the recorded targets);
-//   kinetic   (double)  the side's interface state and targets again (from
-//                       its cell, same arithmetic as in the prologue), its
-//                       half-space moments from the prologue's <u^0> and h1
-//                       in the record, (TC) the coefficients of g_k and the
-//                       terms of eq. dis2 (once per side).
+//   kinetic   (double)  the side's interface state and targets (single
+//                       precision: from the record, where the prologue put
+//                       them; double: again from its cell, same arithmetic
+//                       as in the prologue), its half-space moments from the
+//                       prologue's <u^0> and h1 in the record, (TC) the
+//                       coefficients of g_k and the terms of eq. dis2 (once
+//                       per side).
 // The later sections take e^{-dt/tau} from the record too.
 // The sums keep the order ((prologue + hydrodynamic) + side 0) + side 1.
 // The record is a structure of arrays over the threads of a block.
@@ -282,11 +284,13 @@ enum RecD {  // double fields
   D_RATE0, D_RATE1,        // each side's rate s (Knudsen reading; Navier-Stokes only; kinetic sections)
   D_DECAY,                  // e^{-dt/tau} (the time weights of the later sections)
   D_HM0, D_HH1, D_HM1, D_HH2,  // each side's half-space <u^0> and h1 (its half-space moments, eq. compatibility2)
-  ND_REC = D_HH2 + 1
+  D_SIDE,                   // single-precision compute type: each side's interface state rho, U, V, p, lambda (10)
+  ND_REC = D_SIDE + 10
 };
 enum RecT {  // compute-type fields
-  T_CG = 0  // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar frame; in double
-            // precision its targets bx, by, bxx, bxy, byy (5 x 4)
+  T_CG = 0,  // g0 coefficients ax, ay, A, dxx, dxy, dyy, bx, by, B (9 x 4), peculiar frame; in double
+             // precision its targets bx, by, bxx, bxy, byy (5 x 4)
+  T_SB = 36  // single precision: each side's expansion targets (2 x 5 x 4, peculiar frame)
 };
 
 // Where the coefficient systems of g0 are solved: in the prologue for a
@@ -297,10 +301,20 @@ template <typename TC>
 constexpr bool g0_solved_in_prologue() {
   return sizeof(TC) == 4;
 }
-// compute-type fields of the record: 36 coefficients or 20 targets
+// Whether the prologue hands each side's interface state and targets to its
+// kinetic section through the record (single-precision compute type: 240 B
+// more per thread still leave room in LDS for four waves per compute unit),
+// or the kinetic section reloads its cell and rebuilds them (double: the
+// record would halve the waves a compute unit holds).
+template <typename TC>
+constexpr bool sides_in_record() {
+  return sizeof(TC) == 4;
+}
+// compute-type fields of the record: 36 coefficients (+ 40 side targets) or
+// 20 targets
 template <typename TC>
 constexpr int nt_rec() {
-  return g0_solved_in_prologue<TC>() ? 36 : 20;
+  return g0_solved_in_prologue<TC>() ? (sides_in_record<TC>() ? 76 : 36) : 20;
 }
 
 // weights of the terms of eq. dis1 (hydro) and eq. dis2 (kinetic) from the
@@ -435,6 +449,22 @@ __device__ __forceinline__ bool iface_prologue_2d(const Phys& P, double dt, doub
   const bool okl = side_state_2d(P, 0, hn, hs, Wc[0], pc[0], S[0]);
   const bool okr = side_state_2d(P, 1, hn, hs, Wc[1], pc[1], S[1]);
   if (!okl || !okr) return false;
+  if constexpr (sides_in_record<TC>()) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      R.D(D_SIDE + 5 * s + 0, f) = S[s].rho;
+      R.D(D_SIDE + 5 * s + 1, f) = S[s].U;
+      R.D(D_SIDE + 5 * s + 2, f) = S[s].V;
+      R.D(D_SIDE + 5 * s + 3, f) = S[s].pr;
+      R.D(D_SIDE + 5 * s + 4, f) = S[s].lam;
+      TC b[5][4];
+      side_targets_2d(s, hn, S[s], pc[s], b);
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R.T(T_SB + 20 * s + 4 * k + v, f) = b[k][v];
+    }
+  }
   double W0[4] = {0, 0, 0, 0}, Fk[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -637,7 +667,15 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
                                                  unsigned f, double (&flux)[4], double (&pvm)[4], double (&pvp)[4],
                                                  double (&E)[4]) {
   Side S;
-  side_state_2d(P, s, hn, hs, Wc, pc, S);  // physical: the prologue checked it
+  if constexpr (sides_in_record<TC>()) {
+    S.rho = R.D(D_SIDE + 5 * s + 0, f);
+    S.U = R.D(D_SIDE + 5 * s + 1, f);
+    S.V = R.D(D_SIDE + 5 * s + 2, f);
+    S.pr = R.D(D_SIDE + 5 * s + 3, f);
+    S.lam = R.D(D_SIDE + 5 * s + 4, f);
+  } else {
+    side_state_2d(P, s, hn, hs, Wc, pc, S);  // physical: the prologue checked it
+  }
   const double rho = S.rho, U = S.U, V = S.V, lam = S.lam;
   const Half hm = half_moments_from(R.D(D_HM0 + 2 * s, f), R.D(D_HH1 + 2 * s, f), U, lam);  // the prologue's
   TC th[5], kp[4], h[10];
@@ -649,7 +687,14 @@ __device__ __forceinline__ void iface_kinetic_2d(const Phys& P, double dt, doubl
   Coefs<TC> c;
   {
     TC b[5][4];
-    side_targets_2d(s, hn, S, pc, b);
+    if constexpr (sides_in_record<TC>()) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b[k][v] = R.T(T_SB + 20 * s + 4 * k + v, f);
+    } else {
+      side_targets_2d(s, hn, S, pc, b);
+    }
     // the side's rate for the Knudsen reading from its first derivatives
     if (P.viscous) {
       const double cs = sqrt(P.gamma * S.pr / S.rho);

@@ -57,7 +57,7 @@ void one_interface(bool viscous, long long (&out)[3]) {
     for (int n = 0; n < 3; ++n)
       for (int v = 0; v < 4; ++v) Ueq[m][n][v] = Wc[m][v] * (1.0 + 0.002 * (n - 1));
   D recd[ND_REC];
-  TC rect[36];
+  TC rect[nt_rec<TC>()];
   Rec<TC> R{recd, rect, 1};
   D flux[4], pv[4], pvm[4], pvp[4], E[4];
   counts() = gks_opcount::Counts();
