@@ -931,8 +931,8 @@ __global__ void __launch_bounds__(256) k_recon_1d(KA<Prob<TS, TP, TC>> a) {
 
 // ---------------------------------------------------------------------------
 // 2D interfaces: one thread per interface, x interfaces first, then y
-// interfaces; three phase kernels (prologue, hydrodynamic part, kinetic part
-// of each side) communicating through the frame record R.
+// interfaces; one kernel whose sections (prologue, hydrodynamic part, kinetic
+// part of each side) hand the frame record of g0 on through LDS.
 // ---------------------------------------------------------------------------
 struct Face {
   bool isx;   // x interface (else y)
@@ -1511,8 +1511,6 @@ struct Problem {
   void* FLX = nullptr;
   void* FLY = nullptr;
   void* scal = nullptr;  // t, dt, steps, err, fallbacks, CFL slots (scal_bytes of the cells)
-  void* recd = nullptr;  // (unused: the interface kernel keeps its frame record in LDS)
-  void* rect = nullptr;
   bool borrowed = false;  // W, FX, FY belong to the caller (gks_init_device)
   void* geom = nullptr;   // curvilinear grids: CurvDev arrays (one allocation)
 };
@@ -1848,22 +1846,21 @@ size_t cells_of(const Problem& p) { return p.spec.dim == 2 ? (size_t)p.ix.nx * p
 
 size_t n_interfaces(const Idx& x) { return (size_t)x.fxr * x.ny + (size_t)x.nx * x.fyr; }
 
-// bytes of the buffers W, FX, FY, PC, FLX, FLY, scal, recd, rect of a problem
-void buffer_sizes(const Problem& p, size_t (&sizes)[9]) {
+// bytes of the buffers W, FX, FY, PC, FLX, FLY, scal of a problem
+constexpr int kBufs = 7;
+void buffer_sizes(const Problem& p, size_t (&sizes)[kBufs]) {
   const size_t ts = p.mixed ? sizeof(float) : sizeof(double);
   const Idx& x = p.ix;
   const size_t nx = x.nx, ny = x.ny;
   if (p.spec.dim == 2) {
-    const size_t sz[9] = {4 * (ny + 4) * (nx + 4) * 8,      2 * 4 * (ny + 2) * (nx + 3) * ts,
-                          2 * 4 * (ny + 3) * (nx + 2) * ts, 4 * 5 * (ny + 2) * (nx + 2) * ts,
-                          4 * ny * (nx + 1) * 8,            4 * (ny + 1) * nx * 8,
-                          scal_bytes(cells_of(p)),          0,
-                          0};
+    const size_t sz[kBufs] = {4 * (ny + 4) * (nx + 4) * 8,      2 * 4 * (ny + 2) * (nx + 3) * ts,
+                              2 * 4 * (ny + 3) * (nx + 2) * ts, 4 * 5 * (ny + 2) * (nx + 2) * ts,
+                              4 * ny * (nx + 1) * 8,            4 * (ny + 1) * nx * 8,
+                              scal_bytes(cells_of(p))};
     memcpy(sizes, sz, sizeof(sz));
   } else {
-    const size_t sz[9] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0,
-                          scal_bytes(cells_of(p)),
-                          0, 0};
+    const size_t sz[kBufs] = {3 * (nx + 4) * 8, 3 * (nx + 3) * ts, 0, 3 * 2 * (nx + 2) * ts, 3 * (nx + 1) * 8, 0,
+                              scal_bytes(cells_of(p))};
     memcpy(sizes, sz, sizeof(sz));
   }
 }
@@ -2239,8 +2236,8 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
     const size_t ts = p.mixed ? sizeof(float) : sizeof(double);
     const Idx& x = p.ix;
     const size_t nx = s.nx, ny = x.ny;
-    void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
-    size_t sizes[9];
+    void** bufs[kBufs] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal};
+    size_t sizes[kBufs];
     buffer_sizes(p, sizes);
     if (dev) {
       p.borrowed = true;
@@ -2248,7 +2245,7 @@ int init_handle(gks_handle** out, int32_t n_problems, const gks_problem* probs, 
       p.FX = dfx[n];
       p.FY = s.dim == 2 ? dfy[n] : nullptr;
     }
-    for (int b = 0; b < 9; ++b) {
+    for (int b = 0; b < kBufs; ++b) {
       if (!sizes[b] || (dev && b < 3)) continue;
       if (hipMalloc(bufs[b], sizes[b]) != hipSuccess) {
         *bufs[b] = nullptr;
@@ -2559,11 +2556,11 @@ int gks_step_noalloc(const gks_problem* prob, void* d_cell, void* d_face_x, void
   p.FX = d_face_x;
   p.FY = prob->dim == 2 ? d_face_y : nullptr;
   // the scratch layout: descriptor, controls, then the internal buffers
-  size_t sizes[9];
+  size_t sizes[kBufs];
   buffer_sizes(p, sizes);
   const size_t head = align256(sizeof(Prob<double, double, double>)) + 256;
   size_t need = head;
-  for (int b = 3; b < 9; ++b) need += align256(sizes[b]);
+  for (int b = 3; b < kBufs; ++b) need += align256(sizes[b]);
   if (need > kScratchBytes) {
     g_init_msg = "the problem needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
                  std::to_string(kScratchBytes);
@@ -2575,9 +2572,9 @@ int gks_step_noalloc(const gks_problem* prob, void* d_cell, void* d_face_x, void
     g_init_msg = why;
     return rc;
   }
-  void** bufs[9] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal, &p.recd, &p.rect};
+  void** bufs[kBufs] = {&p.W, &p.FX, &p.FY, &p.PC, &p.FLX, &p.FLY, &p.scal};
   size_t off = head;
-  for (int b = 3; b < 9; ++b) {
+  for (int b = 3; b < kBufs; ++b) {
     *bufs[b] = sizes[b] ? (char*)base + off : nullptr;
     off += align256(sizes[b]);
   }
@@ -2902,8 +2899,8 @@ int gks_destroy(gks_handle* h) {
   }
   for (Problem& p : h->probs) {
     if (p.geom) (void)hipFree(p.geom);
-    void* bufs[9] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal, p.recd, p.rect};
-    for (int b = p.borrowed ? 3 : 0; b < 9; ++b)
+    void* bufs[kBufs] = {p.W, p.FX, p.FY, p.PC, p.FLX, p.FLY, p.scal};
+    for (int b = p.borrowed ? 3 : 0; b < kBufs; ++b)
       if (bufs[b]) (void)hipFree(bufs[b]);
   }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
