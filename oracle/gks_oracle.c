@@ -1798,6 +1798,31 @@ static void from_face_frame(const double* fr, const double* F, double* o) {
 }
 
 static long g_last_fallbacks = 0;
+/* Reading (the paper's cavities and viscous shock tube have no-slip walls
+ * and print no wall condition beyond the ghost images): a no-slip wall is
+ * impermeable.  The interface on a no-slip domain edge passes no mass; the
+ * share of its momentum and energy fluxes that the (spurious) mass flux of
+ * the ghost-image evaluation carries, F_rho (U0, V0, h0) with the velocity
+ * and total enthalpy of the interface equilibrium U0, is removed with it;
+ * pressure, viscous stress and heat flux stay those of the interface
+ * distribution.  out->flux and out->W0 are in the interface frame. */
+static int noslip_edge(const orc_problem* P, int axis, int index) {
+  int n = axis == 0 ? P->nx : P->ny, side = axis * 2 + (index == 0 ? 0 : 1);
+  if (index != 0 && index != n) return 0;
+  int k = P->bc_kind[side];
+  return k == ORC_BC_NOSLIP_ISO || k == ORC_BC_NOSLIP_ADIA;
+}
+
+static void impermeable(const orc_problem* P, orc_face_output* o) {
+  const double* W0 = o->W0;
+  double rho = W0[0], u = W0[1] / rho, v = W0[2] / rho, p = pressure(2, P->gamma, W0), h = (W0[3] + p) / rho;
+  double m = o->flux[0];
+  o->flux[1] -= m * u;
+  o->flux[2] -= m * v;
+  o->flux[3] -= m * h;
+  o->flux[0] = 0.0;
+}
+
 /* every interface of a curvilinear grid (fluxes FLX / FLY and the new
  * Gauss-point values in the grid's (x, y) components) */
 static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt, double* fx, double* fy, double* FLX,
@@ -1832,6 +1857,7 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
+      if (noslip_edge(P, 0, fi)) impermeable(P, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -1870,6 +1896,7 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
+      if (noslip_edge(P, 1, fj)) impermeable(P, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -1962,6 +1989,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, fi - 1, j) != solid(P, fi, j)) wall_mirror(&in, solid(P, fi - 1, j) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
+      if (noslip_edge(P, 0, fi)) impermeable(P, &o);
       for (int v = 0; v < nv; ++v) {
         FLX[((size_t)v * ny + j) * (nx + 1) + fi] = o.flux[v];
         for (int g = 0; g < 2; ++g) fx[(((size_t)g * nv + v) * ny + j) * (nx + 1) + fi] = o.pv[g][v];
@@ -1994,6 +2022,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, i, fj - 1) != solid(P, i, fj)) wall_mirror(&in, solid(P, i, fj - 1) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
+      if (noslip_edge(P, 1, fj)) impermeable(P, &o);
       for (int v = 0; v < nv; ++v) {
         FLY[((size_t)v * (ny + 1) + fj) * nx + i] = o.flux[sw[v]];
         for (int g = 0; g < 2; ++g) fy[(((size_t)g * nv + v) * (ny + 1) + fj) * nx + i] = o.pv[g][sw[v]];

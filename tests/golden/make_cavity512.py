@@ -5,7 +5,7 @@ each step 0.8 times the initial CFL step.  Stored: that step, and the change
 of the cell averages from the initial state (mostly zero: the lid's
 disturbance has crossed a few dozen cells), compressed.
 
-    python tests/golden/make_cavity512.py     (about 5 minutes on 8 cores)
+    python tests/golden/make_cavity512.py     (about 20 minutes on 8 cores)
 
 Calls the oracle only."""
 import os

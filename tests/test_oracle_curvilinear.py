@@ -129,12 +129,9 @@ def test_polar_cavity_runs(oracle):
     th = np.arctan2(X[..., 1], X[..., 0])
     ut = (-np.sin(th) * c[1] + np.cos(th) * c[2]) / c[0]
     assert np.all(ut[2:-2, 0] > 0)
-    # the mirror-image walls are not mass-tight (as in the square cavity: an
-    # isothermal wall's image has the mirrored temperature 2 T_w - T, and the
-    # two half-space fluxes differ by the square roots of the temperatures);
-    # the impulsive start loses about 1e-3 of the mass in 150 steps here
+    # impermeable no-slip walls: the mass changes by rounding only
     m1 = float((st.cell[0] * _areas(p.mesh)).sum())
-    assert abs(m1 / m0 - 1) < 3e-3
+    assert abs(m1 / m0 - 1) < 1e-13
 
 
 def _areas(mesh):
