@@ -71,7 +71,12 @@ enum {
   GKS_BC_OUTFLOW = 1,             /* zero normal gradient (mirror image) */
   GKS_BC_REFLECT = 2,             /* slip wall: mirror image, normal momentum negated */
   GKS_BC_NOSLIP_ISOTHERMAL = 3,   /* ghost velocity 2 u_w - u, ghost temperature 2 T_w - T */
-  GKS_BC_NOSLIP_ADIABATIC = 4,    /* ghost velocity 2 u_w - u, temperature mirrored */
+  GKS_BC_NOSLIP_ADIABATIC = 4,    /* ghost velocity 2 u_w - u, temperature mirrored.
+                                     2D no-slip edges are impermeable: their interfaces pass
+                                     no mass, and the momentum and energy that the mass flux
+                                     of the ghost-image evaluation would carry (F_rho times the
+                                     velocity and total enthalpy of the interface equilibrium)
+                                     are removed with it */
   GKS_BC_INFLOW = 5,              /* fixed primitive state `state` */
   GKS_BC_DMR_BOTTOM = 6,          /* `state` for x < 1/6, slip wall beyond (Sec. 4.5) */
   GKS_BC_DMR_TOP = 7              /* `state` behind the Mach-10 shock line

@@ -1013,6 +1013,15 @@ __device__ __forceinline__ int wall_side(const PR& Q, const Face& F) {
   return s0 == s1 ? -1 : (s0 ? 0 : 1);
 }
 
+// interface F lies on a no-slip edge of the domain
+template <class PR>
+__device__ __forceinline__ bool noslip_edge(const PR& Q, const Face& F) {
+  const int n = F.isx ? Q.g.ix.nx : Q.g.ix.ny, q = F.isx ? F.b : F.a;
+  if (q != 0 && q != n) return false;
+  const int k = Q.bc[(F.isx ? 0 : 2) + (q == 0 ? 0 : 1)].kind;
+  return k == GKS_BC_NOSLIP_ISOTHERMAL || k == GKS_BC_NOSLIP_ADIABATIC;
+}
+
 // the image of a side across the interface, in the interface frame: the
 // normal momentum (component 1) and the odd orders in the normal
 // coordinate (p_n, p_ns) negated
@@ -1290,6 +1299,21 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     for (int v = 0; v < 4; ++v) Ed[v] = R.D(D_E0 + v, me);
     const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
     Fl[3] += P.prfix * qh;
+  }
+  // A no-slip domain edge is impermeable: its interface passes no mass, and
+  // the share of the momentum and energy fluxes that the mass flux of the
+  // ghost-image evaluation carries, F_rho (U0, V0, h0) with the velocity and
+  // total enthalpy of the interface equilibrium, goes with it (interface
+  // frame; pressure, stress and heat flux stay).
+  if (noslip_edge(Q, F) && R.D(D_RHO0, me) > 0.0) {
+    const double rho0 = R.D(D_RHO0, me), U0 = R.D(D_U0, me), V0 = R.D(D_V0, me), lam0 = R.D(D_LAM0, me);
+    const double p0 = 0.5 * rho0 / lam0;
+    const double h0 = (p0 / (P.gamma - 1.0) + 0.5 * rho0 * (U0 * U0 + V0 * V0) + p0) / rho0;
+    const double m = Fl[0];
+    Fl[1] -= m * U0;
+    Fl[2] -= m * V0;
+    Fl[3] -= m * h0;
+    Fl[0] = 0.0;
   }
   if constexpr (kCurv) {
     // frame momentum back to (x, y); the grid's own interface layouts
