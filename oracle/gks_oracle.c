@@ -1798,29 +1798,58 @@ static void from_face_frame(const double* fr, const double* F, double* o) {
 }
 
 static long g_last_fallbacks = 0;
-/* Reading (the paper's cavities and viscous shock tube have no-slip walls
- * and print no wall condition beyond the ghost images): a no-slip wall is
- * impermeable.  The interface on a no-slip domain edge passes no mass; the
- * share of its momentum and energy fluxes that the (spurious) mass flux of
- * the ghost-image evaluation carries, F_rho (U0, V0, h0) with the velocity
- * and total enthalpy of the interface equilibrium U0, is removed with it;
- * pressure, viscous stress and heat flux stay those of the interface
- * distribution.  out->flux and out->W0 are in the interface frame. */
-static int noslip_edge(const orc_problem* P, int axis, int index) {
+/* Readings of the domain-edge walls (the paper gives its walls as slip or
+ * no-slip and prints no wall treatment beyond the ghost images).
+ *
+ * A no-slip wall is impermeable.  The interface on a no-slip domain edge
+ * passes no mass; the share of its momentum and energy fluxes that the
+ * (spurious) mass flux of the ghost-image evaluation carries,
+ * F_rho (U0, V0, h0) with the velocity and total enthalpy of the interface
+ * equilibrium, is removed with it; pressure, viscous stress and heat flux
+ * stay those of the interface distribution.
+ *
+ * A slip wall is the symmetry line of its image pair: the normal momentum of
+ * the interface's new point values is zero and its flux carries normal
+ * momentum only (mass, tangential momentum and energy fluxes are odd under
+ * the mirror).  The ghost cell is reconstructed from its own stencil, which
+ * holds the wall's point values as they are; their odd part, left by
+ * rounding, is not mirrored there and can grow from step to step (it doubled
+ * each step at one wall interface of the viscous shock tube on 1000 x 500
+ * cells), so it is set to zero where the pair defines it to be.
+ *
+ * Both act on out->flux and out->pv in the interface frame (component 1
+ * normal).  kind: 1 slip, 2 no-slip, 0 neither; axis 0 / 1: an x / y
+ * interface at normal index `index`; `along`: the column of a y interface
+ * (the south edge of the double Mach reflection is a slip wall from the
+ * cell whose centre lies at x = 1/6 on). */
+static int wall_edge(const orc_problem* P, int axis, int index, int along) {
   int n = axis == 0 ? P->nx : P->ny, side = axis * 2 + (index == 0 ? 0 : 1);
   if (index != 0 && index != n) return 0;
   int k = P->bc_kind[side];
-  return k == ORC_BC_NOSLIP_ISO || k == ORC_BC_NOSLIP_ADIA;
+  if (k == ORC_BC_NOSLIP_ISO || k == ORC_BC_NOSLIP_ADIA) return 2;
+  if (k == ORC_BC_REFLECT) return 1;
+  if (k == ORC_BC_DMR_BOTTOM) {
+    double h = (P->x1 - P->x0) / P->nx, xc = P->x0 + (along + 0.5) * h;
+    return xc < 1.0 / 6.0 ? 0 : 1;
+  }
+  return 0;
 }
 
-static void impermeable(const orc_problem* P, orc_face_output* o) {
-  const double* W0 = o->W0;
-  double rho = W0[0], u = W0[1] / rho, v = W0[2] / rho, p = pressure(2, P->gamma, W0), h = (W0[3] + p) / rho;
-  double m = o->flux[0];
-  o->flux[1] -= m * u;
-  o->flux[2] -= m * v;
-  o->flux[3] -= m * h;
-  o->flux[0] = 0.0;
+static void wall_flux(const orc_problem* P, int kind, orc_face_output* o) {
+  if (kind == 2) {
+    const double* W0 = o->W0;
+    double rho = W0[0], u = W0[1] / rho, v = W0[2] / rho, p = pressure(2, P->gamma, W0), h = (W0[3] + p) / rho;
+    double m = o->flux[0];
+    o->flux[1] -= m * u;
+    o->flux[2] -= m * v;
+    o->flux[3] -= m * h;
+    o->flux[0] = 0.0;
+  } else if (kind == 1) {
+    int nv = P->dim + 2;
+    for (int v = 0; v < nv; ++v)
+      if (v != 1) o->flux[v] = 0.0;
+    o->pv[0][1] = o->pv[1][1] = 0.0;
+  }
 }
 
 /* every interface of a curvilinear grid (fluxes FLX / FLY and the new
@@ -1857,7 +1886,7 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      if (noslip_edge(P, 0, fi)) impermeable(P, &o);
+      wall_flux(P, wall_edge(P, 0, fi, 0) == 2 ? 2 : 0, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -1896,7 +1925,7 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      if (noslip_edge(P, 1, fj)) impermeable(P, &o);
+      wall_flux(P, wall_edge(P, 1, fj, i) == 2 ? 2 : 0, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -1989,7 +2018,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, fi - 1, j) != solid(P, fi, j)) wall_mirror(&in, solid(P, fi - 1, j) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      if (noslip_edge(P, 0, fi)) impermeable(P, &o);
+      wall_flux(P, wall_edge(P, 0, fi, 0), &o);
       for (int v = 0; v < nv; ++v) {
         FLX[((size_t)v * ny + j) * (nx + 1) + fi] = o.flux[v];
         for (int g = 0; g < 2; ++g) fx[(((size_t)g * nv + v) * ny + j) * (nx + 1) + fi] = o.pv[g][v];
@@ -2022,7 +2051,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, i, fj - 1) != solid(P, i, fj)) wall_mirror(&in, solid(P, i, fj - 1) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      if (noslip_edge(P, 1, fj)) impermeable(P, &o);
+      wall_flux(P, wall_edge(P, 1, fj, i), &o);
       for (int v = 0; v < nv; ++v) {
         FLY[((size_t)v * (ny + 1) + fj) * nx + i] = o.flux[sw[v]];
         for (int g = 0; g < 2; ++g) fy[(((size_t)g * nv + v) * (ny + 1) + fj) * nx + i] = o.pv[g][sw[v]];
@@ -2212,6 +2241,7 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
       for (int v = 0; v < nv; ++v) in.Ueq[m][1][v] = W1(v, fi - 1 + m);
     orc_face_output o;
     if (orc_face(P, &in, dt, &o)) status |= 1;
+    if ((fi == 0 || fi == nx) && P->bc_kind[fi == 0 ? 0 : 1] == ORC_BC_REFLECT) wall_flux(P, 1, &o);
     for (int v = 0; v < nv; ++v) {
       FL[(size_t)v * (nx + 1) + fi] = o.flux[v];
       fx[(size_t)v * (nx + 1) + fi] = o.pv[0][v];

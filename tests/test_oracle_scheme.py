@@ -627,3 +627,25 @@ def test_noslip_walls_pass_no_mass(oracle, kind):
     oracle.run(prob, st, nsteps=400)
     assert abs(st.cell[0].sum() / m0 - 1.0) < 1e-13
     assert abs(st.cell[3].sum() / e0 - 1.0) > 1e-8 and np.abs(st.cell[1]).max() > 1e-3
+
+
+def test_slip_wall_is_a_symmetry_line(oracle):
+    """A slip wall (reading of the symmetry line of the viscous shock tube,
+    Sec. 4.7, and of the reflecting walls of Sec. 4.5 and 4.6): its
+    interfaces pass normal momentum only and their new point values carry no
+    normal momentum, so that the ghost cell stays the mirror image of the
+    cell inside.  The viscous shock tube on 40 x 20 cells over 300 steps
+    keeps its mass to rounding behind its three no-slip walls and its
+    symmetry line, and the point values on the symmetry line have zero
+    normal momentum."""
+    prob, st = W.viscous_shock_tube(40, 20, re=200.0)
+    m0 = st.cell[0].sum()
+    dt = 0.5 * oracle.dt(prob, st)
+    for n in range(300):
+        fxf, fyf = oracle.step(prob, st, dt, n * dt)
+    assert abs(st.cell[0].sum() / m0 - 1.0) < 1e-13
+    top = fyf[:, -1, :]
+    assert np.all(top[0] == 0.0) and np.all(top[1] == 0.0) and np.all(top[3] == 0.0)
+    assert np.all(top[2] > 0.0)  # the pressure
+    assert np.all(st.fy[:, 2, -1, :] == 0.0)
+    assert np.abs(st.fy[:, 2, -2, :]).max() > 1e-6  # (not zero inside)
