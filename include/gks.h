@@ -69,7 +69,11 @@ enum {
 enum {
   GKS_BC_PERIODIC = 0,
   GKS_BC_OUTFLOW = 1,             /* zero normal gradient (mirror image) */
-  GKS_BC_REFLECT = 2,             /* slip wall: mirror image, normal momentum negated */
+  GKS_BC_REFLECT = 2,             /* slip wall: mirror image, normal momentum negated; its
+                                     interfaces pass normal momentum only and their new point
+                                     values carry no normal momentum (the symmetry line of the
+                                     image pair; the south edge of GKS_BC_DMR_BOTTOM likewise
+                                     where it mirrors) */
   GKS_BC_NOSLIP_ISOTHERMAL = 3,   /* ghost velocity 2 u_w - u, ghost temperature 2 T_w - T */
   GKS_BC_NOSLIP_ADIABATIC = 4,    /* ghost velocity 2 u_w - u, temperature mirrored.
                                      2D no-slip edges are impermeable: their interfaces pass

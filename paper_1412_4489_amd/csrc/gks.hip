@@ -1013,13 +1013,18 @@ __device__ __forceinline__ int wall_side(const PR& Q, const Face& F) {
   return s0 == s1 ? -1 : (s0 ? 0 : 1);
 }
 
-// interface F lies on a no-slip edge of the domain
+// the wall an interface F on the domain edge is: 1 a slip wall (the south
+// edge of the double Mach reflection from the cell whose centre lies at
+// x = 1/6 on), 2 a no-slip wall, 0 none
 template <class PR>
-__device__ __forceinline__ bool noslip_edge(const PR& Q, const Face& F) {
+__device__ __forceinline__ int wall_edge(const PR& Q, const Face& F) {
   const int n = F.isx ? Q.g.ix.nx : Q.g.ix.ny, q = F.isx ? F.b : F.a;
-  if (q != 0 && q != n) return false;
+  if (q != 0 && q != n) return 0;
   const int k = Q.bc[(F.isx ? 0 : 2) + (q == 0 ? 0 : 1)].kind;
-  return k == GKS_BC_NOSLIP_ISOTHERMAL || k == GKS_BC_NOSLIP_ADIABATIC;
+  if (k == GKS_BC_NOSLIP_ISOTHERMAL || k == GKS_BC_NOSLIP_ADIABATIC) return 2;
+  if (k == GKS_BC_REFLECT) return 1;
+  if (k == GKS_BC_DMR_BOTTOM) return Q.g.geo.x0 + (F.b + 0.5) * Q.g.geo.h < 1.0 / 6.0 ? 0 : 1;
+  return 0;
 }
 
 // the image of a side across the interface, in the interface frame: the
@@ -1300,12 +1305,21 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
     Fl[3] += P.prfix * qh;
   }
-  // A no-slip domain edge is impermeable: its interface passes no mass, and
-  // the share of the momentum and energy fluxes that the mass flux of the
-  // ghost-image evaluation carries, F_rho (U0, V0, h0) with the velocity and
-  // total enthalpy of the interface equilibrium, goes with it (interface
-  // frame; pressure, stress and heat flux stay).
-  if (noslip_edge(Q, F) && R.D(D_RHO0, me) > 0.0) {
+  // Domain-edge walls (interface frame).  A no-slip wall is impermeable: its
+  // interface passes no mass, and the share of the momentum and energy
+  // fluxes that the mass flux of the ghost-image evaluation carries,
+  // F_rho (U0, V0, h0) with the velocity and total enthalpy of the interface
+  // equilibrium, goes with it (pressure, stress and heat flux stay).  A slip
+  // wall is the symmetry line of its image pair: normal momentum flux only,
+  // and new point values without normal momentum (the ghost cell's own
+  // reconstruction holds the wall's point values unmirrored, so an odd part
+  // left there by rounding would not cancel and can grow from step to step).
+  const int wall = wall_edge(Q, F);
+  if (wall == 1) {
+    Fl[0] = Fl[2] = Fl[3] = 0.0;
+    Pm[1] = Pp[1] = 0.0;
+  }
+  if (wall == 2 && R.D(D_RHO0, me) > 0.0) {
     const double rho0 = R.D(D_RHO0, me), U0 = R.D(D_U0, me), V0 = R.D(D_V0, me), lam0 = R.D(D_LAM0, me);
     const double p0 = 0.5 * rho0 / lam0;
     const double h0 = (p0 / (P.gamma - 1.0) + 0.5 * rho0 * (U0 * U0 + V0 * V0) + p0) / rho0;
@@ -1401,6 +1415,12 @@ __global__ void __launch_bounds__(256) k_face_1d(KA<Prob<TS, TP, TC>> a) {
     atomicCAS(g.err, 0ull, 1ull + (1ull << 32) + (unsigned long long)(fi + 1));
 #pragma unroll
     for (int v = 0; v < 3; ++v) flux[v] = pv[v] = 0.0;
+  }
+  // a slip wall at the domain's end: the symmetry line of its image pair
+  // (momentum flux only, a new point value at rest)
+  if ((fi == 0 || fi == nx) && Q.bc[fi == 0 ? 0 : 1].kind == GKS_BC_REFLECT) {
+    flux[0] = flux[2] = 0.0;
+    pv[1] = 0.0;
   }
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
