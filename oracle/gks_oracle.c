@@ -1799,29 +1799,30 @@ static void from_face_frame(const double* fr, const double* F, double* o) {
 
 static long g_last_fallbacks = 0;
 /* Readings of the domain-edge walls (the paper gives its walls as slip or
- * no-slip and prints no wall treatment beyond the ghost images).
+ * no-slip and prints no wall treatment beyond the ghost images); both act on
+ * the interface fluxes and point values of the step, in the grid's
+ * components, before the update.
  *
- * A no-slip wall is impermeable.  The interface on a no-slip domain edge
- * passes no mass; the share of its momentum and energy fluxes that the
- * (spurious) mass flux of the ghost-image evaluation carries,
- * F_rho (U0, V0, h0) with the velocity and total enthalpy of the interface
- * equilibrium, is removed with it; pressure, viscous stress and heat flux
- * stay those of the interface distribution.
+ * A no-slip wall is impermeable.  Its interface passes no mass, and the
+ * (spurious) mass flux F_rho of the ghost-image evaluation takes with it the
+ * momentum and energy it would carry at the velocity and total enthalpy of
+ * the cell beside the wall (its average at the start of the step):
+ * F_rho (u_c, v_c, h_c) is removed from the momentum and energy fluxes;
+ * pressure, viscous stress and heat flux stay.
  *
- * A slip wall is the symmetry line of its image pair: the normal momentum of
- * the interface's new point values is zero and its flux carries normal
- * momentum only (mass, tangential momentum and energy fluxes are odd under
- * the mirror).  The ghost cell is reconstructed from its own stencil, which
- * holds the wall's point values as they are; their odd part, left by
- * rounding, is not mirrored there and can grow from step to step (it doubled
- * each step at one wall interface of the viscous shock tube on 1000 x 500
- * cells), so it is set to zero where the pair defines it to be.
+ * A slip wall is the symmetry line of its image pair: its interface passes
+ * normal momentum only (the mass, tangential momentum and energy fluxes are
+ * odd under the mirror) and its new point values carry no normal momentum.
+ * The ghost cell is reconstructed from its own stencil, which holds the
+ * wall's point values as they are; their odd part, left by rounding, is not
+ * mirrored there and can grow from step to step (it doubled each step at
+ * one wall interface of the viscous shock tube on 1000 x 500 cells), so it
+ * is set to zero where the pair defines it to be.
  *
- * Both act on out->flux and out->pv in the interface frame (component 1
- * normal).  kind: 1 slip, 2 no-slip, 0 neither; axis 0 / 1: an x / y
- * interface at normal index `index`; `along`: the column of a y interface
- * (the south edge of the double Mach reflection is a slip wall from the
- * cell whose centre lies at x = 1/6 on). */
+ * wall_edge: 1 slip, 2 no-slip, 0 neither, for the interface at normal index
+ * `index` of axis 0 (x) / 1 (y); `along`: the column of a y interface (the
+ * south edge of the double Mach reflection is a slip wall from the cell
+ * whose centre lies at x = 1/6 on). */
 static int wall_edge(const orc_problem* P, int axis, int index, int along) {
   int n = axis == 0 ? P->nx : P->ny, side = axis * 2 + (index == 0 ? 0 : 1);
   if (index != 0 && index != n) return 0;
@@ -1835,21 +1836,59 @@ static int wall_edge(const orc_problem* P, int axis, int index, int along) {
   return 0;
 }
 
-static void wall_flux(const orc_problem* P, int kind, orc_face_output* o) {
+/* one wall interface: F[v] = its flux components (stride fs), pv[g][v] its
+ * point values (Gauss point stride gs, component stride vs), Wc the average
+ * of the cell beside it, axis its normal */
+static void wall_interface(const orc_problem* P, int kind, int axis, const double* Wc, double* F, size_t fs,
+                           double* pv, size_t gs, size_t vs) {
   if (kind == 2) {
-    const double* W0 = o->W0;
-    double rho = W0[0], u = W0[1] / rho, v = W0[2] / rho, p = pressure(2, P->gamma, W0), h = (W0[3] + p) / rho;
-    double m = o->flux[0];
-    o->flux[1] -= m * u;
-    o->flux[2] -= m * v;
-    o->flux[3] -= m * h;
-    o->flux[0] = 0.0;
+    double rho = Wc[0], u = Wc[1] / rho, v = Wc[2] / rho, p = pressure(2, P->gamma, Wc), h = (Wc[3] + p) / rho;
+    double m = F[0];
+    F[fs] -= m * u;
+    F[2 * fs] -= m * v;
+    F[3 * fs] -= m * h;
+    F[0] = 0.0;
   } else if (kind == 1) {
-    int nv = P->dim + 2;
-    for (int v = 0; v < nv; ++v)
-      if (v != 1) o->flux[v] = 0.0;
-    o->pv[0][1] = o->pv[1][1] = 0.0;
+    int cn = 1 + axis, ct = 2 - axis;
+    F[0] = 0.0;
+    F[ct * fs] = 0.0;
+    F[3 * fs] = 0.0;
+    pv[cn * vs] = 0.0;
+    pv[gs + cn * vs] = 0.0;
   }
+}
+
+/* every domain-edge wall interface of a 2D step (gas cells beside it) */
+static void walls_2d(const orc_problem* P, const double* cell, double* FLX, double* FLY, double* fx, double* fy) {
+  int nx = P->nx, ny = P->ny, nv = 4;
+  double Wc[4];
+  for (int e = 0; e < 2; ++e) {
+    int fi = e == 0 ? 0 : nx, ic = e == 0 ? 0 : nx - 1;
+    for (int j = 0; j < ny; ++j) {
+      int kind = wall_edge(P, 0, fi, 0);
+      if (!kind || solid(P, ic, j)) continue;
+      for (int v = 0; v < nv; ++v) Wc[v] = cell[((size_t)v * ny + j) * nx + ic];
+      wall_interface(P, kind, 0, Wc, &FLX[(size_t)j * (nx + 1) + fi], (size_t)ny * (nx + 1),
+                     &fx[(size_t)j * (nx + 1) + fi], (size_t)nv * ny * (nx + 1), (size_t)ny * (nx + 1));
+    }
+  }
+  for (int e = 0; e < 2; ++e) {
+    int fj = e == 0 ? 0 : ny, jc = e == 0 ? 0 : ny - 1;
+    for (int i = 0; i < nx; ++i) {
+      int kind = wall_edge(P, 1, fj, i);
+      if (!kind || solid(P, i, jc)) continue;
+      for (int v = 0; v < nv; ++v) Wc[v] = cell[((size_t)v * ny + jc) * nx + i];
+      wall_interface(P, kind, 1, Wc, &FLY[(size_t)fj * nx + i], (size_t)(ny + 1) * nx,
+                     &fy[(size_t)fj * nx + i], (size_t)nv * (ny + 1) * nx, (size_t)(ny + 1) * nx);
+    }
+  }
+}
+
+/* 1D: a slip wall at either end (the same symmetry line) */
+static void wall_1d(double* F, double* pv) {
+  F[0] = 0.0;
+  F[2] = 0.0;
+  pv[1] = 0.0;
 }
 
 /* every interface of a curvilinear grid (fluxes FLX / FLY and the new
@@ -1886,7 +1925,6 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      wall_flux(P, wall_edge(P, 0, fi, 0) == 2 ? 2 : 0, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -1925,7 +1963,6 @@ static int curv_faces(const orc_problem* P, grid2* G, const cgeom* cg, double dt
         }
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      wall_flux(P, wall_edge(P, 1, fj, i) == 2 ? 2 : 0, &o);
       double F[4], pg[2][4];
       from_face_frame(fr, o.flux, F);
       from_face_frame(fr, o.pv[0], pg[0]);
@@ -2018,7 +2055,6 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, fi - 1, j) != solid(P, fi, j)) wall_mirror(&in, solid(P, fi - 1, j) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      wall_flux(P, wall_edge(P, 0, fi, 0), &o);
       for (int v = 0; v < nv; ++v) {
         FLX[((size_t)v * ny + j) * (nx + 1) + fi] = o.flux[v];
         for (int g = 0; g < 2; ++g) fx[(((size_t)g * nv + v) * ny + j) * (nx + 1) + fi] = o.pv[g][v];
@@ -2051,7 +2087,6 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
       if (solid(P, i, fj - 1) != solid(P, i, fj)) wall_mirror(&in, solid(P, i, fj - 1) ? 0 : 1, nv);
       orc_face_output o;
       if (orc_face(P, &in, dt, &o)) status |= 1;
-      wall_flux(P, wall_edge(P, 1, fj, i), &o);
       for (int v = 0; v < nv; ++v) {
         FLY[((size_t)v * (ny + 1) + fj) * nx + i] = o.flux[sw[v]];
         for (int g = 0; g < 2; ++g) fy[(((size_t)g * nv + v) * (ny + 1) + fj) * nx + i] = o.pv[g][sw[v]];
@@ -2059,6 +2094,7 @@ static int step2d(const orc_problem* P, double* cell, double* fx, double* fy, do
     }
 
 update:
+  walls_2d(P, cell, FLX, FLY, fx, fy);
   /* eq. finite: conservative update */
   for (int v = 0; v < nv; ++v)
     for (int j = 0; j < ny; ++j)
@@ -2241,7 +2277,7 @@ static int step1d(const orc_problem* P, double* cell, double* fx, double dt, dou
       for (int v = 0; v < nv; ++v) in.Ueq[m][1][v] = W1(v, fi - 1 + m);
     orc_face_output o;
     if (orc_face(P, &in, dt, &o)) status |= 1;
-    if ((fi == 0 || fi == nx) && P->bc_kind[fi == 0 ? 0 : 1] == ORC_BC_REFLECT) wall_flux(P, 1, &o);
+    if ((fi == 0 || fi == nx) && P->bc_kind[fi == 0 ? 0 : 1] == ORC_BC_REFLECT) wall_1d(o.flux, o.pv[0]);
     for (int v = 0; v < nv; ++v) {
       FL[(size_t)v * (nx + 1) + fi] = o.flux[v];
       fx[(size_t)v * (nx + 1) + fi] = o.pv[0][v];
