@@ -79,8 +79,8 @@ enum {
                                      2D no-slip edges are impermeable: their interfaces pass
                                      no mass, and the momentum and energy that the mass flux
                                      of the ghost-image evaluation would carry (F_rho times the
-                                     velocity and total enthalpy of the interface equilibrium)
-                                     are removed with it */
+                                     velocity and total enthalpy of the cell beside the wall,
+                                     its average at the start of the step) are removed with it */
   GKS_BC_INFLOW = 5,              /* fixed primitive state `state` */
   GKS_BC_DMR_BOTTOM = 6,          /* `state` for x < 1/6, slip wall beyond (Sec. 4.5) */
   GKS_BC_DMR_TOP = 7              /* `state` behind the Mach-10 shock line

@@ -1013,20 +1013,6 @@ __device__ __forceinline__ int wall_side(const PR& Q, const Face& F) {
   return s0 == s1 ? -1 : (s0 ? 0 : 1);
 }
 
-// the wall an interface F on the domain edge is: 1 a slip wall (the south
-// edge of the double Mach reflection from the cell whose centre lies at
-// x = 1/6 on), 2 a no-slip wall, 0 none
-template <class PR>
-__device__ __forceinline__ int wall_edge(const PR& Q, const Face& F) {
-  const int n = F.isx ? Q.g.ix.nx : Q.g.ix.ny, q = F.isx ? F.b : F.a;
-  if (q != 0 && q != n) return 0;
-  const int k = Q.bc[(F.isx ? 0 : 2) + (q == 0 ? 0 : 1)].kind;
-  if (k == GKS_BC_NOSLIP_ISOTHERMAL || k == GKS_BC_NOSLIP_ADIABATIC) return 2;
-  if (k == GKS_BC_REFLECT) return 1;
-  if (k == GKS_BC_DMR_BOTTOM) return Q.g.geo.x0 + (F.b + 0.5) * Q.g.geo.h < 1.0 / 6.0 ? 0 : 1;
-  return 0;
-}
-
 // the image of a side across the interface, in the interface frame: the
 // normal momentum (component 1) and the odd orders in the normal
 // coordinate (p_n, p_ns) negated
@@ -1305,30 +1291,6 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
     const double qh = Fl[3] - U0 * Fl[1] - V0 * Fl[2] + k2 * Fl[0] - U0 * (Ed[3] - U0 * Ed[1] - V0 * Ed[2] + k2 * Ed[0]);
     Fl[3] += P.prfix * qh;
   }
-  // Domain-edge walls (interface frame).  A no-slip wall is impermeable: its
-  // interface passes no mass, and the share of the momentum and energy
-  // fluxes that the mass flux of the ghost-image evaluation carries,
-  // F_rho (U0, V0, h0) with the velocity and total enthalpy of the interface
-  // equilibrium, goes with it (pressure, stress and heat flux stay).  A slip
-  // wall is the symmetry line of its image pair: normal momentum flux only,
-  // and new point values without normal momentum (the ghost cell's own
-  // reconstruction holds the wall's point values unmirrored, so an odd part
-  // left there by rounding would not cancel and can grow from step to step).
-  const int wall = wall_edge(Q, F);
-  if (wall == 1) {
-    Fl[0] = Fl[2] = Fl[3] = 0.0;
-    Pm[1] = Pp[1] = 0.0;
-  }
-  if (wall == 2 && R.D(D_RHO0, me) > 0.0) {
-    const double rho0 = R.D(D_RHO0, me), U0 = R.D(D_U0, me), V0 = R.D(D_V0, me), lam0 = R.D(D_LAM0, me);
-    const double p0 = 0.5 * rho0 / lam0;
-    const double h0 = (p0 / (P.gamma - 1.0) + 0.5 * rho0 * (U0 * U0 + V0 * V0) + p0) / rho0;
-    const double m = Fl[0];
-    Fl[1] -= m * U0;
-    Fl[2] -= m * V0;
-    Fl[3] -= m * h0;
-    Fl[0] = 0.0;
-  }
   if constexpr (kCurv) {
     // frame momentum back to (x, y); the grid's own interface layouts
     double fr[kFaceGeo];
@@ -1432,6 +1394,49 @@ __global__ void __launch_bounds__(256) k_face_1d(KA<Prob<TS, TP, TC>> a) {
 // ---------------------------------------------------------------------------
 // conservative update (kScan: only the CFL bound of the present state)
 // ---------------------------------------------------------------------------
+
+// Domain-edge walls, applied here to the wall interfaces' fluxes and point
+// values (each such interface has one gas cell, whose update alone reads
+// it).  A no-slip wall is impermeable: its interface passes no mass, and the
+// mass flux F_rho of the ghost-image evaluation takes with it the momentum
+// and energy it would carry at the velocity and total enthalpy of the cell
+// beside the wall (its average at the start of the step); pressure, viscous
+// stress and heat flux stay.  A slip wall is the symmetry line of its image
+// pair: normal momentum flux only, and new point values without normal
+// momentum (the ghost cell's own reconstruction holds the wall's point
+// values unmirrored, so an odd part left there by rounding would not cancel
+// and can grow from step to step).
+//
+// wall_kind: 1 slip, 2 no-slip, 0 neither for side `side` at column or row
+// `pos` (the south edge of the double Mach reflection is a slip wall from
+// the cell whose centre lies at x = 1/6 on)
+template <class PR>
+__device__ __forceinline__ int wall_kind(const PR& Q, int side, int pos) {
+  const int k = Q.bc[side].kind;
+  if (k == GKS_BC_NOSLIP_ISOTHERMAL || k == GKS_BC_NOSLIP_ADIABATIC) return 2;
+  if (k == GKS_BC_REFLECT) return 1;
+  if (k == GKS_BC_DMR_BOTTOM) return Q.g.geo.x0 + (pos + 0.5) * Q.g.geo.h < 1.0 / 6.0 ? 0 : 1;
+  return 0;
+}
+
+// the wall treatment of interface flux F (grid components, in place) beside
+// the cell of average W; axis: the interface's normal
+__device__ __forceinline__ void wall_flux(int kind, int axis, const double* W, double gamma, double* F) {
+  if (kind == 2) {
+    const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
+    const double p = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / rho);
+    const double h = (W[3] + p) / rho, m = F[0];
+    F[1] -= m * u;
+    F[2] -= m * v;
+    F[3] -= m * h;
+    F[0] = 0.0;
+  } else {
+    F[0] = 0.0;
+    F[2 - axis] = 0.0;
+    F[3] = 0.0;
+  }
+}
+
 template <typename TS, typename TP, typename TC, bool kScan>
 __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
   int id;
@@ -1451,10 +1456,14 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
       // periodic seams: the last interface is the first one
       const int ie = (i + 1 == nx && x.fxr == nx) ? 0 : i + 1;
       const int je = (j + 1 == ny && x.fyr == ny) ? 0 : j + 1;
-      double d[4];
+      double f[4][4];  // west, east, south, north interface fluxes
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        d[v] = g.FLX[x.flx(v, j, i)] - g.FLX[x.flx(v, j, ie)] + g.FLY[x.fly(v, j, i)] - g.FLY[x.fly(v, je, i)];
+      for (int v = 0; v < 4; ++v) {
+        f[0][v] = g.FLX[x.flx(v, j, i)];
+        f[1][v] = g.FLX[x.flx(v, j, ie)];
+        f[2][v] = g.FLY[x.fly(v, j, i)];
+        f[3][v] = g.FLY[x.fly(v, je, i)];
+      }
       // the seam gets the first interface's new point values (read by the
       // next reconstruction)
       const bool sx = i == 0 && x.fxr == nx, sy = j == 0 && x.fyr == ny;
@@ -1466,6 +1475,28 @@ __global__ void __launch_bounds__(256) k_update_2d(KA<Prob<TS, TP, TC>> a) {
       }
       const double t0 = id == 0 ? *g.t : 0.0;
       const long long n0 = id == 0 ? *g.steps : 0;
+      if (dt > 0.0 && (i == 0 || i + 1 == nx || j == 0 || j + 1 == ny)) {
+        // the walls among the cell's interfaces
+#pragma unroll
+        for (int side = 0; side < 4; ++side) {
+          const bool on = side == 0 ? i == 0 : side == 1 ? i + 1 == nx : side == 2 ? j == 0 : j + 1 == ny;
+          const int kind = on ? wall_kind(Q, side, side < 2 ? j : i) : 0;
+          if (!kind) continue;
+          wall_flux(kind, side >> 1, W, Q.P.gamma, f[side]);
+          if (kind == 1) {
+#pragma unroll
+            for (int gp = 0; gp < 2; ++gp) {
+              if (side < 2)
+                g.FX[x.fx(gp, 1, j, side == 0 ? 0 : nx)] = TS(0);
+              else
+                g.FY[x.fy(gp, 2, side == 2 ? 0 : ny, i)] = TS(0);
+            }
+          }
+        }
+      }
+      double d[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) d[v] = f[0][v] - f[1][v] + f[2][v] - f[3][v];
       if (dt > 0.0) {
         const double ia = 1.0 / (g.cv.area ? g.cv.area[(size_t)(j + 1) * (nx + 2) + (i + 1)] : g.geo.h * g.geo.k);
 #pragma unroll

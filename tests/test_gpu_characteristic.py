@@ -186,7 +186,12 @@ def test_stationary_shock_on_the_gpu(G):
     mass conserved (the two boundary mass fluxes are equal up to the small
     disturbance the kinetic flux carries upstream), the shock stays at
     x = 0.5 within a quarter cell, and nothing varies across the channel
-    beyond rounding (FP64 3e-15, FP32-mixed 0 measured).  With bit-equal ties
+    beyond rounding (FP64 3e-15; FP32-mixed 3e-8: the interfaces along the
+    channel carry the single-precision rounding of the correction terms in
+    their odd components, which the slip walls, symmetry lines, set to
+    zero, so the rows beside the walls differ from the others at that
+    level; the rows were bit-equal before the walls were made exact
+    symmetry lines).  With bit-equal ties
     only in the cross-derivative choice, the rounding of the GPU's contracted
     multiply-adds picked one sign of a spurious cross derivative near the
     shock and the variation grew to 6e-5, as in the oracle seeded with
@@ -208,7 +213,8 @@ def test_stationary_shock_on_the_gpu(G):
         var, trans = _across(c)
         print(f"precision {p}: across the channel: variation {var:.1e}, transverse momentum {trans:.1e}",
               flush=True)
-        assert var < 1e-12 and trans < 1e-12, (p, var, trans)
+        bound = 1e-12 if p == G.GKS_FP64 else 1e-6
+        assert var < bound and trans < bound, (p, var, trans)
         row, h = c[0, 0], prob.dx
         xc = (np.arange(prob.nx) + 0.5) * h
         mid = 0.5 * (r1 + r2)
