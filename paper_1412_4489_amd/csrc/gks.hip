@@ -15,8 +15,10 @@
 //                                double), eq. dis1 (g0), eq. dis2 of side 0
 //                                (g_l on u > 0) and side 1 (g_r on u < 0), in
 //                                sections passing the frame record through LDS
-//       k_update_2d              conservative update (eq. finite), nonphysical
-//                                flag, CFL bound of the new state
+//       k_update_2d              domain-edge walls (no-slip impermeable, slip a
+//                                symmetry line), conservative update (eq.
+//                                finite), nonphysical flag, CFL bound of the
+//                                new state
 //   1D: k_ghost_1d (+ time step), k_recon_1d, k_face_1d (fused interface), k_update_1d
 // The step of all groups is captured once in a hipGraph and replayed.
 //
