@@ -1129,7 +1129,7 @@ __device__ __forceinline__ void section_boundary() {
 // blocks in turn.
 // kCurv: the problems of the launch are curvilinear grids (each interface
 // in the frame of its edge; no solid step)
-template <typename TS, typename TP, typename TC, bool kCurv>
+template <typename TS, typename TP, typename TC, bool kCurv, unsigned NB>
 __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, unsigned L, unsigned char* lds) {
   int id;
   const Prob<TS, TP, TC>& Q = locate_at(a, L, KK_FACE, id);
@@ -1141,7 +1141,9 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
   const Face F = face_of(x, id);
   if (!kCurv && inside_step(Q, F)) return;
   const int ws = kCurv ? -1 : wall_side(Q, F);
-  const unsigned nb = blockDim.x, me = threadIdx.x;
+  // the block size as a constant: the record's addresses are immediate
+  // offsets, and neighbouring entries pair into one LDS access
+  const unsigned nb = NB, me = threadIdx.x;
   const Rec<TC> R{(double*)lds, (TC*)(lds + (size_t)ND_REC * 8 * nb), nb};
   double* acc = (double*)(lds + (size_t)(ND_REC * 8 + nt_rec<TC>() * sizeof(TC)) * nb);  // [12][nb]
   double hn = F.isx ? g.geo.h : g.geo.k, hs = F.isx ? g.geo.k : g.geo.h;
@@ -1337,20 +1339,41 @@ __device__ __forceinline__ void iface_2d_block(const KA<Prob<TS, TP, TC>>& a, un
   }
 }
 
-// one logical block per block
-template <typename TS, typename TP, typename TC, bool kCurv = false>
+// one logical block per block (NB threads)
+template <typename TS, typename TP, typename TC, bool kCurv, unsigned NB>
 __global__ void __launch_bounds__(256) k_iface_2d(KA<Prob<TS, TP, TC>> a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  iface_2d_block<TS, TP, TC, kCurv>(a, logical_block(a.nblk), lds);
+  iface_2d_block<TS, TP, TC, kCurv, NB>(a, logical_block(a.nblk), lds);
 }
 
 // persistent form: gridDim.x (a multiple of 8) blocks take the logical
 // blocks in turn
-template <typename TS, typename TP, typename TC, bool kCurv = false>
+template <typename TS, typename TP, typename TC, bool kCurv, unsigned NB>
 __global__ void __launch_bounds__(256) k_iface_2d_loop(KA<Prob<TS, TP, TC>> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   for (unsigned b = blockIdx.x; b < a.nblk; b += gridDim.x)
-    iface_2d_block<TS, TP, TC, kCurv>(a, logical_of(b, a.nblk), lds);
+    iface_2d_block<TS, TP, TC, kCurv, NB>(a, logical_of(b, a.nblk), lds);
+}
+
+// the interface launch of a 2D group with blocks of NB threads
+template <typename TS, typename TP, typename TC, bool kCurv, unsigned NB>
+void launch_iface_2d(const KA<Prob<TS, TP, TC>>& A, unsigned face_grid, hipStream_t st) {
+  const size_t lds = NB * iface_lds_per_thread<TC>();
+  if (face_grid)
+    k_iface_2d_loop<TS, TP, TC, kCurv, NB><<<face_grid, NB, lds, st>>>(A);
+  else
+    k_iface_2d<TS, TP, TC, kCurv, NB><<<A.nblk, NB, lds, st>>>(A);
+}
+
+// block sizes 64, 128, 256 (gks_set_launch and the tuner allow no others)
+template <typename TS, typename TP, typename TC, bool kCurv>
+void launch_iface_2d(const KA<Prob<TS, TP, TC>>& A, int bs, unsigned face_grid, hipStream_t st) {
+  if (bs == 64)
+    launch_iface_2d<TS, TP, TC, kCurv, 64>(A, face_grid, st);
+  else if (bs == 128)
+    launch_iface_2d<TS, TP, TC, kCurv, 128>(A, face_grid, st);
+  else
+    launch_iface_2d<TS, TP, TC, kCurv, 256>(A, face_grid, st);
 }
 
 // 1D interfaces 0..nx, fused
@@ -2147,15 +2170,10 @@ void launch_step(gks_handle* h, const KA<Prob<TS, TP, TC>> (&A)[KK_COUNT], const
   record_end(h, st, GKS_K_RECON);
   record_begin(h, st);
   if (dim == 2) {
-    const size_t lds = bs[KK_FACE] * iface_lds_per_thread<TC>();
-    if (curv && face_grid)
-      k_iface_2d_loop<TS, TP, TC, true><<<face_grid, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
-    else if (curv)
-      k_iface_2d<TS, TP, TC, true><<<A[KK_FACE].nblk, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
-    else if (face_grid)
-      k_iface_2d_loop<TS, TP, TC><<<face_grid, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
+    if (curv)
+      launch_iface_2d<TS, TP, TC, true>(A[KK_FACE], bs[KK_FACE], face_grid, st);
     else
-      k_iface_2d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], lds, st>>>(A[KK_FACE]);
+      launch_iface_2d<TS, TP, TC, false>(A[KK_FACE], bs[KK_FACE], face_grid, st);
   } else {
     k_face_1d<TS, TP, TC><<<A[KK_FACE].nblk, bs[KK_FACE], 0, st>>>(A[KK_FACE]);
   }
@@ -2571,8 +2589,13 @@ int persistent_grid_of(gks_handle* h, int bs, unsigned* grid) {
   int per_cu = 0, cus = 0, dev = 0;
   HIP_OR(h, hipGetDevice(&dev));
   HIP_OR(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIP_OR(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iface_2d_loop<TS, TP, TC>, bs,
-                                                         (size_t)bs * iface_lds_per_thread<TC>()));
+  const size_t lds = (size_t)bs * iface_lds_per_thread<TC>();
+  if (bs == 64)
+    HIP_OR(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iface_2d_loop<TS, TP, TC, false, 64>, bs, lds));
+  else if (bs == 128)
+    HIP_OR(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iface_2d_loop<TS, TP, TC, false, 128>, bs, lds));
+  else
+    HIP_OR(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iface_2d_loop<TS, TP, TC, false, 256>, bs, lds));
   const unsigned n = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(cus > 0 ? cus : 8);
   *grid = n < 8 ? 8u : n & ~7u;
   return GKS_OK;
@@ -2833,7 +2856,11 @@ int gks_tune(gks_handle* h, int32_t steps) {
     return GKS_OK;
   };
   // time every candidate block size for all kernel classes at once and
-  // keep the fastest per class
+  // keep the fastest per class.  A later candidate (and below, the
+  // persistent form and the reconstruction tiles) replaces the one kept only
+  // if it is faster by more than kTuneMargin: shapes within timing noise of
+  // each other would otherwise be picked at random from run to run
+  constexpr double kTuneMargin = 0.98;
   static const int cand[3] = {64, 128, 256};
   static const int cls[KK_COUNT] = {GKS_K_GHOST, GKS_K_RECON, GKS_K_INTERFACE, GKS_K_UPDATE, GKS_K_GHOST};
   double best_t[GKS_K_COUNT];
@@ -2873,7 +2900,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
     }
     if (rc != GKS_OK || (rc = time_steps()) != GKS_OK) break;
     for (int k = 0; k < GKS_K_COUNT; ++k)
-      if (k != GKS_K_DT && h->ktime[k] < best_t[k]) {
+      if (k != GKS_K_DT && h->ktime[k] < kTuneMargin * best_t[k]) {
         best_t[k] = h->ktime[k];
         best_bs[k] = cand[c];
       }
@@ -2892,7 +2919,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
     for (Group& G : h->groups)
       if (G.dim == 2 && (rc = persistent_face_grid(h, G, &G.face_grid)) != GKS_OK) break;
     if (rc == GKS_OK) rc = time_steps();
-    if (rc == GKS_OK && !(h->ktime[GKS_K_INTERFACE] < best_t[GKS_K_INTERFACE]))
+    if (rc == GKS_OK && !(h->ktime[GKS_K_INTERFACE] < kTuneMargin * best_t[GKS_K_INTERFACE]))
       for (Group& G : h->groups) G.face_grid = 0;
     // and the tiled reconstruction (averages staged in LDS) with 1, 2 or 4
     // rows per tile at that block size
@@ -2902,7 +2929,7 @@ int gks_tune(gks_handle* h, int32_t steps) {
         G.recon_rows = G.dim == 2 ? rows : 0;
         if ((rc = build_tables(h, G)) != GKS_OK) break;
       }
-      if (rc == GKS_OK && (rc = time_steps()) == GKS_OK && h->ktime[GKS_K_RECON] < best_t[GKS_K_RECON]) {
+      if (rc == GKS_OK && (rc = time_steps()) == GKS_OK && h->ktime[GKS_K_RECON] < kTuneMargin * best_t[GKS_K_RECON]) {
         best_t[GKS_K_RECON] = h->ktime[GKS_K_RECON];
         best_rows = rows;
       }

@@ -188,10 +188,29 @@ def write_kernel_summaries(trace_csv, out):
         fh.write(md)
 
 
+def counted_shape(counter_csv):
+    """(kernel, type, grid threads) of the interface dispatches a counter
+    pass counted (each pass is its own process, which tunes its own launch
+    shapes)"""
+    rows = _batch_iface_rows(_counter_rows(counter_csv))
+    shapes = {(*_short(r["Kernel_Name"]), int(r["Grid_Size"])) for r in rows}
+    if len(shapes) != 1:
+        raise ValueError(f"{counter_csv}: the counted interface dispatches have several shapes {shapes}")
+    return shapes.pop()
+
+
 def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
+    shapes = {path: counted_shape(path) for path in (fetch_csv, write_csv, sq_csv) if path}
+    if len(set(shapes.values())) != 1:
+        raise ValueError(f"the counter passes counted different launch shapes: {shapes}")
+    shape = next(iter(shapes.values()))
     tr = traffic(fetch_csv, write_csv)
     sq = sq_summary(sq_csv) if sq_csv else {}
-    dur = batch_iface_duration(trace_csv) if trace_csv else None
+    # the kernel's duration: the trace's launches of the counted shape
+    dur = None
+    if trace_csv:
+        v = kernel_table(trace_csv).get(shape)
+        dur = sum(v) / len(v) if v else None
     busy = valu_busy(sq["valu_quad_cycles"], dur) if sq and dur else None
     rec = {"source_hash": source_hash(),
            "workload": "96-grid batch, GKS_FP32_MIXED, tuned launch shapes",
@@ -202,6 +221,7 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
            "fetch_kib_per_dispatch": tr["fetch"]["kib_per_dispatch"],
            "write_kib_per_dispatch": tr["write"]["kib_per_dispatch"],
            "waves": sq.get("waves"), "valu_instructions_per_wave": sq.get("valu_per_wave"),
+           "launch": {"kernel": shape[0], "type": shape[1], "grid_threads": shape[2]},
            "duration_us": dur, "valu_busy": None if busy is None else round(busy, 4)}
     with open(os.path.join(out, "traffic_iface_batch96_fp32mixed.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -215,8 +235,9 @@ def write_counter_summaries(fetch_csv, write_csv, sq_csv, out, trace_csv=None):
           "Calibration: `bench.py --pmc-probe` first copies 256 MiB three times (`__amd_rocclr_copyBuffer`).",
           f"FETCH_SIZE reads {tr['fetch']['copy_kib']:.0f} KiB per copy (factor {tr['fetch']['factor']:.4f}), "
           f"WRITE_SIZE {tr['write']['copy_kib']:.0f} KiB (factor {tr['write']['factor']:.4f}).", "",
-          "VALUBusy = SQ_ACTIVE_INST_VALU (quad-cycles, all CUs) / 256 CUs / kernel cycles (the kernel's mean "
-          "duration in the kernel trace x 2.4 GHz).", "",
+          f"Counted launch (the same in every pass): {shape[0]}<{shape[1]}> over {shape[2]} threads.", "",
+          "VALUBusy = SQ_ACTIVE_INST_VALU (quad-cycles, all CUs) / 256 CUs / kernel cycles (the mean duration "
+          "of the same launch shape in the kernel trace x 2.4 GHz).", "",
           "| FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) | HBM bytes/dispatch (scaled) | waves "
           "| VALU instr./wave | duration (us) | VALUBusy |", "|---:|---:|---:|---:|---:|---:|---:|",
           f"| {tr['fetch']['kib_per_dispatch']:.0f} | {tr['write']['kib_per_dispatch']:.0f} "
