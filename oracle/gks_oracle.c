@@ -1798,8 +1798,9 @@ static void from_face_frame(const double* fr, const double* F, double* o) {
 }
 
 static long g_last_fallbacks = 0;
-/* Readings of the domain-edge walls (the paper gives its walls as slip or
- * no-slip and prints no wall treatment beyond the ghost images); both act on
+/* Readings of the domain-edge walls (Sec. 4.5-4.8 give their walls as slip
+ * walls, a symmetry line or no-slip walls, isothermal or adiabatic, and
+ * print no wall treatment beyond the ghost images); both act on
  * the interface fluxes and point values of the step, in the grid's
  * components, before the update.
  *
